@@ -1,0 +1,211 @@
+"""Test oracle: plain CPU evaluation of the chemical source term.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The HIP library
+never loads it and shares no code with it.
+
+What it computes (Barwey & Raman, Sec. 2) in the classical form, cell by
+cell: concentrations from the ideal-gas state, Arrhenius forward rate
+constants (Eq. 5), equilibrium constants from NASA-7 enthalpy and entropy
+changes (Eq. 8), reverse constants k_r = k_f / K_c (Eq. 7), rates of progress
+as products of concentrations (Eq. 3), and net production rates (Eq. 2).
+``source(..., precision="ld")`` evaluates in x86 extended precision.
+
+Pins (``tests/test_oracle_pins.py``): two hand-worked reactions in closed
+form, detailed balance at a constructed equilibrium state, atom and mass
+conservation, degree-0 homogeneity in Y, thermodynamic identities
+(dH/dT = cp, dS/dT = cp/T, van 't Hoff), the Arrhenius special case, brute
+force at 50 digits on tiny mechanisms, and for the Jacobian central finite
+differences and conservation of elements.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ("oracle.c", "oracle.h", "oracle_impl.h")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (-O2, OpenMP, no fast-math)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall",
+           "-o", tmp, os.path.join(_HERE, "oracle.c"), "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Mech(C.Structure):
+    _fields_ = [
+        ("ns", C.c_int), ("nr", C.c_int),
+        ("W", C.c_void_p), ("nu_f", C.c_void_p), ("nu_r", C.c_void_p),
+        ("ln_A", C.c_void_p), ("beta", C.c_void_p), ("Ea", C.c_void_p),
+        ("nasa_low", C.c_void_p), ("nasa_high", C.c_void_p), ("T_mid", C.c_void_p),
+        ("reversible", C.c_void_p),
+    ]
+
+
+_LD = np.longdouble
+assert np.finfo(_LD).nmant >= 63, "the oracle's extended precision needs x86 long double"
+
+
+def _lib_handle():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = C.CDLL(_LIB_PATH)
+        for sfx in ("f64", "ld"):
+            getattr(lib, f"ora_thermo_{sfx}").argtypes = [C.c_void_p, C.c_double, C.c_void_p,
+                                                          C.c_void_p, C.c_void_p]
+            getattr(lib, f"ora_rates_{sfx}").argtypes = [C.c_void_p, C.c_double, C.c_double,
+                                                         C.c_void_p] + [C.c_void_p] * 5
+            getattr(lib, f"ora_source_{sfx}").argtypes = [
+                C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int]
+            getattr(lib, f"ora_temp_source_{sfx}").argtypes = [
+                C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                C.c_void_p, C.c_int]
+            getattr(lib, f"ora_jacobian_{sfx}").argtypes = [
+                C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                C.c_void_p, C.c_int64, C.c_int]
+        _lib = lib
+    return _lib
+
+
+class OracleMechanism:
+    """Holds contiguous copies of a mechanism's arrays and the C view of them.
+
+    ``mech`` is any object with the attributes of ``synth.Mechanism``."""
+
+    def __init__(self, mech):
+        self.ns = int(mech.W.shape[0])
+        self.nr = int(mech.nu_f.shape[0])
+        self._keep = {
+            "W": np.ascontiguousarray(mech.W, dtype=np.float64),
+            "nu_f": np.ascontiguousarray(mech.nu_f, dtype=np.int8),
+            "nu_r": np.ascontiguousarray(mech.nu_r, dtype=np.int8),
+            "ln_A": np.ascontiguousarray(mech.ln_A, dtype=np.float64),
+            "beta": np.ascontiguousarray(mech.beta, dtype=np.float64),
+            "Ea": np.ascontiguousarray(mech.Ea, dtype=np.float64),
+            "nasa_low": np.ascontiguousarray(mech.nasa_low, dtype=np.float64),
+            "nasa_high": np.ascontiguousarray(mech.nasa_high, dtype=np.float64),
+            "T_mid": np.ascontiguousarray(mech.T_mid, dtype=np.float64),
+            "reversible": np.ascontiguousarray(mech.reversible, dtype=np.uint8),
+        }
+        assert self._keep["nu_f"].shape == (self.nr, self.ns)
+        k = self._keep
+        self._c = _Mech(self.ns, self.nr, *(k[n].ctypes.data for n in (
+            "W", "nu_f", "nu_r", "ln_A", "beta", "Ea", "nasa_low", "nasa_high", "T_mid",
+            "reversible")))
+
+    @property
+    def ptr(self):
+        return C.addressof(self._c)
+
+
+def _as_mech(m):
+    return m if isinstance(m, OracleMechanism) else OracleMechanism(m)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dtype(precision):
+    if precision == "f64":
+        return np.float64
+    if precision == "ld":
+        return _LD
+    raise ValueError(precision)
+
+
+def thermo(mech, T: float, precision: str = "f64"):
+    """(h/RT, s/R, cp/R) per species at temperature T."""
+    m = _as_mech(mech)
+    dt = _dtype(precision)
+    h, s, cp = (np.zeros(m.ns, dt) for _ in range(3))
+    getattr(_lib_handle(), f"ora_thermo_{precision}")(m.ptr, float(T), h.ctypes.data,
+                                                      s.ctypes.data, cp.ctypes.data)
+    return h, s, cp
+
+
+def rates(mech, T: float, P: float, Y, precision: str = "f64"):
+    """One cell: dict of C [NS] and kf, Kc, qf, qr [NR] (SI-kmol units)."""
+    m = _as_mech(mech)
+    dt = _dtype(precision)
+    Yc = _f64(Y)
+    assert Yc.shape == (m.ns,)
+    out = {"C": np.zeros(m.ns, dt)}
+    for n in ("kf", "Kc", "qf", "qr"):
+        out[n] = np.zeros(m.nr, dt)
+    rc = getattr(_lib_handle(), f"ora_rates_{precision}")(
+        m.ptr, float(T), float(P), Yc.ctypes.data, out["C"].ctypes.data,
+        out["kf"].ctypes.data, out["Kc"].ctypes.data, out["qf"].ctypes.data,
+        out["qr"].ctypes.data)
+    if rc:
+        raise RuntimeError("oracle rates failed")
+    return out
+
+
+def source(mech, T, P, Y, precision: str = "f64", scales: bool = False, n_threads: int = 0):
+    """Net production rates omega [NS, n] (kmol m^-3 s^-1) for states
+    T [n] (K), P [n] (Pa), Y [NS, n].  With ``scales`` also returns the gross
+    scale S and net scale N (same shape)."""
+    m = _as_mech(mech)
+    dt = _dtype(precision)
+    T, P = _f64(T), _f64(P)
+    Y = _f64(Y)
+    n = T.shape[0]
+    assert P.shape == (n,) and Y.shape == (m.ns, n)
+    om = np.zeros((m.ns, n), dt)
+    S = np.zeros((m.ns, n), dt) if scales else None
+    N = np.zeros((m.ns, n), dt) if scales else None
+    rc = getattr(_lib_handle(), f"ora_source_{precision}")(
+        m.ptr, n, T.ctypes.data, P.ctypes.data, Y.ctypes.data, n, om.ctypes.data,
+        S.ctypes.data if scales else None, N.ctypes.data if scales else None, n,
+        int(n_threads))
+    if rc:
+        raise RuntimeError("oracle source failed")
+    return (om, S, N) if scales else om
+
+
+def temp_source(mech, T, P, Y, precision: str = "f64", n_threads: int = 0):
+    """Constant-pressure temperature source omega_T [n] in K/s."""
+    m = _as_mech(mech)
+    dt = _dtype(precision)
+    T, P, Y = _f64(T), _f64(P), _f64(Y)
+    n = T.shape[0]
+    out = np.zeros(n, dt)
+    rc = getattr(_lib_handle(), f"ora_temp_source_{precision}")(
+        m.ptr, n, T.ctypes.data, P.ctypes.data, Y.ctypes.data, n, out.ctypes.data,
+        int(n_threads))
+    if rc:
+        raise RuntimeError("oracle temp_source failed")
+    return out
+
+
+def jacobian(mech, T, P, Y, precision: str = "f64", n_threads: int = 0):
+    """Analytic Jacobian [n, NS+1, NS+1] of (omega, omega_T) w.r.t. (Y, T)."""
+    m = _as_mech(mech)
+    dt = _dtype(precision)
+    T, P, Y = _f64(T), _f64(P), _f64(Y)
+    n = T.shape[0]
+    nv = m.ns + 1
+    J = np.zeros((n, nv, nv), dt)
+    rc = getattr(_lib_handle(), f"ora_jacobian_{precision}")(
+        m.ptr, n, T.ctypes.data, P.ctypes.data, Y.ctypes.data, n, J.ctypes.data, nv * nv,
+        int(n_threads))
+    if rc:
+        raise RuntimeError("oracle jacobian failed")
+    return J

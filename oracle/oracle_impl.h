@@ -1,0 +1,336 @@
+/*
+ * Test oracle body, instantiated twice by oracle.c: once with REAL = double
+ * (suffix _f64) and once with REAL = long double (suffix _ld).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load or call this code.
+ *
+ * It computes the *plain definition* of the chemical source term
+ * (Barwey & Raman, Sec. 2): the classical law of mass action with products
+ * of concentrations, Arrhenius rate constants, and equilibrium constants from
+ * enthalpy and entropy changes.  It deliberately does NOT use the paper's
+ * log-space matrix ("ANN") re-association.
+ *
+ * Expects the including file to define REAL, SFX(name), EXP, LOG, POW, FABS.
+ */
+
+/* NASA-7 enthalpy, entropy and heat capacity of one species at T (McBride,
+ * Gordon & Reno, NASA TM-4513; the paper's "NASA polynomials", Sec. 2.2,
+ * Eq. 10).  The high-range set applies for T >= T_mid. */
+static void SFX(thermo1)(const ora_mech *m, int k, REAL T, REAL *h_RT, REAL *s_R,
+                         REAL *cp_R, REAL *dcp_R)
+{
+    const double *a = (T >= (REAL)m->T_mid[k]) ? &m->nasa_high[7 * k] : &m->nasa_low[7 * k];
+    REAL a1 = a[0], a2 = a[1], a3 = a[2], a4 = a[3], a5 = a[4], a6 = a[5], a7 = a[6];
+    REAL T2 = T * T, T3 = T2 * T, T4 = T3 * T;
+    if (h_RT) *h_RT = a1 + a2 * T / 2 + a3 * T2 / 3 + a4 * T3 / 4 + a5 * T4 / 5 + a6 / T;
+    if (s_R)  *s_R  = a1 * LOG(T) + a2 * T + a3 * T2 / 2 + a4 * T3 / 3 + a5 * T4 / 4 + a7;
+    if (cp_R) *cp_R = a1 + a2 * T + a3 * T2 + a4 * T3 + a5 * T4;
+    if (dcp_R) *dcp_R = a2 + 2 * a3 * T + 3 * a4 * T2 + 4 * a5 * T3;
+}
+
+/* Arrhenius forward rate constant in SI-kmol units (Eq. 5).  The mechanism
+ * carries A in cgs units, (cm^3/mol)^(n-1)/s, and Ea in cal/mol. */
+static REAL SFX(kf1)(const ora_mech *m, int j, REAL T)
+{
+    int order = 0;
+    for (int k = 0; k < m->ns; ++k) order += m->nu_f[j * m->ns + k];
+    REAL A_si = EXP((REAL)m->ln_A[j]) * POW((REAL)1e-3L, (REAL)(order - 1));
+    REAL E_R = (REAL)m->Ea[j] * (REAL)ORA_CAL / (REAL)ORA_RU_MOL;
+    return A_si * POW(T, (REAL)m->beta[j]) * EXP(-E_R / T);
+}
+
+/* Concentrations from the ideal-gas state: C_k = P/(Ru T) * (Y_k/W_k)/sum_l(Y_l/W_l),
+ * with negative mass fractions clamped to zero. */
+static REAL SFX(concentrations)(const ora_mech *m, REAL T, REAL P, const REAL *Y, REAL *C)
+{
+    REAL sum = 0;
+    for (int k = 0; k < m->ns; ++k) {
+        REAL y = Y[k] > 0 ? Y[k] : 0;
+        C[k] = y / (REAL)m->W[k];
+        sum += C[k];
+    }
+    REAL rho_hat = P / ((REAL)ORA_RU * T * sum);
+    for (int k = 0; k < m->ns; ++k) C[k] *= rho_hat;
+    return sum;
+}
+
+/* integer power by repeated multiplication */
+static REAL SFX(ipow)(REAL x, int n)
+{
+    REAL r = 1;
+    for (int i = 0; i < n; ++i) r *= x;
+    return r;
+}
+
+/* Per-reaction quantities for one cell at given concentrations:
+ * kf (Eq. 5), Kc (Eq. 8), kr = kf/Kc (Eq. 7, zero for irreversible
+ * reactions), qf and qr (Eq. 3).  h_RT and s_R are the species values at T. */
+static void SFX(reaction1)(const ora_mech *m, int j, REAL T, const REAL *C,
+                           const REAL *h_RT, const REAL *s_R,
+                           REAL *kf, REAL *Kc, REAL *qf, REAL *qr)
+{
+    const int ns = m->ns;
+    const int8_t *nf = &m->nu_f[j * ns], *nr = &m->nu_r[j * ns];
+    REAL k_f = SFX(kf1)(m, j, T);
+    REAL dn = 0, dS = 0, dH = 0;
+    for (int k = 0; k < ns; ++k) {
+        int nu = nr[k] - nf[k];
+        if (!nu) continue;
+        dn += nu;
+        dS += nu * s_R[k];
+        dH += nu * h_RT[k];
+    }
+    REAL K_c = POW((REAL)ORA_PREF / ((REAL)ORA_RU * T), dn) * EXP(dS - dH);
+    REAL k_r = (m->reversible == 0 || m->reversible[j]) ? k_f / K_c : 0;
+    REAL pf = 1, pr = 1;
+    for (int k = 0; k < ns; ++k) {
+        if (nf[k]) pf *= SFX(ipow)(C[k], nf[k]);
+        if (nr[k]) pr *= SFX(ipow)(C[k], nr[k]);
+    }
+    *kf = k_f;
+    *Kc = K_c;
+    *qf = k_f * pf;
+    *qr = k_r * pr;
+}
+
+int SFX(ora_thermo)(const ora_mech *m, double T, REAL *h_RT, REAL *s_R, REAL *cp_R)
+{
+    for (int k = 0; k < m->ns; ++k)
+        SFX(thermo1)(m, k, (REAL)T, h_RT ? &h_RT[k] : 0, s_R ? &s_R[k] : 0,
+                     cp_R ? &cp_R[k] : 0, 0);
+    return 0;
+}
+
+/* One cell: concentrations and per-reaction kf, Kc, qf, qr (arrays of NR). */
+int SFX(ora_rates)(const ora_mech *m, double T, double P, const double *Y,
+                   REAL *C, REAL *kf, REAL *Kc, REAL *qf, REAL *qr)
+{
+    const int ns = m->ns;
+    if (ns <= 0) return -1;
+    REAL *Yr = (REAL *)malloc(sizeof(REAL) * 3 * ns);
+    if (!Yr) return -1;
+    REAL *h = Yr + ns, *s = h + ns;
+    for (int k = 0; k < ns; ++k) Yr[k] = Y[k];
+    SFX(concentrations)(m, T, P, Yr, C);
+    for (int k = 0; k < ns; ++k) SFX(thermo1)(m, k, T, &h[k], &s[k], 0, 0);
+    for (int j = 0; j < m->nr; ++j)
+        SFX(reaction1)(m, j, T, C, h, s, &kf[j], &Kc[j], &qf[j], &qr[j]);
+    free(Yr);
+    return 0;
+}
+
+/* Net molar production rates (Eq. 2) for n cells.
+ * Y is species-major with leading dimension ldY (Y[k*ldY + i]); omega, S and
+ * N likewise with ldO.  S_ik = sum_j |nu_kj| (qf + qr) is the gross rate
+ * scale and N_ik = sum_j |nu_kj| |qf - qr| the net rate scale (used to grade
+ * rounding error); either may be NULL. */
+int SFX(ora_source)(const ora_mech *m, int64_t n, const double *T, const double *P,
+                    const double *Y, int64_t ldY, REAL *omega, REAL *S, REAL *N,
+                    int64_t ldO, int n_threads)
+{
+    const int ns = m->ns, nr = m->nr;
+    int err = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+#endif
+    {
+        REAL *buf = (REAL *)malloc(sizeof(REAL) * 7 * ns);
+        if (!buf) {
+            err = -1;
+        } else {
+            REAL *Yc = buf, *C = Yc + ns, *h = C + ns, *s = h + ns, *om = s + ns, *sg = om + ns,
+                 *sn = sg + ns;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+            for (int64_t i = 0; i < n; ++i) {
+                REAL Ti = T[i], Pi = P[i];
+                for (int k = 0; k < ns; ++k) {
+                    Yc[k] = Y[k * ldY + i];
+                    om[k] = sg[k] = sn[k] = 0;
+                }
+                SFX(concentrations)(m, Ti, Pi, Yc, C);
+                for (int k = 0; k < ns; ++k) SFX(thermo1)(m, k, Ti, &h[k], &s[k], 0, 0);
+                for (int j = 0; j < nr; ++j) {
+                    REAL kf, Kc, qf, qr;
+                    SFX(reaction1)(m, j, Ti, C, h, s, &kf, &Kc, &qf, &qr);
+                    REAL qn = qf - qr;
+                    const int8_t *nf = &m->nu_f[j * ns], *nrr = &m->nu_r[j * ns];
+                    for (int k = 0; k < ns; ++k) {
+                        int nu = nrr[k] - nf[k];
+                        if (!nu) continue;
+                        om[k] += nu * qn;
+                        sg[k] += FABS((REAL)nu) * (qf + qr);
+                        sn[k] += FABS((REAL)nu) * FABS(qn);
+                    }
+                }
+                for (int k = 0; k < ns; ++k) {
+                    omega[k * ldO + i] = om[k];
+                    if (S) S[k * ldO + i] = sg[k];
+                    if (N) N[k * ldO + i] = sn[k];
+                }
+            }
+            free(buf);
+        }
+    }
+    return err;
+}
+
+/* Constant-pressure temperature source  omega_T = -sum_k h_k omega_k / sum_k C_k cp_k
+ * in K/s, with h_k = Ru T (h/RT)_k the molar enthalpy and cp_k = Ru (cp/R)_k.
+ * (Not part of the paper's method; it is the last row of the state Jacobian
+ * an implicit integrator of (Y, T) needs.) */
+int SFX(ora_temp_source)(const ora_mech *m, int64_t n, const double *T, const double *P,
+                         const double *Y, int64_t ldY, REAL *omega_T, int n_threads)
+{
+    const int ns = m->ns;
+    REAL *om = (REAL *)malloc(sizeof(REAL) * ns * n);
+    if (!om) return -1;
+    int rc = SFX(ora_source)(m, n, T, P, Y, ldY, om, 0, 0, n, n_threads);
+    if (rc) { free(om); return rc; }
+    REAL *C = (REAL *)malloc(sizeof(REAL) * 2 * ns);
+    if (!C) { free(om); return -1; }
+    REAL *Yc = C + ns;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < ns; ++k) Yc[k] = Y[k * ldY + i];
+        SFX(concentrations)(m, T[i], P[i], Yc, C);
+        REAL num = 0, den = 0;
+        for (int k = 0; k < ns; ++k) {
+            REAL h, cp;
+            SFX(thermo1)(m, k, T[i], &h, 0, &cp, 0);
+            num += (REAL)ORA_RU * T[i] * h * om[k * n + i];
+            den += C[k] * (REAL)ORA_RU * cp;
+        }
+        omega_T[i] = -num / den;
+    }
+    free(C);
+    free(om);
+    return 0;
+}
+
+/* Analytic Jacobian of (omega_1..omega_NS, omega_T) with respect to
+ * x = (Y_1..Y_NS, T) at fixed P, in the classical (product) form.
+ * J is [n][NS+1][NS+1] row-major per cell, cells outermost, cell stride ldJ.
+ * dC_l/dY_m = (rho_hat/W_m) delta_lm - C_l/(sigma W_m) with sigma = sum Y/W,
+ * dC_l/dT = -C_l/T, d ln kf/dT = (beta + E/RT)/T,
+ * d ln Kc/dT = (dH/RT - dn)/T, and dq/dC_l by differentiating each power
+ * C_l^nu directly (defined at C_l = 0).  For Y_m < 0 the clamp makes
+ * dC/dY_m zero; at Y_m = 0 the right derivative is used. */
+int SFX(ora_jacobian)(const ora_mech *m, int64_t n, const double *T, const double *P,
+                      const double *Y, int64_t ldY, REAL *J, int64_t ldJ, int n_threads)
+{
+    const int ns = m->ns, nr = m->nr, nv = ns + 1;
+    int err = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+#endif
+    {
+        REAL *buf = (REAL *)malloc(sizeof(REAL) * (8 * ns + 2 * ns * nv + nv * nv));
+        if (!buf) {
+            err = -1;
+        } else {
+            REAL *Yc = buf, *C = Yc + ns, *h = C + ns, *s = h + ns, *cp = s + ns, *dcp = cp + ns,
+                 *om = dcp + ns, *dqdC = om + ns;     /* dqdC: [ns] per reaction */
+            REAL *dCdx = dqdC + ns;                   /* [ns][nv] */
+            REAL *Jc = dCdx + ns * nv;                /* [nv][nv] */
+            REAL *rowtmp = Jc + nv * nv;              /* [ns][nv] scratch (unused rows) */
+            (void)rowtmp;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+            for (int64_t i = 0; i < n; ++i) {
+                REAL Ti = T[i], Pi = P[i];
+                for (int k = 0; k < ns; ++k) { Yc[k] = Y[k * ldY + i]; om[k] = 0; }
+                REAL sigma = SFX(concentrations)(m, Ti, Pi, Yc, C);
+                REAL rho_hat = Pi / ((REAL)ORA_RU * Ti * sigma);
+                for (int k = 0; k < ns; ++k)
+                    SFX(thermo1)(m, k, Ti, &h[k], &s[k], &cp[k], &dcp[k]);
+                /* dC_l/dx_c */
+                for (int l = 0; l < ns; ++l) {
+                    for (int c = 0; c < ns; ++c) {
+                        REAL clamp_c = Yc[c] >= 0 ? 1 : 0;
+                        REAL v = -C[l] / (sigma * (REAL)m->W[c]);
+                        if (l == c) v += rho_hat / (REAL)m->W[c];
+                        dCdx[l * nv + c] = v * clamp_c;
+                    }
+                    dCdx[l * nv + ns] = -C[l] / Ti;
+                }
+                for (int a = 0; a < nv * nv; ++a) Jc[a] = 0;
+                for (int j = 0; j < nr; ++j) {
+                    REAL kf, Kc, qf, qr;
+                    SFX(reaction1)(m, j, Ti, C, h, s, &kf, &Kc, &qf, &qr);
+                    const int8_t *nf = &m->nu_f[j * ns], *nrr = &m->nu_r[j * ns];
+                    int rev = (m->reversible == 0 || m->reversible[j]);
+                    REAL kr = rev ? kf / Kc : 0;
+                    REAL dn = 0, dH = 0;
+                    for (int k = 0; k < ns; ++k) {
+                        int nu = nrr[k] - nf[k];
+                        dn += nu;
+                        dH += nu * h[k];
+                    }
+                    REAL E_R = (REAL)m->Ea[j] * (REAL)ORA_CAL / (REAL)ORA_RU_MOL;
+                    REAL dlnkf = ((REAL)m->beta[j] + E_R / Ti) / Ti;
+                    REAL dlnKc = (dH - dn) / Ti;
+                    /* explicit temperature dependence at fixed C */
+                    REAL dqdT = qf * dlnkf - (rev ? qr * (dlnkf - dlnKc) : 0);
+                    /* dq/dC_l, product rule on each power */
+                    for (int l = 0; l < ns; ++l) {
+                        REAL d = 0;
+                        if (nf[l]) {
+                            REAL p = kf * (REAL)nf[l] * SFX(ipow)(C[l], nf[l] - 1);
+                            for (int mm = 0; mm < ns; ++mm)
+                                if (mm != l && nf[mm]) p *= SFX(ipow)(C[mm], nf[mm]);
+                            d += p;
+                        }
+                        if (nrr[l] && rev) {
+                            REAL p = kr * (REAL)nrr[l] * SFX(ipow)(C[l], nrr[l] - 1);
+                            for (int mm = 0; mm < ns; ++mm)
+                                if (mm != l && nrr[mm]) p *= SFX(ipow)(C[mm], nrr[mm]);
+                            d -= p;
+                        }
+                        dqdC[l] = d;
+                    }
+                    REAL qn = qf - qr;
+                    for (int k = 0; k < ns; ++k) {
+                        int nu = nrr[k] - nf[k];
+                        if (!nu) continue;
+                        om[k] += nu * qn;
+                        for (int c = 0; c < nv; ++c) {
+                            REAL g = (c == ns) ? dqdT : 0;
+                            for (int l = 0; l < ns; ++l)
+                                if (dqdC[l] != 0) g += dqdC[l] * dCdx[l * nv + c];
+                            Jc[k * nv + c] += nu * g;
+                        }
+                    }
+                }
+                /* last row: omega_T = -num/den */
+                REAL num = 0, den = 0;
+                for (int k = 0; k < ns; ++k) {
+                    num += (REAL)ORA_RU * Ti * h[k] * om[k];
+                    den += C[k] * (REAL)ORA_RU * cp[k];
+                }
+                for (int c = 0; c < nv; ++c) {
+                    REAL dnum = 0, dden = 0;
+                    for (int k = 0; k < ns; ++k) {
+                        dnum += (REAL)ORA_RU * Ti * h[k] * Jc[k * nv + c];
+                        dden += (REAL)ORA_RU * cp[k] * dCdx[k * nv + c];
+                    }
+                    if (c == ns) {
+                        for (int k = 0; k < ns; ++k) {
+                            dnum += (REAL)ORA_RU * cp[k] * om[k];   /* d h_k/dT = cp_k */
+                            dden += C[k] * (REAL)ORA_RU * dcp[k];
+                        }
+                    }
+                    Jc[ns * nv + c] = -(dnum * den - num * dden) / (den * den);
+                }
+                REAL *Jo = &J[i * ldJ];
+                for (int a = 0; a < nv * nv; ++a) Jo[a] = Jc[a];
+            }
+            free(buf);
+        }
+    }
+    return err;
+}
