@@ -1,0 +1,216 @@
+"""Benchmark: batched chemical source-term throughput on one MI355X.
+
+A step is one evaluation of the whole source term (concentrations, Gibbs and
+Arrhenius layers, rates of progress, production rates; Barwey & Raman,
+Sec. 2) over one batch of synthetic cells already resident in HBM.  The
+default workload is the 53-species / 325-reaction synthetic mechanism over
+2^20 cells with FP32 states (the throughput target size), FP32 path.
+
+Prints one JSON line.  Extra keys: the FP64 path on the same workload,
+per-step latency percentiles, the FP32-vs-FP64 difference, the 65,536-cell
+precision configuration, the roofline of the kernel and the CPU oracle
+baseline.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2008_08483_amd import roofline, synth  # noqa: E402
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_source_f32_53x325_1M.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("source_kernels.hip", "ak_device.h"):
+        with open(os.path.join(ROOT, "paper_2008_08483_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None
+    if absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_path(torch, annkin, mech, T, P, Y, steps, warmup):
+    """Whole-step wall time (barrier + sync around K steps) and per-launch
+    kernel durations from HIP events on the launch stream."""
+    out = torch.empty_like(Y)
+    for _ in range(warmup):
+        annkin.eval_source(mech, T, P, Y, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        annkin.eval_source(mech, T, P, Y, out=out)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    return wall, ms, out
+
+
+def cpu_baseline(src, T, P, Y, target_s=12.0):
+    """The oracle (plain C, double, OpenMP over cells) on the host cores, on
+    a bounded sample of the same workload."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        cores = min(cores, int(env))
+    T64, P64, Y64 = (np.asarray(a, np.float64) for a in (T, P, Y))
+    n0 = min(256 * cores, T64.shape[0])
+    t0 = time.perf_counter()
+    oracle.source(src, T64[:n0], P64[:n0], Y64[:, :n0], n_threads=cores)
+    dt0 = time.perf_counter() - t0
+    n = int(min(T64.shape[0], max(n0, n0 * target_s / max(dt0, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.source(src, T64[:n], P64[:n], Y64[:, :n], n_threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n} cells of the workload, double precision, "
+                      f"{cores} OpenMP threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c1_full", choices=list(synth.WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU: the source term shards "
+                          "over cells with no exchange, so N GPUs would each run this "
+                          "same single-GPU workload; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2008_08483_amd import annkin
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
+        return
+
+    wl = synth.WORKLOADS[args.workload]
+    src, T, P, Y = synth.workload(args.workload, dtype=np.float32)
+    ns, nr, n = src.n_species, src.n_reactions, T.shape[0]
+    mech = annkin.Mechanism(src)
+    T32, P32, Y32 = (torch.tensor(a, device="cuda") for a in (T, P, Y))
+
+    wall, ms, om32 = time_path(torch, annkin, mech, T32, P32, Y32, args.steps, args.warmup)
+    k_avg_s = float(ms.mean()) * 1e-3
+    value = n * args.steps / wall
+
+    slots = roofline.method_slots(src.nu_f, src.nu_r)
+    achieved = slots * n / k_avg_s
+    traffic = measured_traffic()
+    result = {
+        "metric": "source-term cells/s at 53sp/325rxn (FP32 path; FP64 path, p50/p99 "
+                  "latency and FP32-vs-FP64 error alongside)",
+        "value": value,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{ns}sp/{nr}rxn synthetic mechanism x {n} cells, FP32 states",
+                   "n_species": ns, "n_reactions": nr, "n_cells": n,
+                   "mechanism_seed": synth.MECH_SEEDS[(ns, nr)], "state_seed": wl["state_seed"],
+                   "layout": "T[n], P[n], Y[NS][n] (cell index fastest)"},
+        "latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99)),
+                       "kernel_mean": float(ms.mean())},
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": roofline.PEAK_VALU_SLOTS / 1e12,
+            "unit": "T VALU lane-slots/s",
+            "frac": achieved / roofline.PEAK_VALU_SLOTS,
+            "traffic": traffic,
+            "kernel": "ak::source_kernel<float>",
+            "slots_per_cell": slots,
+            "hbm_GBps": roofline.hbm_bytes(ns, 4) * n / k_avg_s / 1e9,
+            "hbm_frac": roofline.hbm_bytes(ns, 4) * n / k_avg_s / roofline.PEAK_HBM,
+        },
+    }
+
+    if not args.no_fp64:
+        T64, P64, Y64 = (t.double() for t in (T32, P32, Y32))
+        wall64, ms64, om64 = time_path(torch, annkin, mech, T64, P64, Y64,
+                                       max(5, args.steps // 2), 2)
+        d = (om32.double() - om64).abs()
+        ref = om64.abs()
+        big = ref >= 1e-6 * ref.max()
+        rel = (d[big] / ref[big]).float()
+        result["fp64"] = {
+            "cells_per_s": n * max(5, args.steps // 2) / wall64,
+            "kernel_mean_ms": float(ms64.mean()),
+            "p50_ms": float(np.percentile(ms64, 50)),
+            "p99_ms": float(np.percentile(ms64, 99)),
+        }
+        result["err_fp32_vs_fp64"] = {
+            "rel_median": float(rel.median()), "rel_p99": float(torch.quantile(
+                rel[torch.randperm(rel.numel(), device=rel.device)[:1 << 20]], 0.99)),
+            "definition": "|w32 - w64| / |w64| over entries with |w64| >= 1e-6 max|w64|",
+        }
+        del T64, P64, Y64, om64
+
+    if args.workload == "c1_full":
+        m = 65536
+        wall_s, ms_s, _ = time_path(torch, annkin, mech, T32[:m].contiguous(),
+                                    P32[:m].contiguous(), Y32[:, :m].contiguous(),
+                                    args.steps, args.warmup)
+        result["c1_65536_cells_per_s"] = m * args.steps / wall_s
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(src, T, P, Y)
+
+    mech.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

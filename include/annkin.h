@@ -1,0 +1,144 @@
+/*
+ * annkin: batched chemical source terms on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libannkin.so.  The library evaluates, for a batch of N_C
+ * reacting cells, the net molar production rates of Barwey & Raman,
+ * "A Neural Network Inspired Formulation of Chemical Kinetics":
+ *
+ *   omega_k = sum_j nu_kj (q_f,j - q_r,j)                        (Eq. 2)
+ *   q_f,j = exp(sum_k nu'_kj ln C_k + ln k_f,j),
+ *   q_r,j = exp(sum_k nu''_kj ln C_k + ln k_f,j - ln K_c,j)      (Eq. 4, Eq. 7)
+ *   ln k_f,j = ln A_j + beta_j ln T - (E_j/R)/T                  (Eq. 6)
+ *   ln K_c,j = -sum_k nu_kj (G_k - ln(p_ref/(R T)))              (Eqs. 9-11)
+ *
+ * with G_k = H_k/(RT) - S_k/R from NASA 7-coefficient polynomials (Eq. 10)
+ * and p_ref = 1 bar.  The batch dimension N_C is the leading (fastest)
+ * dimension of every per-cell array (Sec. 2.1).
+ *
+ * Conventions for every entry point:
+ *  - Return 0 on success or a negative AK_E* code; ak_last_error() then
+ *    returns a message for the calling thread.
+ *  - State and result pointers are DEVICE pointers on the mechanism's
+ *    device, owned by the caller, of the element type the precision
+ *    selects (AK_FP32: float, AK_FP64: double).
+ *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*;
+ *    NULL is the null stream).  Argument errors are reported synchronously,
+ *    before anything is enqueued.  Concurrent calls on different streams
+ *    are allowed.
+ *  - Units: T in K, P in Pa, Y mass fractions (need not sum to one;
+ *    negative values count as zero), omega in kmol m^-3 s^-1.
+ *  - Layout: Y[k*ldY + i] for species k and cell i (ldY >= n_cells), and
+ *    likewise for omega with ldO.
+ *  - A cell with non-finite input, T <= 0 or P <= 0 gets NaN outputs and is
+ *    counted on the mechanism's device-side error counter (ak_error_count).
+ *  - n_cells == 0 is a no-op.
+ */
+#ifndef ANNKIN_H
+#define ANNKIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AK_OK 0
+#define AK_EINVAL (-1)       /* bad argument (null pointer, size, enum, layout) */
+#define AK_EDEVICE (-2)      /* HIP runtime error; message in ak_last_error() */
+#define AK_ENOMEM (-3)       /* device or host allocation failed */
+#define AK_E2BIG (-4)        /* request larger than a configured limit */
+#define AK_ETIMEDOUT (-5)    /* wait timed out */
+#define AK_ECANCELED (-6)    /* request was cancelled */
+#define AK_EUNSUPPORTED (-7) /* mechanism feature outside what the kernels handle */
+
+typedef enum { AK_FP64 = 0, AK_FP32 = 1 } ak_precision;
+
+typedef struct ak_mechanism ak_mechanism; /* opaque; owns its device tables */
+
+/*
+ * Mechanism as a CHEMKIN-style file carries it (Sec. 2, Eq. 1; Eq. 5;
+ * Eq. 10).  All pointers are HOST arrays owned by the caller and copied
+ * during ak_load_mechanism; row-major.
+ *   W          [NS]      molecular weights, kg/kmol (> 0)
+ *   nu_f, nu_r [NR][NS]  reactant / product stoichiometric coefficients
+ *                        nu'_kj, nu''_kj at [j*NS + k] (>= 0)
+ *   ln_A       [NR]      ln of the pre-exponential factor in cgs units,
+ *                        (cm^3/mol)^(order-1)/s, order = sum_k nu'_kj
+ *   beta       [NR]      temperature exponent
+ *   Ea         [NR]      activation energy, cal/mol
+ *   nasa_low, nasa_high [NS][7]  NASA-7 coefficients a1..a7 below / at and
+ *                        above T_mid
+ *   T_mid      [NS]      range switch temperature, K
+ *   reversible [NR]      1 = reversible, 0 = irreversible (the indicator of
+ *                        Sec. 2.4); NULL means all reversible
+ * Limits: 1 <= NS <= 1024, NR >= 1, at most 4 reactant and 4 product
+ * molecules per reaction counting multiplicity (sum of nu' <= 4,
+ * sum of nu'' <= 4); otherwise AK_EUNSUPPORTED.
+ */
+typedef struct {
+    int32_t n_species;
+    int32_t n_reactions;
+    const double *W;
+    const int8_t *nu_f;
+    const int8_t *nu_r;
+    const double *ln_A;
+    const double *beta;
+    const double *Ea;
+    const double *nasa_low;
+    const double *nasa_high;
+    const double *T_mid;
+    const uint8_t *reversible;
+} ak_mechanism_desc;
+
+/* Thread-local message describing the last error on this thread. */
+const char *ak_last_error(void);
+
+/* Library version string. */
+const char *ak_version(void);
+
+/*
+ * Convert and upload a mechanism to `device` (HIP ordinal): rate parameters
+ * to SI-kmol units and base-2 logarithms, NASA coefficients to the
+ * Gibbs-layer weights of Eq. 11 with the standard concentration folded in,
+ * and the stoichiometry to per-reaction factor lists.  The call is
+ * synchronous.  On success *out owns device memory until ak_free_mechanism.
+ * Errors: AK_EINVAL (null/invalid desc), AK_EUNSUPPORTED, AK_EDEVICE,
+ * AK_ENOMEM.
+ */
+int ak_load_mechanism(const ak_mechanism_desc *desc, int device, ak_mechanism **out);
+
+/* Free a mechanism.  The caller must ensure no enqueued work still uses it
+ * (synchronise the streams first).  NULL is a no-op. */
+int ak_free_mechanism(ak_mechanism *mech);
+
+/* Number of species / reactions of a loaded mechanism (or -1 for NULL). */
+int ak_mechanism_n_species(const ak_mechanism *mech);
+int ak_mechanism_n_reactions(const ak_mechanism *mech);
+
+/*
+ * Net production rates omega (Eq. 2 with the rates of Eq. 4) for n_cells
+ * cells.  T[n_cells], P[n_cells], Y[NS][ldY] in; omega[NS][ldO] out.
+ * AK_FP32 takes float states and returns float omega; internally the
+ * chemical potentials and the forward/reverse difference are evaluated in
+ * double precision and the rate exponentials in single precision.
+ * AK_FP64 is double throughout.
+ * Errors: AK_EINVAL (null pointers with n_cells > 0, n_cells < 0,
+ * ldY or ldO < n_cells, bad precision), AK_EDEVICE (launch failure).
+ */
+int ak_eval_source(const ak_mechanism *mech, ak_precision prec, const void *T, const void *P,
+                   const void *Y, int64_t ldY, int64_t n_cells, void *omega, int64_t ldO,
+                   void *stream);
+
+/*
+ * Read and reset the number of bad cells (non-finite input, T <= 0 or
+ * P <= 0) seen by all evaluations with this mechanism since the last call.
+ * Synchronises `stream`.  Errors: AK_EINVAL, AK_EDEVICE.
+ */
+int ak_error_count(const ak_mechanism *mech, void *stream, int64_t *n_bad_cells);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ANNKIN_H */

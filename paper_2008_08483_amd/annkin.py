@@ -1,0 +1,178 @@
+"""Python binding of libannkin.so (ctypes).
+
+Argument marshalling only: every step of the source-term evaluation runs in
+the library's HIP kernels.  PyTorch provides device memory (CUDA/HIP tensors)
+and the current stream.  There is no CPU fallback: if the library or a GPU is
+missing, these functions raise.
+
+Layouts follow the C ABI (``include/annkin.h``): T and P are [n] tensors, Y
+and omega are [NS, n] tensors with the cell index fastest (row stride = the
+leading dimension ld >= n).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libannkin.so")
+
+AK_FP64 = 0
+AK_FP32 = 1
+_ERRORS = {-1: "AK_EINVAL", -2: "AK_EDEVICE", -3: "AK_ENOMEM", -4: "AK_E2BIG",
+           -5: "AK_ETIMEDOUT", -6: "AK_ECANCELED", -7: "AK_EUNSUPPORTED"}
+
+_lib = None
+
+
+class AnnkinError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MechanismDesc(C.Structure):
+    _fields_ = [
+        ("n_species", C.c_int32), ("n_reactions", C.c_int32),
+        ("W", C.c_void_p), ("nu_f", C.c_void_p), ("nu_r", C.c_void_p),
+        ("ln_A", C.c_void_p), ("beta", C.c_void_p), ("Ea", C.c_void_p),
+        ("nasa_low", C.c_void_p), ("nasa_high", C.c_void_p), ("T_mid", C.c_void_p),
+        ("reversible", C.c_void_p),
+    ]
+
+
+def lib():
+    """Load libannkin.so (fails loudly if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2008_08483_amd.build`")
+        h = C.CDLL(LIB_PATH)
+        h.ak_last_error.restype = C.c_char_p
+        h.ak_version.restype = C.c_char_p
+        h.ak_load_mechanism.argtypes = [C.POINTER(MechanismDesc), C.c_int, C.POINTER(C.c_void_p)]
+        h.ak_free_mechanism.argtypes = [C.c_void_p]
+        h.ak_mechanism_n_species.argtypes = [C.c_void_p]
+        h.ak_mechanism_n_reactions.argtypes = [C.c_void_p]
+        h.ak_eval_source.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+        h.ak_error_count.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]
+        _lib = h
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise AnnkinError(rc, lib().ak_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Mechanism:
+    """A mechanism uploaded to one GPU.  ``src`` is any object with the
+    attributes of ``synth.Mechanism`` (W, nu_f, nu_r, ln_A, beta, Ea,
+    nasa_low, nasa_high, T_mid, reversible)."""
+
+    def __init__(self, src, device: int | None = None):
+        torch = _torch()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        self.n_species = int(src.W.shape[0])
+        self.n_reactions = int(src.nu_f.shape[0])
+        keep = {
+            "W": np.ascontiguousarray(src.W, np.float64),
+            "nu_f": np.ascontiguousarray(src.nu_f, np.int8),
+            "nu_r": np.ascontiguousarray(src.nu_r, np.int8),
+            "ln_A": np.ascontiguousarray(src.ln_A, np.float64),
+            "beta": np.ascontiguousarray(src.beta, np.float64),
+            "Ea": np.ascontiguousarray(src.Ea, np.float64),
+            "nasa_low": np.ascontiguousarray(src.nasa_low, np.float64),
+            "nasa_high": np.ascontiguousarray(src.nasa_high, np.float64),
+            "T_mid": np.ascontiguousarray(src.T_mid, np.float64),
+            "reversible": np.ascontiguousarray(src.reversible, np.uint8),
+        }
+        d = MechanismDesc(self.n_species, self.n_reactions, *(keep[k].ctypes.data for k in (
+            "W", "nu_f", "nu_r", "ln_A", "beta", "Ea", "nasa_low", "nasa_high", "T_mid",
+            "reversible")))
+        h = C.c_void_p()
+        _check(lib().ak_load_mechanism(C.byref(d), self.device, C.byref(h)))
+        self._h = h
+        self.name = getattr(src, "name", "mechanism")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ak_free_mechanism(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error_count(self, stream=None) -> int:
+        """Read and reset the device-side bad-cell counter (synchronises)."""
+        n = C.c_int64()
+        _check(lib().ak_error_count(self._h, _stream_ptr(stream), C.byref(n)))
+        return int(n.value)
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _prec(dtype):
+    torch = _torch()
+    if dtype == torch.float32:
+        return AK_FP32
+    if dtype == torch.float64:
+        return AK_FP64
+    raise TypeError(f"unsupported dtype {dtype}: use float32 or float64")
+
+
+def _check_state(mech, T, P, Y):
+    torch = _torch()
+    for name, t in (("T", T), ("P", P), ("Y", Y)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a GPU tensor")
+    if T.dtype != P.dtype or T.dtype != Y.dtype:
+        raise TypeError("T, P and Y must share one dtype")
+    n = T.shape[0]
+    if T.dim() != 1 or P.shape != (n,) or not T.is_contiguous() or not P.is_contiguous():
+        raise ValueError("T and P must be contiguous [n] tensors")
+    if Y.dim() != 2 or Y.shape[0] != mech.n_species or Y.shape[1] != n or Y.stride(1) != 1:
+        raise ValueError(f"Y must be [NS={mech.n_species}, n={n}] with unit cell stride")
+    return n
+
+
+def eval_source(mech: Mechanism, T, P, Y, out=None, stream=None):
+    """omega [NS, n] (kmol m^-3 s^-1) for states T [n] (K), P [n] (Pa),
+    Y [NS, n]; float32 tensors select the FP32 path, float64 the FP64 path.
+    Asynchronous on ``stream`` (default: torch's current stream)."""
+    torch = _torch()
+    n = _check_state(mech, T, P, Y)
+    if out is None:
+        out = torch.empty((mech.n_species, n), dtype=T.dtype, device=T.device)
+    elif (out.shape != (mech.n_species, n) or out.dtype != T.dtype or out.stride(1) != 1
+          or not out.is_cuda):
+        raise ValueError("out must be a GPU [NS, n] tensor of the state dtype")
+    ldY = Y.stride(0) if mech.n_species > 1 else n
+    ldO = out.stride(0) if mech.n_species > 1 else n
+    _check(lib().ak_eval_source(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
+                                Y.data_ptr(), ldY, n, out.data_ptr(), ldO, _stream_ptr(stream)))
+    return out

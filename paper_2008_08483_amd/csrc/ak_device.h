@@ -1,0 +1,69 @@
+// Device-side mechanism tables shared by the annkin kernels and their host
+// preprocessing.  The layouts here are the library's own; the test oracle
+// never sees them.
+#pragma once
+#include <stdint.h>
+
+namespace ak {
+
+// Physical constants: gas constant J/(kmol K), thermochemical calorie,
+// reference pressure 1 bar (Eq. 8).
+constexpr double kRu = 8314.46261815324;
+constexpr double kRuMol = 8.31446261815324;
+constexpr double kCal = 4.184;
+constexpr double kPref = 1.0e5;
+constexpr double kLog2e = 1.4426950408889634073599;
+
+// Per species (128 B).  The Gibbs-layer weights act on the temperature
+// features (ln T, T, T^2, T^3, T^4, 1/T, 1) and give
+//     g2_k(T) = log2(e) * (G_k(T) - ln(p_ref/(Ru T)))
+// i.e. the paper's Gibbs matrix (Eq. 10) with the standard concentration
+// p_ref/(R T) folded into the weights (Eq. 11), in base-2 units.
+struct SpeciesRec {
+    double inv_W;      // 1 / W_k, kmol/kg
+    double T_mid;      // K; the high-range weights apply for T >= T_mid
+    double lo[7];
+    double hi[7];
+};
+static_assert(sizeof(SpeciesRec) == 128, "SpeciesRec layout");
+
+// Per reaction (64 B), reactions stored sorted by shape (see ShapeRun).
+// Arrhenius layer (Eq. 6) in base 2:
+//     log2 k_f = log2A + beta * log2 T + negEoR2 / T
+// off[0..nf) are the LDS byte offsets of the reactant molecules' species
+// rows (a species repeated nu' times), off[nf..nf+nr) those of the product
+// molecules; row offset = species * species_stride.
+struct RxnRec {
+    double log2A;      // log2 of A in SI-kmol units
+    double beta;
+    double negEoR2;    // -(E/R) * log2(e), K
+    double rev;        // 1 reversible, 0 irreversible
+    uint32_t off[8];
+};
+static_assert(sizeof(RxnRec) == 64, "RxnRec layout");
+
+constexpr int kMaxSide = 4;      // molecules per side
+constexpr int kMaxRuns = 16;     // shapes (nf, nr) in 1..4 x 1..4
+
+struct ShapeRun {
+    int32_t nf, nr, start, count;
+};
+
+// Kernel argument view of a loaded mechanism.
+struct MechView {
+    const SpeciesRec *sp;
+    const RxnRec *rx;
+    unsigned long long *err;     // bad-cell counter
+    int32_t ns, nr, nruns;
+    int32_t tile;                // cells per workgroup tile (<= 64)
+    ShapeRun runs[kMaxRuns];
+};
+
+// LDS tile: per (species k, cell c) a 24-byte entry at
+//     k * species_stride(tile) + c * kEntry
+// holding {double a, double v, accumulator (float or double)}.
+constexpr int kEntry = 24;
+constexpr int kMaxTile = 64;
+constexpr uint32_t species_stride(int tile) { return (uint32_t)tile * kEntry; }
+
+}  // namespace ak

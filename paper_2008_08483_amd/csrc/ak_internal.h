@@ -1,0 +1,37 @@
+// Host-side internals shared by the annkin translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "ak_device.h"
+
+struct ak_mechanism {
+    int device = 0;
+    int ns = 0, nr = 0;
+    ak::MechView view{};
+    std::vector<ak::SpeciesRec> host_species;
+    std::vector<ak::RxnRec> host_rxn;   // shape-sorted order
+    std::vector<int> rxn_order;         // file index of each sorted reaction
+};
+
+namespace ak {
+
+int set_error(int code, const char *fmt, ...);
+int hip_error(hipError_t e, const char *what);
+
+// Makes `dev` current for the lifetime of the guard, restoring the caller's
+// device afterwards.
+struct DeviceGuard {
+    int prev;
+    bool ok;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+size_t source_lds_bytes(int ns, int tile);
+hipError_t source_launch(const MechView &m, bool f64, const void *T, const void *P,
+                         const void *Y, int64_t ldY, int64_t n, void *om, int64_t ldO,
+                         hipStream_t st);
+
+}  // namespace ak

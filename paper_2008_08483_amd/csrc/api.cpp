@@ -1,0 +1,271 @@
+// C ABI of libannkin.so: argument checking, mechanism preprocessing and
+// upload, launch dispatch.  See include/annkin.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "annkin.h"
+#include "ak_device.h"
+#include "ak_internal.h"
+
+namespace ak {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_error(hipError_t e, const char *what)
+{
+    return set_error(AK_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+DeviceGuard::DeviceGuard(int dev) : prev(-1), ok(true)
+{
+    if (hipGetDevice(&prev) != hipSuccess) {
+        ok = false;
+        return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+}
+DeviceGuard::~DeviceGuard()
+{
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
+
+// Gibbs-layer weights on (ln T, T, T^2, T^3, T^4, 1/T, 1) for one NASA-7
+// set a1..a7, scaled by log2(e):
+//   G - ln(p_ref/(Ru T)) = (1 - a1) ln T - a2/2 T - a3/6 T^2 - a4/12 T^3
+//                          - a5/20 T^4 + a6/T + a1 - a7 - ln(p_ref/Ru)
+// (G = H/RT - S/R with the NASA-7 enthalpy and entropy, Eq. 10; the
+// standard-concentration term of Eq. 9 folded into the ln T weight and the
+// bias as Eq. 11 describes).
+static void gibbs_weights(const double *a, double *c)
+{
+    c[0] = (1.0 - a[0]) * kLog2e;
+    c[1] = -a[1] / 2.0 * kLog2e;
+    c[2] = -a[2] / 6.0 * kLog2e;
+    c[3] = -a[3] / 12.0 * kLog2e;
+    c[4] = -a[4] / 20.0 * kLog2e;
+    c[5] = a[5] * kLog2e;
+    c[6] = (a[0] - a[6] - std::log(kPref / kRu)) * kLog2e;
+}
+
+static bool finite_all(const double *p, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace ak
+
+using namespace ak;
+
+extern "C" {
+
+const char *ak_last_error(void) { return g_last_error.c_str(); }
+
+const char *ak_version(void) { return "annkin 0.1 (gfx950)"; }
+
+int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out)
+{
+    if (!d || !out) return set_error(AK_EINVAL, "ak_load_mechanism: null argument");
+    *out = nullptr;
+    const int ns = d->n_species, nr = d->n_reactions;
+    if (ns < 1 || ns > 1024 || nr < 1)
+        return set_error(AK_EINVAL, "ak_load_mechanism: bad sizes ns=%d nr=%d", ns, nr);
+    if (!d->W || !d->nu_f || !d->nu_r || !d->ln_A || !d->beta || !d->Ea || !d->nasa_low ||
+        !d->nasa_high || !d->T_mid)
+        return set_error(AK_EINVAL, "ak_load_mechanism: null array in descriptor");
+    for (int k = 0; k < ns; ++k)
+        if (!(d->W[k] > 0.0) || !std::isfinite(d->W[k]) || !std::isfinite(d->T_mid[k]))
+            return set_error(AK_EINVAL, "ak_load_mechanism: bad W or T_mid of species %d", k);
+    if (!finite_all(d->ln_A, nr) || !finite_all(d->beta, nr) || !finite_all(d->Ea, nr) ||
+        !finite_all(d->nasa_low, 7 * (size_t)ns) || !finite_all(d->nasa_high, 7 * (size_t)ns))
+        return set_error(AK_EINVAL, "ak_load_mechanism: non-finite parameter");
+
+    std::vector<SpeciesRec> sp(ns);
+    for (int k = 0; k < ns; ++k) {
+        sp[k].inv_W = 1.0 / d->W[k];
+        sp[k].T_mid = d->T_mid[k];
+        gibbs_weights(&d->nasa_low[7 * k], sp[k].lo);
+        gibbs_weights(&d->nasa_high[7 * k], sp[k].hi);
+    }
+
+    DeviceGuard g(device);
+    if (!g.ok) return set_error(AK_EDEVICE, "ak_load_mechanism: cannot select device %d", device);
+    // tile: cells per workgroup, as many as the LDS holds (at most 64)
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              device) != hipSuccess || lds_max <= 0)
+        return set_error(AK_EDEVICE, "ak_load_mechanism: cannot query LDS size of device %d",
+                         device);
+    lds_max = std::min(lds_max, 160 * 1024);
+    const int tile = std::min<int>(kMaxTile, lds_max / (ns * kEntry));
+    if (tile < 16)
+        return set_error(AK_EUNSUPPORTED, "ak_load_mechanism: %d species do not fit the LDS tile",
+                         ns);
+    const uint32_t sstride = species_stride(tile);
+
+    std::vector<RxnRec> rx(nr);
+    std::vector<int> shape(nr);
+    for (int j = 0; j < nr; ++j) {
+        RxnRec &r = rx[j];
+        std::memset(&r, 0, sizeof r);
+        int nf = 0, np = 0, order = 0;
+        uint32_t reac[kMaxSide], prod[kMaxSide];
+        for (int k = 0; k < ns; ++k) {
+            const int a = d->nu_f[(size_t)j * ns + k], b = d->nu_r[(size_t)j * ns + k];
+            if (a < 0 || b < 0)
+                return set_error(AK_EINVAL, "reaction %d: negative stoichiometric coefficient", j);
+            order += a;
+            if (nf + a > kMaxSide || np + b > kMaxSide)
+                return set_error(AK_EUNSUPPORTED,
+                                 "reaction %d: more than %d molecules on one side", j, kMaxSide);
+            for (int t = 0; t < a; ++t) reac[nf++] = (uint32_t)k * sstride;
+            for (int t = 0; t < b; ++t) prod[np++] = (uint32_t)k * sstride;
+        }
+        if (nf == 0 || np == 0)
+            return set_error(AK_EUNSUPPORTED, "reaction %d: empty reactant or product side", j);
+        for (int t = 0; t < nf; ++t) r.off[t] = reac[t];
+        for (int t = 0; t < np; ++t) r.off[nf + t] = prod[t];
+        // Arrhenius parameters: A from (cm^3/mol)^(order-1)/s to (m^3/kmol)^(order-1)/s
+        r.log2A = (d->ln_A[j] + (order - 1) * std::log(1e-3)) * kLog2e;
+        r.beta = d->beta[j];
+        r.negEoR2 = -(d->Ea[j] * kCal / kRuMol) * kLog2e;
+        r.rev = (d->reversible == nullptr || d->reversible[j]) ? 1.0 : 0.0;
+        shape[j] = (nf - 1) * kMaxSide + (np - 1);
+    }
+    // sort reactions by shape so each wave runs a uniform code path per run
+    std::vector<int> order(nr);
+    for (int j = 0; j < nr; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return shape[a] < shape[b]; });
+    std::vector<RxnRec> rxs(nr);
+    MechView view;
+    std::memset(&view, 0, sizeof view);
+    view.ns = ns;
+    view.nr = nr;
+    view.tile = tile;
+    std::vector<int> rxn_order(order);
+    for (int i = 0; i < nr; ++i) {
+        rxs[i] = rx[order[i]];
+        const int s = shape[order[i]];
+        if (view.nruns == 0 || (view.runs[view.nruns - 1].nf - 1) * kMaxSide +
+                                       (view.runs[view.nruns - 1].nr - 1) != s) {
+            ShapeRun &run = view.runs[view.nruns++];
+            run.nf = s / kMaxSide + 1;
+            run.nr = s % kMaxSide + 1;
+            run.start = i;
+            run.count = 0;
+        }
+        view.runs[view.nruns - 1].count++;
+    }
+
+    ak_mechanism *m = new (std::nothrow) ak_mechanism();
+    if (!m) return set_error(AK_ENOMEM, "ak_load_mechanism: out of host memory");
+    m->device = device;
+    m->ns = ns;
+    m->nr = nr;
+    hipError_t e;
+    void *psp = nullptr, *prx = nullptr, *perr = nullptr;
+    if ((e = hipMalloc(&psp, sizeof(SpeciesRec) * ns)) != hipSuccess ||
+        (e = hipMalloc(&prx, sizeof(RxnRec) * nr)) != hipSuccess ||
+        (e = hipMalloc(&perr, sizeof(unsigned long long))) != hipSuccess) {
+        if (psp) (void)hipFree(psp);
+        if (prx) (void)hipFree(prx);
+        delete m;
+        return set_error(AK_ENOMEM, "ak_load_mechanism: device allocation failed: %s",
+                         hipGetErrorString(e));
+    }
+    unsigned long long zero = 0;
+    if ((e = hipMemcpy(psp, sp.data(), sizeof(SpeciesRec) * ns, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(prx, rxs.data(), sizeof(RxnRec) * nr, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(perr, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(psp);
+        (void)hipFree(prx);
+        (void)hipFree(perr);
+        delete m;
+        return hip_error(e, "ak_load_mechanism: upload");
+    }
+    view.sp = (const SpeciesRec *)psp;
+    view.rx = (const RxnRec *)prx;
+    view.err = (unsigned long long *)perr;
+    m->view = view;
+    m->host_species = std::move(sp);
+    m->host_rxn = std::move(rxs);
+    m->rxn_order = std::move(rxn_order);
+    *out = m;
+    return AK_OK;
+}
+
+int ak_free_mechanism(ak_mechanism *m)
+{
+    if (!m) return AK_OK;
+    DeviceGuard g(m->device);
+    (void)hipFree((void *)m->view.sp);
+    (void)hipFree((void *)m->view.rx);
+    (void)hipFree((void *)m->view.err);
+    delete m;
+    return AK_OK;
+}
+
+int ak_mechanism_n_species(const ak_mechanism *m) { return m ? m->ns : -1; }
+int ak_mechanism_n_reactions(const ak_mechanism *m) { return m ? m->nr : -1; }
+
+int ak_eval_source(const ak_mechanism *m, ak_precision prec, const void *T, const void *P,
+                   const void *Y, int64_t ldY, int64_t n, void *omega, int64_t ldO, void *stream)
+{
+    if (!m) return set_error(AK_EINVAL, "ak_eval_source: null mechanism");
+    if (prec != AK_FP32 && prec != AK_FP64)
+        return set_error(AK_EINVAL, "ak_eval_source: bad precision %d", (int)prec);
+    if (n < 0) return set_error(AK_EINVAL, "ak_eval_source: n_cells < 0");
+    if (n == 0) return AK_OK;
+    if (!T || !P || !Y || !omega) return set_error(AK_EINVAL, "ak_eval_source: null pointer");
+    if (ldY < n || ldO < n)
+        return set_error(AK_EINVAL, "ak_eval_source: ldY=%lld ldO=%lld < n_cells=%lld",
+                         (long long)ldY, (long long)ldO, (long long)n);
+    if (n > (int64_t)1 << 40) return set_error(AK_E2BIG, "ak_eval_source: n_cells too large");
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "ak_eval_source: cannot select device %d", m->device);
+    hipError_t e = source_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, omega, ldO,
+                                 (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "ak_eval_source: launch");
+    return AK_OK;
+}
+
+int ak_error_count(const ak_mechanism *m, void *stream, int64_t *n_bad)
+{
+    if (!m || !n_bad) return set_error(AK_EINVAL, "ak_error_count: null argument");
+    DeviceGuard g(m->device);
+    unsigned long long v = 0, zero = 0;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(&v, m->view.err, sizeof v, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(m->view.err, &zero, sizeof zero, hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+        return hip_error(e, "ak_error_count");
+    *n_bad = (int64_t)v;
+    return AK_OK;
+}
+
+}  // extern "C"
