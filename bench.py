@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--workload", default="c1_full", choices=list(synth.WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--only-main", action="store_true",
+                    help="time only the main FP32 leg (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -177,6 +179,8 @@ def main():
         },
     }
 
+    if args.only_main:
+        args.no_fp64 = args.no_cpu_baseline = True
     if not args.no_fp64:
         T64, P64, Y64 = (t.double() for t in (T32, P32, Y32))
         wall64, ms64, om64 = time_path(torch, annkin, mech, T64, P64, Y64,
@@ -198,7 +202,7 @@ def main():
         }
         del T64, P64, Y64, om64
 
-    if args.workload == "c1_full":
+    if args.workload == "c1_full" and not args.only_main:
         m = 65536
         wall_s, ms_s, _ = time_path(torch, annkin, mech, T32[:m].contiguous(),
                                     P32[:m].contiguous(), Y32[:, :m].contiguous(),

@@ -4,7 +4,7 @@
 // waves share an LDS tile that holds, per (species k, cell):
 //     a_k   = C_k * exp(Gt_k)   (double)   -- exp of the chemical potential
 //     v_k   = exp(-Gt_k)        (double)
-//     w_k   = omega_k accumulator (float in the FP32 path, double in FP64)
+//     w_k   = omega_k accumulator (double)
 // with Gt_k = G_k - ln(p_ref/(R T)) the Gibbs-layer output (Eqs. 10-11).
 // The exact ANN form of Eq. 4,
 //     q_f = exp(nu'.lnC + ln k_f),  q_r = exp(nu''.lnC + ln k_f - ln K_c),
@@ -22,7 +22,7 @@
 #include "ak_device.h"
 
 #ifndef AK_SOURCE_WAVES
-#define AK_SOURCE_WAVES 4
+#define AK_SOURCE_WAVES 8
 #endif
 
 namespace ak {
@@ -31,30 +31,41 @@ struct Cell {
     double log2T, invT;
 };
 
-template <bool F64>
-struct AccT;
-template <>
-struct AccT<false> { using type = float; };
-template <>
-struct AccT<true> { using type = double; };
+// omega accumulators are double in both paths: LDS float atomics stall the
+// LDS pipeline on gfx950 far more than double ones (measured), and double
+// accumulation costs nothing in accuracy.
 
-__device__ __forceinline__ void lds_add(float *p, float x)
+// Reaction record held in VGPRs.  Records are fetched with vector loads
+// (all lanes read the same address): scalar loads would share the LGKM
+// counter with the LDS traffic, and every wait for a record would then also
+// wait for all outstanding LDS reads and atomics.
+struct RxnV {
+    double log2A, beta, negEoR2, rev;
+    uint32_t off[8];
+};
+
+__device__ __forceinline__ RxnV load_rxn(const RxnRec *rx, int j, uint32_t lane_zero)
 {
-    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_add(double *p, double x)
-{
-    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // lane_zero is 0 at run time but not known uniform to the compiler,
+    // which keeps this a vector load
+    const uint4 *p = (const uint4 *)(rx + j + lane_zero);
+    const uint4 w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3];
+    RxnV r;
+    r.log2A = __builtin_bit_cast(double, make_uint2(w0.x, w0.y));
+    r.beta = __builtin_bit_cast(double, make_uint2(w0.z, w0.w));
+    r.negEoR2 = __builtin_bit_cast(double, make_uint2(w1.x, w1.y));
+    r.rev = __builtin_bit_cast(double, make_uint2(w1.z, w1.w));
+    r.off[0] = w2.x; r.off[1] = w2.y; r.off[2] = w2.z; r.off[3] = w2.w;
+    r.off[4] = w3.x; r.off[5] = w3.y; r.off[6] = w3.z; r.off[7] = w3.w;
+    return r;
 }
 
 // One reaction's rate of progress q = q_f - q_r for this lane's cell, from
 // the LDS tile.  Also returns the LDS addresses of its molecules' entries.
 template <bool F64, int NF, int NR>
-__device__ __forceinline__ typename AccT<F64>::type rate_of_progress(const RxnRec &R,
-                                                                     const unsigned char *lds,
-                                                                     uint32_t lane_off,
-                                                                     const Cell c,
-                                                                     uint32_t (&addr)[NF + NR])
+__device__ __forceinline__ double rate_of_progress(const RxnV &R, const unsigned char *lds,
+                                                   uint32_t lane_off, const Cell c,
+                                                   uint32_t (&addr)[NF + NR])
 {
     // Arrhenius layer, base 2 (Eq. 6)
     const double t = __builtin_fma(R.beta, c.log2T, __builtin_fma(R.negEoR2, c.invT, R.log2A));
@@ -83,54 +94,70 @@ __device__ __forceinline__ typename AccT<F64>::type rate_of_progress(const RxnRe
         const double n = __builtin_rint(t);
         const float f = (float)(t - n);
         const float p = __builtin_amdgcn_exp2f(f);
-        return (float)__builtin_ldexp(Vr * D, (int)n) * p;
+        return __builtin_ldexp(Vr * D, (int)n) * (double)p;
     }
+}
+
+__device__ __forceinline__ void lds_add(double *p, double x)
+{
+    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Production layer (Eq. 2): -q into each reactant molecule's accumulator,
 // +q into each product molecule's.
-template <bool F64, int NF, int NR>
+template <int NF, int NR>
 __device__ __forceinline__ void scatter(unsigned char *lds, const uint32_t (&addr)[NF + NR],
-                                        typename AccT<F64>::type q)
+                                        double q)
 {
-    using Acc = typename AccT<F64>::type;
 #pragma unroll
-    for (int i = 0; i < NF; ++i) lds_add((Acc *)(lds + addr[i] + 16), -q);
+    for (int i = 0; i < NF; ++i) lds_add((double *)(lds + addr[i] + 16), -q);
 #pragma unroll
-    for (int i = 0; i < NR; ++i) lds_add((Acc *)(lds + addr[NF + i] + 16), q);
+    for (int i = 0; i < NR; ++i) lds_add((double *)(lds + addr[NF + i] + 16), q);
 }
 
 // Reactions of one shape run: this wave takes reactions start+wave,
-// start+wave+WAVES, ...; two at a time so that their loads overlap.
+// start+wave+WAVES, ...; two at a time so that their loads overlap, with the
+// next pair's records fetched while the current pair computes.
 template <bool F64, int NF, int NR, int WAVES>
 __device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun run, int wave,
                                              unsigned char *lds, uint32_t lane_off,
-                                             const Cell c, bool active)
+                                             const Cell c, bool active, uint32_t lane_zero)
 {
     const int end = run.start + run.count;
-    for (int j = run.start + wave; j < end; j += 2 * WAVES) {
-        const int j2 = j + WAVES;
-        const bool two = j2 < end;
+    int j = run.start + wave;
+    if (j >= end) return;
+    RxnV r1 = load_rxn(m.rx, j, lane_zero);
+    RxnV r2 = load_rxn(m.rx, j + WAVES < end ? j + WAVES : j, lane_zero);
+    for (; j < end; j += 2 * WAVES) {
+        const bool two = j + WAVES < end;
+        const int jn = j + 2 * WAVES;
+        const int jn1 = jn < end ? jn : j;
+        const int jn2 = jn + WAVES < end ? jn + WAVES : jn1;
+        const RxnV n1 = load_rxn(m.rx, jn1, lane_zero);
+        const RxnV n2 = load_rxn(m.rx, jn2, lane_zero);
         uint32_t a1[NF + NR], a2[NF + NR];
-        const auto q1 = rate_of_progress<F64, NF, NR>(m.rx[j], lds, lane_off, c, a1);
-        const auto q2 = rate_of_progress<F64, NF, NR>(m.rx[two ? j2 : j], lds, lane_off, c, a2);
+        const double q1 = rate_of_progress<F64, NF, NR>(r1, lds, lane_off, c, a1);
+        const double q2 = rate_of_progress<F64, NF, NR>(r2, lds, lane_off, c, a2);
         if (active) {
-            scatter<F64, NF, NR>(lds, a1, q1);
-            if (two) scatter<F64, NF, NR>(lds, a2, q2);
+            scatter<NF, NR>(lds, a1, q1);
+            if (two) scatter<NF, NR>(lds, a2, q2);
         }
+        r1 = n1;
+        r2 = n2;
     }
 }
 
 template <bool F64, int WAVES>
 __device__ __forceinline__ void all_reactions(const MechView &m, int wave, unsigned char *lds,
-                                              uint32_t lane_off, const Cell c, bool active)
+                                              uint32_t lane_off, const Cell c, bool active,
+                                              uint32_t lane_zero)
 {
     for (int r = 0; r < m.nruns; ++r) {
         const ShapeRun run = m.runs[r];
         const int s = (run.nf - 1) * 4 + (run.nr - 1);
-#define AK_CASE(a, b)                                                                  \
-    case (a - 1) * 4 + (b - 1):                                                        \
-        reaction_run<F64, a, b, WAVES>(m, run, wave, lds, lane_off, c, active);        \
+#define AK_CASE(a, b)                                                                          \
+    case (a - 1) * 4 + (b - 1):                                                                \
+        reaction_run<F64, a, b, WAVES>(m, run, wave, lds, lane_off, c, active, lane_zero);     \
         break;
         switch (s) {
             AK_CASE(1, 1) AK_CASE(1, 2) AK_CASE(1, 3) AK_CASE(1, 4)
@@ -145,14 +172,14 @@ __device__ __forceinline__ void all_reactions(const MechView &m, int wave, unsig
 
 // IO: float (AK_FP32) or double (AK_FP64).  Grid: one workgroup per tile of
 // m.tile cells; block = 64 * WAVES threads; dynamic LDS = ns * m.tile * 24 B.
+// lane_zero must be 0 (see load_rxn).
 template <typename IO, bool F64, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void source_kernel(MechView m, const IO *__restrict__ T,
                                                            const IO *__restrict__ P,
                                                            const IO *__restrict__ Y, int64_t ldY,
                                                            int64_t n, IO *__restrict__ om,
-                                                           int64_t ldO)
+                                                           int64_t ldO, uint32_t zero)
 {
-    using Acc = typename AccT<F64>::type;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -161,18 +188,32 @@ __global__ __launch_bounds__(64 * WAVES) void source_kernel(MechView m, const IO
     const int64_t cell = (int64_t)blockIdx.x * tile + lane;
     const bool valid = active && cell < n;          // owns a real cell
     const uint32_t sstride = species_stride(tile);
+    // lanes past the tile read column 0 (harmless) and never write
+    const uint32_t lane_off = active ? (uint32_t)lane * kEntry : 0u;
+    const uint32_t lane_zero = (uint32_t)threadIdx.x & zero;
+
+    // (1) this wave's species: y_k = max(Y_k, 0) / W_k into the a-slot, and
+    //     a partial mixture sum (NaN if any input is not finite)
+    double psum = 0.0;
+    for (int k = wave; k < m.ns; k += WAVES) {
+        const double y = valid ? (double)Y[k * ldY + cell] : 1.0;
+        const double yw = __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
+        psum += __builtin_isfinite(y) ? yw : __builtin_nan("");
+        if (active) *(double *)(lds + (uint32_t)k * sstride + lane_off) = yw;
+    }
+    if (wave < m.ns && active) *(double *)(lds + (uint32_t)wave * sstride + lane_off + 16) = psum;
+    __syncthreads();
+    // (2) mixture sum, same order in every wave
+    double sigma = 0.0;
+    const int nparts = m.ns < WAVES ? m.ns : WAVES;
+    for (int w = 0; w < nparts; ++w)
+        sigma += *(const double *)(lds + (uint32_t)w * sstride + lane_off + 16);
+    __syncthreads();
 
     double Tc = valid ? (double)T[cell] : 1000.0;
     double Pc = valid ? (double)P[cell] : 1.0e5;
-    bool bad = !(Tc > 0.0) || !(Pc > 0.0) || !__builtin_isfinite(Tc) || !__builtin_isfinite(Pc);
-    // mixture: sigma = sum_k max(Y_k, 0) / W_k (every wave, same order)
-    double sigma = 0.0;
-    for (int k = 0; k < m.ns; ++k) {
-        const double y = valid ? (double)Y[k * ldY + cell] : 1.0;
-        bad |= !__builtin_isfinite(y);
-        sigma += __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
-    }
-    bad |= !(sigma > 0.0);
+    const bool bad = !(Tc > 0.0) || !(Pc > 0.0) || !__builtin_isfinite(Tc) ||
+                     !__builtin_isfinite(Pc) || !(sigma > 0.0) || !__builtin_isfinite(sigma);
     if (bad) {
         Tc = 1000.0;
         Pc = 1.0e5;
@@ -182,15 +223,11 @@ __global__ __launch_bounds__(64 * WAVES) void source_kernel(MechView m, const IO
     const double invT = 1.0 / Tc;
     const double T2 = Tc * Tc, T3 = T2 * Tc, T4 = T3 * Tc;
     const double rho_hat = Pc / (kRu * Tc * sigma);   // C_k = rho_hat * Y_k / W_k
-    // lanes past the tile read column 0 (harmless) and never write
-    const uint32_t lane_off = active ? (uint32_t)lane * kEntry : 0u;
 
-    // Gibbs layer (Eqs. 10-11) and the exponentials of the chemical
-    // potentials for this wave's species
+    // (3) Gibbs layer (Eqs. 10-11) and the exponentials of the chemical
+    //     potentials for this wave's species
     for (int k = wave; k < m.ns; k += WAVES) {
         const SpeciesRec &s = m.sp[k];
-        double y = valid ? (double)Y[k * ldY + cell] : 1.0;
-        y = __builtin_fmax(y, 0.0) * s.inv_W;
         const double glo = s.lo[0] * lnT + s.lo[1] * Tc + s.lo[2] * T2 + s.lo[3] * T3 +
                            s.lo[4] * T4 + s.lo[5] * invT + s.lo[6];
         const double ghi = s.hi[0] * lnT + s.hi[1] * Tc + s.hi[2] * T2 + s.hi[3] * T3 +
@@ -198,23 +235,26 @@ __global__ __launch_bounds__(64 * WAVES) void source_kernel(MechView m, const IO
         const double g2 = (Tc >= s.T_mid) ? ghi : glo;
         if (active) {
             double *e = (double *)(lds + (uint32_t)k * sstride + lane_off);
-            e[0] = rho_hat * y * exp2(g2);
+            const double yw = bad ? 0.0 : e[0];
+            e[0] = rho_hat * yw * exp2(g2);
             e[1] = exp2(-g2);
-            *(Acc *)(e + 2) = (Acc)0;
+            e[2] = 0.0;
         }
     }
     __syncthreads();
 
+    // (4) rates of progress and production
     Cell cc;
     cc.log2T = lnT * kLog2e;
     cc.invT = invT;
-    all_reactions<F64, WAVES>(m, wave, lds, lane_off, cc, active);
+    all_reactions<F64, WAVES>(m, wave, lds, lane_off, cc, active, lane_zero);
     __syncthreads();
 
+    // (5) store omega (species-major, coalesced over cells)
     const IO nan = __builtin_nan("");
     for (int k = wave; k < m.ns; k += WAVES) {
         if (valid) {
-            const Acc w = *(const Acc *)(lds + (uint32_t)k * sstride + lane_off + 16);
+            const double w = *(const double *)(lds + (uint32_t)k * sstride + lane_off + 16);
             om[k * ldO + cell] = bad ? nan : (IO)w;
         }
     }
@@ -236,7 +276,7 @@ static hipError_t launch_source(const MechView &m, const void *T, const void *P,
     const int64_t blocks = (n + m.tile - 1) / m.tile;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * WAVES), lds, st, m,
-                       (const IO *)T, (const IO *)P, (const IO *)Y, ldY, n, (IO *)om, ldO);
+                       (const IO *)T, (const IO *)P, (const IO *)Y, ldY, n, (IO *)om, ldO, 0u);
     return hipGetLastError();
 }
 
