@@ -131,6 +131,37 @@ int ak_eval_source(const ak_mechanism *mech, ak_precision prec, const void *T, c
                    void *stream);
 
 /*
+ * Dense Jacobian of the state source with respect to x = (Y_1..Y_NS, T) at
+ * fixed P, per cell: rows 0..NS-1 are d omega_k / dx (kmol m^-3 s^-1 per unit
+ * mass fraction, per K), row NS is d omega_T / dx with
+ * omega_T = -sum_k h_k omega_k / sum_k C_k cp_k (K/s) the constant-pressure
+ * temperature source (h_k molar enthalpy, cp_k molar heat capacity from the
+ * NASA-7 polynomials).  This is the matrix an implicit integrator of the
+ * paper's source term (Eq. 2) needs.  Output J is [n_cells][NS+1][NS+1],
+ * row-major per cell, cells outermost with stride ldJ >= (NS+1)^2 elements;
+ * float for AK_FP32, double for AK_FP64 (both evaluate in double).  Where
+ * Y_m < 0 the column of Y_m is zero (the clamp); at Y_m = 0 the one-sided
+ * derivative from above is returned.
+ * Errors: as ak_eval_source, plus AK_EINVAL for ldJ < (NS+1)^2 and
+ * AK_EUNSUPPORTED when (NS+1)^2 + 9 NS doubles exceed one workgroup's LDS
+ * (NS > ~140 on gfx950).
+ */
+int ak_eval_jacobian(const ak_mechanism *mech, ak_precision prec, const void *T, const void *P,
+                     const void *Y, int64_t ldY, int64_t n_cells, void *J, int64_t ldJ,
+                     void *stream);
+
+/*
+ * Vector-Jacobian product of omega (Eq. 2) with respect to (Y, T) at fixed P:
+ * given g_omega [NS][ldG], returns g_Y[m] = sum_k g_omega_k d omega_k / dY_m
+ * ([NS][ldGY]) and g_T = sum_k g_omega_k d omega_k / dT ([n_cells]), without
+ * forming the Jacobian.  Same clamp convention as ak_eval_jacobian.
+ * Errors: as ak_eval_source, plus AK_EINVAL for ldG or ldGY < n_cells.
+ */
+int ak_eval_vjp(const ak_mechanism *mech, ak_precision prec, const void *T, const void *P,
+                const void *Y, int64_t ldY, int64_t n_cells, const void *g_omega, int64_t ldG,
+                void *g_Y, int64_t ldGY, void *g_T, void *stream);
+
+/*
  * Read and reset the number of bad cells (non-finite input, T <= 0 or
  * P <= 0) seen by all evaluations with this mechanism since the last call.
  * Synchronises `stream`.  Errors: AK_EINVAL, AK_EDEVICE.

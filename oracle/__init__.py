@@ -79,6 +79,9 @@ def _lib_handle():
             getattr(lib, f"ora_jacobian_{sfx}").argtypes = [
                 C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                 C.c_void_p, C.c_int64, C.c_int]
+            getattr(lib, f"ora_jacobian_scaled_{sfx}").argtypes = [
+                C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                C.c_void_p, C.c_void_p, C.c_int64, C.c_int]
         _lib = lib
     return _lib
 
@@ -195,17 +198,20 @@ def temp_source(mech, T, P, Y, precision: str = "f64", n_threads: int = 0):
     return out
 
 
-def jacobian(mech, T, P, Y, precision: str = "f64", n_threads: int = 0):
-    """Analytic Jacobian [n, NS+1, NS+1] of (omega, omega_T) w.r.t. (Y, T)."""
+def jacobian(mech, T, P, Y, precision: str = "f64", scales: bool = False, n_threads: int = 0):
+    """Analytic Jacobian [n, NS+1, NS+1] of (omega, omega_T) w.r.t. (Y, T).
+    With ``scales`` also returns the gross scale of every entry (each
+    chain-rule term replaced by its absolute value)."""
     m = _as_mech(mech)
     dt = _dtype(precision)
     T, P, Y = _f64(T), _f64(P), _f64(Y)
     n = T.shape[0]
     nv = m.ns + 1
     J = np.zeros((n, nv, nv), dt)
-    rc = getattr(_lib_handle(), f"ora_jacobian_{precision}")(
-        m.ptr, n, T.ctypes.data, P.ctypes.data, Y.ctypes.data, n, J.ctypes.data, nv * nv,
-        int(n_threads))
+    Ja = np.zeros((n, nv, nv), dt) if scales else None
+    rc = getattr(_lib_handle(), f"ora_jacobian_scaled_{precision}")(
+        m.ptr, n, T.ctypes.data, P.ctypes.data, Y.ctypes.data, n, J.ctypes.data,
+        Ja.ctypes.data if scales else None, nv * nv, int(n_threads))
     if rc:
         raise RuntimeError("oracle jacobian failed")
-    return J
+    return (J, Ja) if scales else J

@@ -46,7 +46,10 @@ typedef struct {
     int ora_temp_source_##S(const ora_mech *m, int64_t n, const double *T, const double *P,  \
                             const double *Y, int64_t ldY, R *omega_T, int n_threads);          \
     int ora_jacobian_##S(const ora_mech *m, int64_t n, const double *T, const double *P,     \
-                         const double *Y, int64_t ldY, R *J, int64_t ldJ, int n_threads);
+                         const double *Y, int64_t ldY, R *J, int64_t ldJ, int n_threads);      \
+    int ora_jacobian_scaled_##S(const ora_mech *m, int64_t n, const double *T,                 \
+                                const double *P, const double *Y, int64_t ldY, R *J, R *Jabs,  \
+                                int64_t ldJ, int n_threads);
 
 ORA_DECL(double, f64)
 ORA_DECL(long double, ld)

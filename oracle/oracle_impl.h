@@ -221,6 +221,16 @@ int SFX(ora_temp_source)(const ora_mech *m, int64_t n, const double *T, const do
 int SFX(ora_jacobian)(const ora_mech *m, int64_t n, const double *T, const double *P,
                       const double *Y, int64_t ldY, REAL *J, int64_t ldJ, int n_threads)
 {
+    return SFX(ora_jacobian_scaled)(m, n, T, P, Y, ldY, J, 0, ldJ, n_threads);
+}
+
+/* As ora_jacobian, and (if Jabs is not NULL) the gross scale of every entry:
+ * the same chain-rule sums with every term replaced by its absolute value,
+ * the rounding-error scale for grading a Jacobian computed another way. */
+int SFX(ora_jacobian_scaled)(const ora_mech *m, int64_t n, const double *T, const double *P,
+                             const double *Y, int64_t ldY, REAL *J, REAL *Jabs, int64_t ldJ,
+                             int n_threads)
+{
     const int ns = m->ns, nr = m->nr, nv = ns + 1;
     int err = 0;
 #ifdef _OPENMP
@@ -228,7 +238,7 @@ int SFX(ora_jacobian)(const ora_mech *m, int64_t n, const double *T, const doubl
 #pragma omp parallel
 #endif
     {
-        REAL *buf = (REAL *)malloc(sizeof(REAL) * (8 * ns + 2 * ns * nv + nv * nv));
+        REAL *buf = (REAL *)malloc(sizeof(REAL) * (9 * ns + 2 * ns * nv + 2 * nv * nv));
         if (!buf) {
             err = -1;
         } else {
@@ -236,8 +246,8 @@ int SFX(ora_jacobian)(const ora_mech *m, int64_t n, const double *T, const doubl
                  *om = dcp + ns, *dqdC = om + ns;     /* dqdC: [ns] per reaction */
             REAL *dCdx = dqdC + ns;                   /* [ns][nv] */
             REAL *Jc = dCdx + ns * nv;                /* [nv][nv] */
-            REAL *rowtmp = Jc + nv * nv;              /* [ns][nv] scratch (unused rows) */
-            (void)rowtmp;
+            REAL *Ja = Jc + nv * nv;                  /* [nv][nv] gross scale */
+            REAL *dqdCa = Ja + nv * nv;               /* [ns] |dq_f/dC| + |dq_r/dC| */
 #ifdef _OPENMP
 #pragma omp for schedule(static)
 #endif
@@ -258,7 +268,7 @@ int SFX(ora_jacobian)(const ora_mech *m, int64_t n, const double *T, const doubl
                     }
                     dCdx[l * nv + ns] = -C[l] / Ti;
                 }
-                for (int a = 0; a < nv * nv; ++a) Jc[a] = 0;
+                for (int a = 0; a < nv * nv; ++a) Jc[a] = Ja[a] = 0;
                 for (int j = 0; j < nr; ++j) {
                     REAL kf, Kc, qf, qr;
                     SFX(reaction1)(m, j, Ti, C, h, s, &kf, &Kc, &qf, &qr);
@@ -276,22 +286,26 @@ int SFX(ora_jacobian)(const ora_mech *m, int64_t n, const double *T, const doubl
                     REAL dlnKc = (dH - dn) / Ti;
                     /* explicit temperature dependence at fixed C */
                     REAL dqdT = qf * dlnkf - (rev ? qr * (dlnkf - dlnKc) : 0);
+                    REAL dqdTa = FABS(qf * dlnkf) + (rev ? FABS(qr * (dlnkf - dlnKc)) : 0);
                     /* dq/dC_l, product rule on each power */
                     for (int l = 0; l < ns; ++l) {
-                        REAL d = 0;
+                        REAL d = 0, da = 0;
                         if (nf[l]) {
                             REAL p = kf * (REAL)nf[l] * SFX(ipow)(C[l], nf[l] - 1);
                             for (int mm = 0; mm < ns; ++mm)
                                 if (mm != l && nf[mm]) p *= SFX(ipow)(C[mm], nf[mm]);
                             d += p;
+                            da += FABS(p);
                         }
                         if (nrr[l] && rev) {
                             REAL p = kr * (REAL)nrr[l] * SFX(ipow)(C[l], nrr[l] - 1);
                             for (int mm = 0; mm < ns; ++mm)
                                 if (mm != l && nrr[mm]) p *= SFX(ipow)(C[mm], nrr[mm]);
                             d -= p;
+                            da += FABS(p);
                         }
                         dqdC[l] = d;
+                        dqdCa[l] = da;
                     }
                     REAL qn = qf - qr;
                     for (int k = 0; k < ns; ++k) {
@@ -300,9 +314,13 @@ int SFX(ora_jacobian)(const ora_mech *m, int64_t n, const double *T, const doubl
                         om[k] += nu * qn;
                         for (int c = 0; c < nv; ++c) {
                             REAL g = (c == ns) ? dqdT : 0;
-                            for (int l = 0; l < ns; ++l)
+                            REAL ga = (c == ns) ? dqdTa : 0;
+                            for (int l = 0; l < ns; ++l) {
                                 if (dqdC[l] != 0) g += dqdC[l] * dCdx[l * nv + c];
+                                if (dqdCa[l] != 0) ga += dqdCa[l] * FABS(dCdx[l * nv + c]);
+                            }
                             Jc[k * nv + c] += nu * g;
+                            Ja[k * nv + c] += FABS((REAL)nu) * ga;
                         }
                     }
                 }
@@ -313,21 +331,30 @@ int SFX(ora_jacobian)(const ora_mech *m, int64_t n, const double *T, const doubl
                     den += C[k] * (REAL)ORA_RU * cp[k];
                 }
                 for (int c = 0; c < nv; ++c) {
-                    REAL dnum = 0, dden = 0;
+                    REAL dnum = 0, dden = 0, dnuma = 0, ddena = 0;
                     for (int k = 0; k < ns; ++k) {
                         dnum += (REAL)ORA_RU * Ti * h[k] * Jc[k * nv + c];
                         dden += (REAL)ORA_RU * cp[k] * dCdx[k * nv + c];
+                        dnuma += FABS((REAL)ORA_RU * Ti * h[k]) * Ja[k * nv + c];
+                        ddena += FABS((REAL)ORA_RU * cp[k] * dCdx[k * nv + c]);
                     }
                     if (c == ns) {
                         for (int k = 0; k < ns; ++k) {
                             dnum += (REAL)ORA_RU * cp[k] * om[k];   /* d h_k/dT = cp_k */
                             dden += C[k] * (REAL)ORA_RU * dcp[k];
+                            dnuma += FABS((REAL)ORA_RU * cp[k] * om[k]);
+                            ddena += FABS(C[k] * (REAL)ORA_RU * dcp[k]);
                         }
                     }
                     Jc[ns * nv + c] = -(dnum * den - num * dden) / (den * den);
+                    Ja[ns * nv + c] = (dnuma * FABS(den) + FABS(num) * ddena) / (den * den);
                 }
                 REAL *Jo = &J[i * ldJ];
                 for (int a = 0; a < nv * nv; ++a) Jo[a] = Jc[a];
+                if (Jabs) {
+                    REAL *Jao = &Jabs[i * ldJ];
+                    for (int a = 0; a < nv * nv; ++a) Jao[a] = Ja[a];
+                }
             }
             free(buf);
         }

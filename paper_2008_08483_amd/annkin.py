@@ -61,6 +61,11 @@ def lib():
         h.ak_eval_source.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
         h.ak_error_count.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]
+        h.ak_eval_jacobian.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+        h.ak_eval_vjp.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.c_int64, C.c_void_p, C.c_void_p]
         _lib = h
     return _lib
 
@@ -176,3 +181,78 @@ def eval_source(mech: Mechanism, T, P, Y, out=None, stream=None):
     _check(lib().ak_eval_source(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
                                 Y.data_ptr(), ldY, n, out.data_ptr(), ldO, _stream_ptr(stream)))
     return out
+
+
+def eval_jacobian(mech: Mechanism, T, P, Y, out=None, stream=None):
+    """Dense Jacobian [n, NS+1, NS+1] of (omega, omega_T) with respect to
+    (Y_1..Y_NS, T) at fixed P (row-major per cell).  Asynchronous."""
+    torch = _torch()
+    n = _check_state(mech, T, P, Y)
+    nv = mech.n_species + 1
+    if out is None:
+        out = torch.empty((n, nv, nv), dtype=T.dtype, device=T.device)
+    elif (out.shape != (n, nv, nv) or out.dtype != T.dtype or not out.is_cuda
+          or out.stride(2) != 1 or out.stride(1) != nv):
+        raise ValueError("out must be a GPU [n, NS+1, NS+1] tensor, rows contiguous")
+    ldY = Y.stride(0) if mech.n_species > 1 else n
+    ldJ = out.stride(0) if n > 1 else nv * nv
+    _check(lib().ak_eval_jacobian(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
+                                  Y.data_ptr(), ldY, n, out.data_ptr(), ldJ,
+                                  _stream_ptr(stream)))
+    return out
+
+
+def eval_vjp(mech: Mechanism, T, P, Y, g_omega, stream=None):
+    """(g_Y [NS, n], g_T [n]) = (g_omega^T d omega/dY, g_omega^T d omega/dT)."""
+    torch = _torch()
+    n = _check_state(mech, T, P, Y)
+    if (g_omega.shape != (mech.n_species, n) or g_omega.dtype != T.dtype
+            or not g_omega.is_cuda or g_omega.stride(1) != 1):
+        raise ValueError("g_omega must be a GPU [NS, n] tensor of the state dtype")
+    gY = torch.empty((mech.n_species, n), dtype=T.dtype, device=T.device)
+    gT = torch.empty((n,), dtype=T.dtype, device=T.device)
+    ldY = Y.stride(0) if mech.n_species > 1 else n
+    ldG = g_omega.stride(0) if mech.n_species > 1 else n
+    _check(lib().ak_eval_vjp(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
+                             Y.data_ptr(), ldY, n, g_omega.data_ptr(), ldG, gY.data_ptr(),
+                             n, gT.data_ptr(), _stream_ptr(stream)))
+    return gY, gT
+
+
+def _source_function():
+    torch = _torch()
+
+    class SourceTerm(torch.autograd.Function):
+        """omega(T, P, Y), differentiable in T and Y through the library's
+        hand-written VJP kernel (P is treated as a constant)."""
+
+        @staticmethod
+        def forward(ctx, mech, T, P, Y):
+            Tc, Pc, Yc = T.contiguous(), P.contiguous(), Y.contiguous()
+            ctx.mech = mech
+            ctx.save_for_backward(Tc, Pc, Yc)
+            return eval_source(mech, Tc, Pc, Yc)
+
+        @staticmethod
+        def backward(ctx, g):
+            T, P, Y = ctx.saved_tensors
+            gY, gT = eval_vjp(ctx.mech, T, P, Y, g.contiguous())
+            return None, gT, None, gY
+
+    return SourceTerm
+
+
+_SOURCE_FN = None
+
+
+def source_term(mech: Mechanism, T, P, Y):
+    """Differentiable omega (see SourceTerm)."""
+    global _SOURCE_FN
+    if _SOURCE_FN is None:
+        _SOURCE_FN = _source_function()
+    return _SOURCE_FN.apply(mech, T, P, Y)
+
+
+def jacobian(mech: Mechanism, T, P, Y):
+    """Alias of eval_jacobian."""
+    return eval_jacobian(mech, T, P, Y)

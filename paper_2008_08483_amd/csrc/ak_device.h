@@ -49,10 +49,29 @@ struct ShapeRun {
     int32_t nf, nr, start, count;
 };
 
+// NASA-7 coefficients a1..a7 per species and range (112 B), for enthalpy
+// and heat capacity in the derivative kernels.
+struct ThermoRec {
+    double lo[7];
+    double hi[7];
+};
+
+// Per reaction, in the same shape-sorted order as RxnRec (32 B): species of
+// the molecule slots (reactants first), molecule counts, and E/R.
+struct RxnAux {
+    uint16_t sp[8];
+    uint8_t nf, nr;
+    uint8_t pad[6];
+    double EoR;        // E/R, K
+};
+static_assert(sizeof(RxnAux) == 32, "RxnAux layout");
+
 // Kernel argument view of a loaded mechanism.
 struct MechView {
     const SpeciesRec *sp;
     const RxnRec *rx;
+    const ThermoRec *th;
+    const RxnAux *aux;
     unsigned long long *err;     // bad-cell counter
     int32_t ns, nr, nruns;
     int32_t tile;                // cells per workgroup tile (<= 64)

@@ -10,6 +10,9 @@ struct ak_mechanism {
     int device = 0;
     int ns = 0, nr = 0;
     ak::MechView view{};
+    unsigned char *dev = nullptr;        // single device allocation for all tables
+    int lds_max = 0;                     // LDS bytes per workgroup on the device
+    int vjp_tile = 0;                    // cells per VJP workgroup tile
     std::vector<ak::SpeciesRec> host_species;
     std::vector<ak::RxnRec> host_rxn;   // shape-sorted order
     std::vector<int> rxn_order;         // file index of each sorted reaction
@@ -33,5 +36,14 @@ size_t source_lds_bytes(int ns, int tile);
 hipError_t source_launch(const MechView &m, bool f64, const void *T, const void *P,
                          const void *Y, int64_t ldY, int64_t n, void *om, int64_t ldO,
                          hipStream_t st);
+
+size_t jacobian_lds_bytes(int ns);
+hipError_t jacobian_launch(const MechView &m, int lds_max, bool f64, const void *T, const void *P,
+                           const void *Y, int64_t ldY, int64_t n, void *J, int64_t ldJ,
+                           hipStream_t st);
+int vjp_tile(int ns, int lds_max);
+hipError_t vjp_launch(const MechView &m, int tile, bool f64, const void *T, const void *P,
+                      const void *Y, int64_t ldY, int64_t n, const void *G, int64_t ldG,
+                      void *GY, int64_t ldGY, void *GT, hipStream_t st);
 
 }  // namespace ak

@@ -125,6 +125,7 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     const uint32_t sstride = species_stride(tile);
 
     std::vector<RxnRec> rx(nr);
+    std::vector<RxnAux> aux(nr);
     std::vector<int> shape(nr);
     for (int j = 0; j < nr; ++j) {
         RxnRec &r = rx[j];
@@ -152,12 +153,26 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
         r.negEoR2 = -(d->Ea[j] * kCal / kRuMol) * kLog2e;
         r.rev = (d->reversible == nullptr || d->reversible[j]) ? 1.0 : 0.0;
         shape[j] = (nf - 1) * kMaxSide + (np - 1);
+        RxnAux &x = aux[j];
+        std::memset(&x, 0, sizeof x);
+        for (int t = 0; t < nf; ++t) x.sp[t] = (uint16_t)(reac[t] / sstride);
+        for (int t = 0; t < np; ++t) x.sp[nf + t] = (uint16_t)(prod[t] / sstride);
+        x.nf = (uint8_t)nf;
+        x.nr = (uint8_t)np;
+        x.EoR = d->Ea[j] * kCal / kRuMol;
     }
     // sort reactions by shape so each wave runs a uniform code path per run
     std::vector<int> order(nr);
     for (int j = 0; j < nr; ++j) order[j] = j;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return shape[a] < shape[b]; });
     std::vector<RxnRec> rxs(nr);
+    std::vector<RxnAux> auxs(nr);
+    std::vector<ThermoRec> th(ns);
+    for (int k = 0; k < ns; ++k)
+        for (int c = 0; c < 7; ++c) {
+            th[k].lo[c] = d->nasa_low[7 * k + c];
+            th[k].hi[c] = d->nasa_high[7 * k + c];
+        }
     MechView view;
     std::memset(&view, 0, sizeof view);
     view.ns = ns;
@@ -166,6 +181,7 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     std::vector<int> rxn_order(order);
     for (int i = 0; i < nr; ++i) {
         rxs[i] = rx[order[i]];
+        auxs[i] = aux[order[i]];
         const int s = shape[order[i]];
         if (view.nruns == 0 || (view.runs[view.nruns - 1].nf - 1) * kMaxSide +
                                        (view.runs[view.nruns - 1].nr - 1) != s) {
@@ -183,32 +199,38 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     m->device = device;
     m->ns = ns;
     m->nr = nr;
+    m->lds_max = lds_max;
+    m->vjp_tile = vjp_tile(ns, lds_max);
     hipError_t e;
-    void *psp = nullptr, *prx = nullptr, *perr = nullptr;
-    if ((e = hipMalloc(&psp, sizeof(SpeciesRec) * ns)) != hipSuccess ||
-        (e = hipMalloc(&prx, sizeof(RxnRec) * nr)) != hipSuccess ||
-        (e = hipMalloc(&perr, sizeof(unsigned long long))) != hipSuccess) {
-        if (psp) (void)hipFree(psp);
-        if (prx) (void)hipFree(prx);
+    // one device allocation holds every table
+    const size_t o_sp = 0;
+    const size_t o_rx = o_sp + ((sizeof(SpeciesRec) * ns + 255) & ~(size_t)255);
+    const size_t o_th = o_rx + ((sizeof(RxnRec) * nr + 255) & ~(size_t)255);
+    const size_t o_aux = o_th + ((sizeof(ThermoRec) * ns + 255) & ~(size_t)255);
+    const size_t o_err = o_aux + ((sizeof(RxnAux) * nr + 255) & ~(size_t)255);
+    const size_t bytes = o_err + 256;
+    std::vector<unsigned char> host(bytes, 0);
+    std::memcpy(&host[o_sp], sp.data(), sizeof(SpeciesRec) * ns);
+    std::memcpy(&host[o_rx], rxs.data(), sizeof(RxnRec) * nr);
+    std::memcpy(&host[o_th], th.data(), sizeof(ThermoRec) * ns);
+    std::memcpy(&host[o_aux], auxs.data(), sizeof(RxnAux) * nr);
+    unsigned char *dev = nullptr;
+    if ((e = hipMalloc((void **)&dev, bytes)) != hipSuccess) {
         delete m;
         return set_error(AK_ENOMEM, "ak_load_mechanism: device allocation failed: %s",
                          hipGetErrorString(e));
     }
-    unsigned long long zero = 0;
-    if ((e = hipMemcpy(psp, sp.data(), sizeof(SpeciesRec) * ns, hipMemcpyHostToDevice)) !=
-            hipSuccess ||
-        (e = hipMemcpy(prx, rxs.data(), sizeof(RxnRec) * nr, hipMemcpyHostToDevice)) !=
-            hipSuccess ||
-        (e = hipMemcpy(perr, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) {
-        (void)hipFree(psp);
-        (void)hipFree(prx);
-        (void)hipFree(perr);
+    if ((e = hipMemcpy(dev, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(dev);
         delete m;
         return hip_error(e, "ak_load_mechanism: upload");
     }
-    view.sp = (const SpeciesRec *)psp;
-    view.rx = (const RxnRec *)prx;
-    view.err = (unsigned long long *)perr;
+    m->dev = dev;
+    view.sp = (const SpeciesRec *)(dev + o_sp);
+    view.rx = (const RxnRec *)(dev + o_rx);
+    view.th = (const ThermoRec *)(dev + o_th);
+    view.aux = (const RxnAux *)(dev + o_aux);
+    view.err = (unsigned long long *)(dev + o_err);
     m->view = view;
     m->host_species = std::move(sp);
     m->host_rxn = std::move(rxs);
@@ -221,9 +243,7 @@ int ak_free_mechanism(ak_mechanism *m)
 {
     if (!m) return AK_OK;
     DeviceGuard g(m->device);
-    (void)hipFree((void *)m->view.sp);
-    (void)hipFree((void *)m->view.rx);
-    (void)hipFree((void *)m->view.err);
+    (void)hipFree(m->dev);
     delete m;
     return AK_OK;
 }
@@ -249,6 +269,63 @@ int ak_eval_source(const ak_mechanism *m, ak_precision prec, const void *T, cons
     hipError_t e = source_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, omega, ldO,
                                  (hipStream_t)stream);
     if (e != hipSuccess) return hip_error(e, "ak_eval_source: launch");
+    return AK_OK;
+}
+
+static int check_state(const char *fn, const ak_mechanism *m, ak_precision prec, const void *T,
+                       const void *P, const void *Y, int64_t ldY, int64_t n)
+{
+    if (!m) return set_error(AK_EINVAL, "%s: null mechanism", fn);
+    if (prec != AK_FP32 && prec != AK_FP64)
+        return set_error(AK_EINVAL, "%s: bad precision %d", fn, (int)prec);
+    if (n < 0) return set_error(AK_EINVAL, "%s: n_cells < 0", fn);
+    if (n > 0 && (!T || !P || !Y)) return set_error(AK_EINVAL, "%s: null state pointer", fn);
+    if (n > 0 && ldY < n)
+        return set_error(AK_EINVAL, "%s: ldY=%lld < n_cells=%lld", fn, (long long)ldY,
+                         (long long)n);
+    if (n > (int64_t)1 << 40) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
+    return AK_OK;
+}
+
+int ak_eval_jacobian(const ak_mechanism *m, ak_precision prec, const void *T, const void *P,
+                     const void *Y, int64_t ldY, int64_t n, void *J, int64_t ldJ, void *stream)
+{
+    int rc = check_state("ak_eval_jacobian", m, prec, T, P, Y, ldY, n);
+    if (rc) return rc;
+    if (n == 0) return AK_OK;
+    const int64_t nv = (int64_t)m->ns + 1;
+    if (!J) return set_error(AK_EINVAL, "ak_eval_jacobian: null J");
+    if (ldJ < nv * nv)
+        return set_error(AK_EINVAL, "ak_eval_jacobian: ldJ=%lld < (NS+1)^2=%lld", (long long)ldJ,
+                         (long long)(nv * nv));
+    if (jacobian_lds_bytes(m->ns) > (size_t)m->lds_max)
+        return set_error(AK_EUNSUPPORTED, "ak_eval_jacobian: %d species exceed the LDS", m->ns);
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "ak_eval_jacobian: cannot select device %d", m->device);
+    hipError_t e = jacobian_launch(m->view, m->lds_max, prec == AK_FP64, T, P, Y, ldY, n, J, ldJ,
+                                   (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "ak_eval_jacobian: launch");
+    return AK_OK;
+}
+
+int ak_eval_vjp(const ak_mechanism *m, ak_precision prec, const void *T, const void *P,
+                const void *Y, int64_t ldY, int64_t n, const void *g_omega, int64_t ldG,
+                void *g_Y, int64_t ldGY, void *g_T, void *stream)
+{
+    int rc = check_state("ak_eval_vjp", m, prec, T, P, Y, ldY, n);
+    if (rc) return rc;
+    if (n == 0) return AK_OK;
+    if (!g_omega || !g_Y || !g_T) return set_error(AK_EINVAL, "ak_eval_vjp: null pointer");
+    if (ldG < n || ldGY < n)
+        return set_error(AK_EINVAL, "ak_eval_vjp: ldG=%lld ldGY=%lld < n_cells=%lld",
+                         (long long)ldG, (long long)ldGY, (long long)n);
+    if (m->vjp_tile < 16)
+        return set_error(AK_EUNSUPPORTED, "ak_eval_vjp: %d species exceed the LDS", m->ns);
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "ak_eval_vjp: cannot select device %d", m->device);
+    hipError_t e = vjp_launch(m->view, m->vjp_tile, prec == AK_FP64, T, P, Y, ldY, n, g_omega,
+                              ldG, g_Y, ldGY, g_T, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "ak_eval_vjp: launch");
     return AK_OK;
 }
 

@@ -1,0 +1,436 @@
+// Derivatives of the source term on gfx950: the dense state Jacobian and the
+// vector-Jacobian product (VJP), both in double precision internally.
+//
+// State x = (Y_1..Y_NS, T) at fixed P; outputs omega_k (Eq. 2) and the
+// constant-pressure temperature source omega_T = -sum_k h_k omega_k /
+// sum_k C_k cp_k.  With a_k = C_k exp(Gt_k), v_k = exp(-Gt_k), w_k = 1/v_k
+// (Gt the Gibbs-layer output, Eqs. 10-11) and E_j = k_f,j prod_reac v:
+//     q_f = E prod_reac a,   q_r = rev E prod_prod a        (Eqs. 3-4, 7)
+//     dq_f/dC_m = E w_m sum_{slots i of m} prod_{l != i} a_l    (same for q_r)
+//     dC_l/dY_m = [Y_m >= 0] (delta_lm rho/W_m - C_l/(sigma W_m)),  dC_l/dT = -C_l/T
+// so that, using the homogeneity sum_l C_l dq_f/dC_l = n_f q_f,
+//     d omega_k/dY_m = [Y_m >= 0] (rho G_km - u_k/sigma) / W_m,
+//     G_km = sum_j nu_kj dq_j/dC_m,  u_k = sum_j nu_kj (n_f q_f - n_r q_r)_j,
+//     d omega_k/dT = sum_j nu_kj (dq_j/dT|_C - (n_f q_f - n_r q_r)_j / T),
+//     d ln k_f/dT = (beta + E/RT)/T,  d ln K_c/dT = (dH/RT - dn)/T.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ak_device.h"
+
+namespace ak {
+
+
+__device__ __forceinline__ void lds_addd(double *p, double x)
+{
+    __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+struct Thermo1 {
+    double h, cp, dcp;   // h/RT, cp/R, d(cp/R)/dT
+};
+
+__device__ __forceinline__ Thermo1 nasa(const ThermoRec &t, double T, double T_mid)
+{
+    const double *a = (T >= T_mid) ? t.hi : t.lo;
+    const double T2 = T * T, T3 = T2 * T, T4 = T3 * T;
+    Thermo1 r;
+    r.h = a[0] + a[1] * T / 2 + a[2] * T2 / 3 + a[3] * T3 / 4 + a[4] * T4 / 5 + a[5] / T;
+    r.cp = a[0] + a[1] * T + a[2] * T2 + a[3] * T3 + a[4] * T4;
+    r.dcp = a[1] + 2 * a[2] * T + 3 * a[3] * T2 + 4 * a[4] * T3;
+    return r;
+}
+
+__device__ __forceinline__ double gibbs2(const SpeciesRec &s, double lnT, double T, double T2,
+                                         double T3, double T4, double invT)
+{
+    const double *c = (T >= s.T_mid) ? s.hi : s.lo;
+    return c[0] * lnT + c[1] * T + c[2] * T2 + c[3] * T3 + c[4] * T4 + c[5] * invT + c[6];
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian: one wave per cell, lane = reaction.
+//
+// LDS per wave (doubles): J[(ns+1)^2] then per species C, a, v, w, h, cp, dcp,
+// omega, u.  J holds G_km (and d omega_k/dT in the last column) during the
+// reaction sweep and the finished Jacobian afterwards.
+template <typename IO, int kJacWaves>
+__global__ __launch_bounds__(64 * kJacWaves) void jacobian_kernel(MechView m,
+                                                                  const IO *__restrict__ Tin,
+                                                                  const IO *__restrict__ Pin,
+                                                                  const IO *__restrict__ Y,
+                                                                  int64_t ldY, int64_t n,
+                                                                  IO *__restrict__ Jout,
+                                                                  int64_t ldJ)
+{
+    extern __shared__ __attribute__((aligned(16))) double jl[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int ns = m.ns, nv = ns + 1;
+    const int per_wave = nv * nv + 9 * ns;
+    double *Jw = jl + (size_t)wave * per_wave;
+    double *sC = Jw + nv * nv, *sa = sC + ns, *sv = sa + ns, *sw = sv + ns, *sh = sw + ns,
+           *scp = sh + ns, *sdcp = scp + ns, *som = sdcp + ns, *su = som + ns;
+    const int64_t cell = (int64_t)blockIdx.x * kJacWaves + wave;
+    const bool valid = cell < n;
+
+    double T = valid ? (double)Tin[cell] : 1000.0;
+    double P = valid ? (double)Pin[cell] : 1.0e5;
+    bool bad = !(T > 0.0) || !(P > 0.0) || !__builtin_isfinite(T) || !__builtin_isfinite(P);
+    // mixture sum (lane = species)
+    double ysum = 0.0;
+    bool ybad = false;
+    for (int k = lane; k < ns; k += 64) {
+        const double y = valid ? (double)Y[k * ldY + cell] : 1.0;
+        ybad |= !__builtin_isfinite(y);
+        ysum += __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
+    }
+    double sigma = wave_sum(ysum);
+    bad |= __any(ybad) || !(sigma > 0.0) || !__builtin_isfinite(sigma);
+    if (bad) {
+        T = 1000.0;
+        P = 1.0e5;
+        sigma = 1.0;
+    }
+    const double lnT = log(T), invT = 1.0 / T, T2 = T * T, T3 = T2 * T, T4 = T3 * T;
+    const double rho = P / (kRu * T * sigma);
+    for (int k = lane; k < ns; k += 64) {
+        const SpeciesRec &s = m.sp[k];
+        const double y = bad ? 0.0 : __builtin_fmax(valid ? (double)Y[k * ldY + cell] : 1.0, 0.0);
+        const double C = rho * y * s.inv_W;
+        const double g2 = gibbs2(s, lnT, T, T2, T3, T4, invT);
+        const double w = exp2(g2), v = exp2(-g2);
+        const Thermo1 th = nasa(m.th[k], T, s.T_mid);
+        sC[k] = C;
+        sa[k] = C * w;
+        sv[k] = v;
+        sw[k] = w;
+        sh[k] = th.h;
+        scp[k] = th.cp;
+        sdcp[k] = th.dcp;
+        som[k] = 0.0;
+        su[k] = 0.0;
+    }
+    for (int i = lane; i < nv * nv; i += 64) Jw[i] = 0.0;
+    __syncthreads();
+
+    const double log2T = lnT * kLog2e;
+    for (int j0 = 0; j0 < m.nr; j0 += 64) {
+        const int j = j0 + lane;
+        if (j < m.nr) {
+            const RxnRec R = m.rx[j];
+            const RxnAux X = m.aux[j];
+            const int nf = X.nf, nr = X.nr, nm = nf + nr;
+            const double kf = exp2(__builtin_fma(R.beta, log2T, __builtin_fma(R.negEoR2, invT, R.log2A)));
+            double a[8], Ar = 1.0, Ap = 1.0, E = kf, dH = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (i < nm) {
+                    const int s = X.sp[i];
+                    a[i] = sa[s];
+                    if (i < nf) {
+                        Ar *= a[i];
+                        E *= sv[s];
+                        dH -= sh[s];
+                    } else {
+                        Ap *= a[i];
+                        dH += sh[s];
+                    }
+                }
+            }
+            const double qf = E * Ar, qr = R.rev * E * Ap;
+            const double dlnkf = (R.beta + X.EoR * invT) * invT;
+            const double dn = (double)(nr - nf);
+            const double dqT = qf * (dlnkf - nf * invT) - qr * (dlnkf - (dH - dn) * invT - nr * invT);
+            const double wu = nf * qf - nr * qr;
+            const double qn = qf - qr;
+            // d q_net / dC at each molecule slot (leave-one-out products)
+            double dq[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (i < nm) {
+                    double loo = 1.0;
+                    const bool reac = i < nf;
+#pragma unroll
+                    for (int l = 0; l < 8; ++l)
+                        if (l != i && l < nm && ((l < nf) == reac)) loo *= a[l];
+                    const double base = E * sw[X.sp[i]] * loo;
+                    dq[i] = reac ? base : -R.rev * base;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                if (r < nm) {
+                    const int k = X.sp[r];
+                    const double sg = r < nf ? -1.0 : 1.0;
+                    lds_addd(&som[k], sg * qn);
+                    lds_addd(&su[k], sg * wu);
+                    lds_addd(&Jw[k * nv + ns], sg * dqT);
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        if (c < nm) lds_addd(&Jw[k * nv + X.sp[c]], sg * dq[c]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // assembly of the composition columns (the temperature column already
+    // holds the full d omega_k/dT: dq/dT above includes -(n_f q_f - n_r q_r)/T)
+    const double inv_sigma = 1.0 / sigma;
+    for (int i = lane; i < ns * nv; i += 64) {
+        const int k = i / nv, c = i - k * nv;
+        if (c < ns) {
+            const double ycl = (valid ? (double)Y[c * ldY + cell] : 1.0) >= 0.0 ? 1.0 : 0.0;
+            Jw[i] = ycl * (rho * Jw[i] - su[k] * inv_sigma) * m.sp[c].inv_W;
+        }
+    }
+    // temperature row
+    double num = 0.0, den = 0.0, omcp = 0.0, cdcp = 0.0;
+    for (int k = lane; k < ns; k += 64) {
+        num += kRu * T * sh[k] * som[k];
+        den += sC[k] * kRu * scp[k];
+        omcp += kRu * scp[k] * som[k];
+        cdcp += sC[k] * kRu * sdcp[k];
+    }
+    num = wave_sum(num);
+    den = wave_sum(den);
+    omcp = wave_sum(omcp);
+    cdcp = wave_sum(cdcp);
+    __syncthreads();
+    for (int c = lane; c < nv; c += 64) {
+        double dnum = 0.0;
+        for (int k = 0; k < ns; ++k) dnum += kRu * T * sh[k] * Jw[k * nv + c];
+        double dden;
+        if (c < ns) {
+            const double ycl = (valid ? (double)Y[c * ldY + cell] : 1.0) >= 0.0 ? 1.0 : 0.0;
+            dden = ycl * (kRu * scp[c] * rho - den * inv_sigma) * m.sp[c].inv_W;
+        } else {
+            dnum += omcp;
+            dden = -den * invT + cdcp;
+        }
+        Jw[ns * nv + c] = -(dnum * den - num * dden) / (den * den);
+    }
+    __syncthreads();
+    if (valid) {
+        const IO nan = __builtin_nan("");
+        IO *o = Jout + cell * ldJ;
+        for (int i = lane; i < nv * nv; i += 64) o[i] = bad ? nan : (IO)Jw[i];
+        if (lane == 0 && bad) atomicAdd(m.err, 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// VJP: lane = cell, tile of m.tile cells shared by the workgroup's waves.
+// LDS entry per (species, cell), 40 B: a, v, omega_bar, h/RT, a_bar.
+constexpr int kVjpEntry = 40;
+constexpr int kVjpWaves = 8;
+
+template <typename IO>
+__global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int tile,
+                                                             const IO *__restrict__ Tin,
+                                                             const IO *__restrict__ Pin,
+                                                             const IO *__restrict__ Y,
+                                                             int64_t ldY, int64_t n,
+                                                             const IO *__restrict__ G,
+                                                             int64_t ldG, IO *__restrict__ GY,
+                                                             int64_t ldGY, IO *__restrict__ GT)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char vl[];
+    __shared__ double partial[kVjpWaves][2][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool active = lane < tile;
+    const int64_t cell = (int64_t)blockIdx.x * tile + lane;
+    const bool valid = active && cell < n;
+    const uint32_t sstride = (uint32_t)tile * kVjpEntry;
+    const uint32_t lane_off = active ? (uint32_t)lane * kVjpEntry : 0u;
+    auto E = [&](int k) { return (double *)(vl + (uint32_t)k * sstride + lane_off); };
+
+    double T = valid ? (double)Tin[cell] : 1000.0;
+    double P = valid ? (double)Pin[cell] : 1.0e5;
+    // mixture sum: every wave, same order
+    double sigma = 0.0;
+    bool bad = !(T > 0.0) || !(P > 0.0) || !__builtin_isfinite(T) || !__builtin_isfinite(P);
+    for (int k = 0; k < m.ns; ++k) {
+        const double y = valid ? (double)Y[k * ldY + cell] : 1.0;
+        bad |= !__builtin_isfinite(y);
+        sigma += __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
+    }
+    bad |= !(sigma > 0.0);
+    if (bad) {
+        T = 1000.0;
+        P = 1.0e5;
+        sigma = 1.0;
+    }
+    const double lnT = log(T), invT = 1.0 / T, T2 = T * T, T3 = T2 * T, T4 = T3 * T;
+    const double rho = P / (kRu * T * sigma);
+    for (int k = wave; k < m.ns; k += kVjpWaves) {
+        const SpeciesRec &s = m.sp[k];
+        const double y = bad ? 0.0 : __builtin_fmax(valid ? (double)Y[k * ldY + cell] : 1.0, 0.0);
+        const double g2 = gibbs2(s, lnT, T, T2, T3, T4, invT);
+        const Thermo1 th = nasa(m.th[k], T, s.T_mid);
+        if (active) {
+            double *e = E(k);
+            e[0] = rho * y * s.inv_W * exp2(g2);
+            e[1] = exp2(-g2);
+            e[2] = valid ? (double)G[k * ldG + cell] : 0.0;
+            e[3] = th.h;
+            e[4] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    // reverse sweep over reactions (this wave: every kVjpWaves-th reaction)
+    const double log2T = lnT * kLog2e;
+    double s_acc = 0.0, tbar = 0.0;
+    for (int j = wave; j < m.nr; j += kVjpWaves) {
+        const RxnRec &R = m.rx[j];
+        const RxnAux &X = m.aux[j];
+        const int nf = X.nf, nm = X.nf + X.nr;
+        const double kf = exp2(__builtin_fma(R.beta, log2T, __builtin_fma(R.negEoR2, invT, R.log2A)));
+        double a[8], Ar = 1.0, Ap = 1.0, Ek = kf, dH = 0.0, qbar = 0.0;
+        for (int i = 0; i < nm; ++i) {
+            const double *e = E(X.sp[i]);
+            a[i] = e[0];
+            if (i < nf) {
+                Ar *= a[i];
+                Ek *= e[1];
+                dH -= e[3];
+                qbar -= e[2];
+            } else {
+                Ap *= a[i];
+                dH += e[3];
+                qbar += e[2];
+            }
+        }
+        const double qf = Ek * Ar, qr = R.rev * Ek * Ap;
+        const int nr = nm - nf;
+        const double dlnkf = (R.beta + X.EoR * invT) * invT;
+        const double dqT = qf * (dlnkf - nf * invT) - qr * (dlnkf - (dH - (double)(nr - nf)) * invT - nr * invT);
+        s_acc += qbar * (nf * qf - nr * qr);
+        tbar += qbar * dqT;
+        for (int i = 0; i < nm; ++i) {
+            double loo = 1.0;
+            const bool reac = i < nf;
+            for (int l = 0; l < nm; ++l)
+                if (l != i && ((l < nf) == reac)) loo *= a[l];
+            const double d = reac ? Ek * loo : -R.rev * Ek * loo;   // d q / d a_slot
+            if (active) lds_addd(E(X.sp[i]) + 4, qbar * d);
+        }
+    }
+    if (active) {
+        partial[wave][0][lane] = s_acc;
+        partial[wave][1][lane] = tbar;
+    }
+    __syncthreads();
+    double s_tot = 0.0, t_tot = 0.0;   // s = sum_j q_bar_j (n_f q_f - n_r q_r)_j
+    for (int w = 0; w < kVjpWaves; ++w) {
+        s_tot += partial[w][0][lane];
+        t_tot += partial[w][1][lane];
+    }
+    const IO nan = __builtin_nan("");
+    // Y_bar_m = [Y_m >= 0] (rho w_m a_bar_m - s/sigma) / W_m; T_bar = sum q_bar dq/dT
+    for (int k = wave; k < m.ns; k += kVjpWaves) {
+        if (valid) {
+            const double *e = E(k);
+            const double ycl = (double)Y[k * ldY + cell] >= 0.0 ? 1.0 : 0.0;
+            const double gy = ycl * (rho * e[4] / e[1] - s_tot / sigma) * m.sp[k].inv_W;
+            GY[k * ldGY + cell] = bad ? nan : (IO)gy;
+        }
+    }
+    if (wave == 0 && valid) {
+        GT[cell] = bad ? nan : (IO)t_tot;
+        if (bad) atomicAdd(m.err, 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static size_t jacobian_lds_per_cell(int ns)
+{
+    return ((size_t)(ns + 1) * (ns + 1) + 9 * (size_t)ns) * sizeof(double);
+}
+
+// LDS for one cell (the minimum a launch needs)
+size_t jacobian_lds_bytes(int ns) { return jacobian_lds_per_cell(ns); }
+
+template <typename IO, int JW>
+static hipError_t jacobian_launch_t(const MechView &m, const void *T, const void *P,
+                                    const void *Y, int64_t ldY, int64_t n, void *J,
+                                    int64_t ldJ, hipStream_t st)
+{
+    const size_t lds = JW * jacobian_lds_per_cell(m.ns);
+    const int64_t blocks = (n + JW - 1) / JW;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    auto fn = jacobian_kernel<IO, JW>;
+    hipError_t e = hipFuncSetAttribute((const void *)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * JW), lds, st, m, (const IO *)T,
+                       (const IO *)P, (const IO *)Y, ldY, n, (IO *)J, ldJ);
+    return hipGetLastError();
+}
+
+template <typename IO>
+static hipError_t jacobian_dispatch(const MechView &m, int lds_max, const void *T,
+                                    const void *P, const void *Y, int64_t ldY, int64_t n,
+                                    void *J, int64_t ldJ, hipStream_t st)
+{
+    const size_t per = jacobian_lds_per_cell(m.ns);
+    if (4 * per <= (size_t)lds_max) return jacobian_launch_t<IO, 4>(m, T, P, Y, ldY, n, J, ldJ, st);
+    if (2 * per <= (size_t)lds_max) return jacobian_launch_t<IO, 2>(m, T, P, Y, ldY, n, J, ldJ, st);
+    return jacobian_launch_t<IO, 1>(m, T, P, Y, ldY, n, J, ldJ, st);
+}
+
+hipError_t jacobian_launch(const MechView &m, int lds_max, bool f64, const void *T,
+                           const void *P, const void *Y, int64_t ldY, int64_t n, void *J,
+                           int64_t ldJ, hipStream_t st)
+{
+    if (f64) return jacobian_dispatch<double>(m, lds_max, T, P, Y, ldY, n, J, ldJ, st);
+    return jacobian_dispatch<float>(m, lds_max, T, P, Y, ldY, n, J, ldJ, st);
+}
+
+int vjp_tile(int ns, int lds_max)
+{
+    const int static_lds = kVjpWaves * 2 * 64 * (int)sizeof(double);
+    int t = (lds_max - static_lds) / (ns * kVjpEntry);
+    return t > 64 ? 64 : t;
+}
+
+hipError_t vjp_launch(const MechView &m, int tile, bool f64, const void *T, const void *P,
+                      const void *Y, int64_t ldY, int64_t n, const void *G, int64_t ldG,
+                      void *GY, int64_t ldGY, void *GT, hipStream_t st)
+{
+    const size_t lds = (size_t)m.ns * tile * kVjpEntry;
+    const int64_t blocks = (n + tile - 1) / tile;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (f64) {
+        auto fn = vjp_kernel<double>;
+        hipError_t e = hipFuncSetAttribute((const void *)fn,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * kVjpWaves), lds, st, m, tile,
+                           (const double *)T, (const double *)P, (const double *)Y, ldY, n,
+                           (const double *)G, ldG, (double *)GY, ldGY, (double *)GT);
+    } else {
+        auto fn = vjp_kernel<float>;
+        hipError_t e = hipFuncSetAttribute((const void *)fn,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * kVjpWaves), lds, st, m, tile,
+                           (const float *)T, (const float *)P, (const float *)Y, ldY, n,
+                           (const float *)G, ldG, (float *)GY, ldGY, (float *)GT);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ak

@@ -1,0 +1,203 @@
+"""GPU parity of the Jacobian and VJP kernels against the oracle's analytic
+Jacobian (itself pinned against finite differences), through the C ABI.
+
+Tolerances: every entry's error is measured against the oracle's gross scale
+of that entry (each chain-rule term taken in absolute value).  FP64 path
+<= 1e-11 against the extended-precision oracle; FP32 path (double inside,
+float output) <= 1e-6.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_08483_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ak():
+    from paper_2008_08483_amd import annkin
+    return annkin
+
+
+_MECHS = {}
+
+
+def _mech(ak, ns, nr):
+    if (ns, nr) not in _MECHS:
+        src = synth.make_mechanism(ns, nr)
+        _MECHS[(ns, nr)] = (src, ak.Mechanism(src))
+    return _MECHS[(ns, nr)]
+
+
+def _dev(torch, dt, *arrs):
+    return [torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda") for a in arrs]
+
+
+def _jac_check(src, T, P, Y, J, tol):
+    Jr, Ja = oracle.jacobian(src, T, P, Y, precision="ld", scales=True)
+    err = np.abs(J.astype(np.longdouble) - Jr) / np.maximum(Ja, np.longdouble(1e-300))
+    e = float(err.max())
+    print("jacobian max err/scale", e, "median", float(np.median(err)), flush=True)
+    assert np.all(np.isfinite(J))
+    assert e <= tol
+    return Jr, Ja
+
+
+@pytest.mark.parametrize("wl,n", [("c0", 300), ("c4", 1000)])
+def test_jacobian_fp64(torch, ak, wl, n):
+    w = synth.WORKLOADS[wl]
+    src, m = _mech(ak, w["ns"], w["nr"])
+    _, T, P, Y = synth.workload(wl, n_cells=n)
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    J = ak.eval_jacobian(m, Tt, Pt, Yt)
+    torch.cuda.synchronize()
+    _jac_check(src, T, P, Y, J.cpu().numpy(), 1e-11)
+
+
+def test_jacobian_fp32(torch, ak):
+    src, m = _mech(ak, 53, 325)
+    _, T, P, Y = synth.workload("c4", n_cells=777, dtype=np.float32)
+    Tt, Pt, Yt = _dev(torch, torch.float32, T, P, Y)
+    J = ak.eval_jacobian(m, Tt, Pt, Yt)
+    torch.cuda.synchronize()
+    _jac_check(src, T.astype(np.float64), P.astype(np.float64), Y.astype(np.float64),
+               J.cpu().numpy().astype(np.float64), 1e-6)
+
+
+def test_jacobian_zero_negative_mass_fractions_and_stride(torch, ak):
+    src, m = _mech(ak, 53, 325)
+    _, T, P, Y = synth.workload("c4", n_cells=130)
+    Y = Y.copy()
+    Y[4, :] = 0.0
+    Y[9, ::3] = -1e-9
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    nv = 54
+    big = torch.full((130, nv * nv + 17), 5.0, dtype=torch.float64, device="cuda")
+    L = ak.lib()
+    import ctypes as C
+    rc = L.ak_eval_jacobian(m.handle, 0, Tt.data_ptr(), Pt.data_ptr(), Yt.data_ptr(), 130, 130,
+                            big.data_ptr(), nv * nv + 17, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    b = big.cpu().numpy()
+    assert np.all(b[:, nv * nv:] == 5.0)         # stride padding untouched
+    J = b[:, :nv * nv].reshape(130, nv, nv)
+    _jac_check(src, T, P, Y, J, 1e-11)
+    assert np.all(J[::3, :53, 9] == 0.0)          # clamped column
+
+
+def test_jacobian_111_species(torch, ak):
+    src, m = _mech(ak, 111, 784)
+    _, T, P, Y = synth.workload("c2", n_cells=40)
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    J = ak.eval_jacobian(m, Tt, Pt, Yt)
+    torch.cuda.synchronize()
+    _jac_check(src, T, P, Y, J.cpu().numpy(), 1e-11)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_vjp_against_oracle_jacobian(torch, ak, dt):
+    src, m = _mech(ak, 53, 325)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    npdt = np.float64 if dt == "f64" else np.float32
+    _, T, P, Y = synth.workload("c4", n_cells=700, dtype=npdt)
+    g = np.random.default_rng(9).standard_normal((53, 700)).astype(npdt)
+    Tt, Pt, Yt, gt = _dev(torch, tdt, T, P, Y, g)
+    gY, gT = ak.eval_vjp(m, Tt, Pt, Yt, gt)
+    torch.cuda.synchronize()
+    gY, gT = gY.cpu().numpy().astype(np.float64), gT.cpu().numpy().astype(np.float64)
+    T64, P64, Y64, g64 = (a.astype(np.float64) for a in (T, P, Y, g))
+    Jr, Ja = oracle.jacobian(src, T64, P64, Y64, precision="ld", scales=True)
+    Jr, Ja = Jr[:, :53, :].astype(np.float64), Ja[:, :53, :].astype(np.float64)
+    ref = np.einsum("ik,ikc->ic", g64.T, Jr)
+    scale = np.einsum("ik,ikc->ic", np.abs(g64.T), Ja)
+    got = np.concatenate([gY.T, gT[:, None]], axis=1)
+    err = np.abs(got - ref) / scale
+    print("vjp max err/scale", float(err.max()), flush=True)
+    assert float(err.max()) <= (1e-11 if dt == "f64" else 1e-6)
+
+
+def test_vjp_dot_product_identity(torch, ak):
+    """<g, J v> = <J^T g, v> with the GPU Jacobian and the GPU VJP."""
+    src, m = _mech(ak, 53, 325)
+    _, T, P, Y = synth.workload("c4", n_cells=256)
+    rng = np.random.default_rng(11)
+    g = rng.standard_normal((53, 256))
+    v = rng.standard_normal((54, 256)) * np.concatenate([Y, T[None, :]], axis=0)
+    Tt, Pt, Yt, gt = _dev(torch, torch.float64, T, P, Y, g)
+    J = ak.eval_jacobian(m, Tt, Pt, Yt).cpu().numpy()[:, :53, :]
+    gY, gT = ak.eval_vjp(m, Tt, Pt, Yt, gt)
+    torch.cuda.synchronize()
+    lhs = np.einsum("ki,ikc,ci->i", g, J, v)
+    rhs = (gY.cpu().numpy() * v[:53]).sum(0) + gT.cpu().numpy() * v[53]
+    scale = np.einsum("ki,ikc,ci->i", np.abs(g), np.abs(J), np.abs(v))
+    assert np.all(np.abs(lhs - rhs) <= 1e-12 * scale)
+
+
+def test_autograd_source_term(torch, ak):
+    src, m = _mech(ak, 53, 325)
+    _, T, P, Y = synth.workload("c4", n_cells=300)
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    Tt.requires_grad_(True)
+    Yt.requires_grad_(True)
+    om = ak.source_term(m, Tt, Pt, Yt)
+    g = torch.randn_like(om)
+    (om * g).sum().backward()
+    gY, gT = ak.eval_vjp(m, Tt.detach(), Pt, Yt.detach(), g)
+    torch.cuda.synchronize()
+    # the VJP accumulates adjoints with LDS atomics: equal up to rounding
+    Ja = oracle.jacobian(src, T, P, Y, scales=True)[1][:, :53, :]
+    scale = np.einsum("ki,ikc->ic", np.abs(g.cpu().numpy()), Ja)
+    got = np.concatenate([Yt.grad.cpu().numpy().T, Tt.grad.cpu().numpy()[:, None]], axis=1)
+    ref = np.concatenate([gY.cpu().numpy().T, gT.cpu().numpy()[:, None]], axis=1)
+    assert np.all(np.abs(got - ref) <= 1e-13 * scale)
+    # forward of the Function equals eval_source
+    om2 = ak.eval_source(m, Tt.detach(), Pt, Yt.detach())
+    torch.cuda.synchronize()
+    S = oracle.source(src, T, P, Y, scales=True)[1]
+    assert np.all(np.abs(om.detach().cpu().numpy() - om2.cpu().numpy()) <= 1e-13 * S)
+
+
+def test_jacobian_vs_gpu_finite_differences(torch, ak):
+    """Central differences of the GPU FP64 source term (h = 1e-6 |x|)."""
+    src, m = _mech(ak, 9, 21)
+    _, T, P, Y = synth.workload("c0", n_cells=8)
+    ns = 9
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    J = ak.eval_jacobian(m, Tt, Pt, Yt).cpu().numpy()
+    Ja = oracle.jacobian(src, T, P, Y, scales=True)[1]
+    for c in range(ns + 1):
+        x = np.concatenate([Y, T[None, :]], axis=0)
+        h = 1e-6 * np.abs(x[c])
+        xp, xm = x.copy(), x.copy()
+        xp[c] += h
+        xm[c] -= h
+        fp = ak.eval_source(m, *_dev(torch, torch.float64, xp[ns], P, xp[:ns])).cpu().numpy()
+        fm = ak.eval_source(m, *_dev(torch, torch.float64, xm[ns], P, xm[:ns])).cpu().numpy()
+        fd = (fp - fm) / (xp[c] - xm[c])
+        err = np.abs(fd.T - J[:, :ns, c]) / np.maximum(Ja[:, :ns, c], 1e-300)
+        assert float(err.max()) < 1e-5, (c, float(err.max()))
+
+
+def test_deriv_argument_errors(torch, ak):
+    src, m = _mech(ak, 9, 21)
+    L = ak.lib()
+    x = torch.zeros(8, dtype=torch.float64, device="cuda")
+    Y = torch.zeros((9, 8), dtype=torch.float64, device="cuda")
+    J = torch.zeros((8, 100), dtype=torch.float64, device="cuda")
+    p = lambda t: t.data_ptr()
+    assert L.ak_eval_jacobian(m.handle, 0, p(x), p(x), p(Y), 8, 8, p(J), 99, None) == -1
+    assert L.ak_eval_jacobian(m.handle, 0, p(x), p(x), p(Y), 8, 8, None, 100, None) == -1
+    assert L.ak_eval_vjp(m.handle, 0, p(x), p(x), p(Y), 8, 8, p(Y), 7, p(Y), 8, p(x), None) == -1
+    assert L.ak_eval_vjp(m.handle, 0, p(x), p(x), p(Y), 8, 8, None, 8, p(Y), 8, p(x), None) == -1
+    assert L.ak_eval_vjp(m.handle, 0, None, None, None, 0, 0, None, 0, None, 0, None, None) == 0
