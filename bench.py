@@ -95,6 +95,103 @@ def cpu_baseline(src, T, P, Y, target_s=12.0):
                       f"{cores} OpenMP threads, {dt:.1f} s"}
 
 
+def _serving_pools(torch, annkin, mechs, nmax):
+    """Page-locked host states per mechanism (requests use the first n cells,
+    leading dimension nmax) and a shared output scratch per mechanism."""
+    pools = []
+    for i, src in enumerate(mechs):
+        T, P, Y = synth.make_states(src, nmax, 3000 + i, (800.0, 2800.0), (1.0, 20.0), 0.3,
+                                    dtype=np.float32)
+        pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+        pools.append((pin(T), pin(P), pin(Y),
+                      torch.zeros((src.n_species, nmax), dtype=torch.float32).pin_memory()))
+    return pools
+
+
+def _run_trace(annkin, srv, dev_mechs, pools, arrivals, sizes, which, warmup):
+    """Open-loop replay: submit request i at arrivals[i] (seconds from start);
+    a second thread waits for and frees completed requests.  Statistics are
+    reset after `warmup` requests have completed."""
+    import queue
+    import threading
+    q = queue.Queue()
+    done = [0]
+
+    def reaper():
+        while True:
+            r = q.get()
+            if r is None:
+                return
+            r.wait(120.0)
+            r.free()
+            done[0] += 1
+            if done[0] == warmup:
+                srv.reset_stats()
+
+    th = threading.Thread(target=reaper)
+    th.start()
+    t0 = time.perf_counter()
+    for i in range(len(sizes)):
+        delay = arrivals[i] - (time.perf_counter() - t0)
+        if delay > 2e-3:
+            time.sleep(delay - 1e-3)
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        k, n = int(which[i]), int(sizes[i])
+        T, P, Y, O = pools[k]
+        q.put(srv.submit(dev_mechs[k], T[:n], P[:n], Y[:, :n], O[:, :n]))
+    q.put(None)
+    th.join()
+    return srv.stats()
+
+
+def serving_bench(torch, annkin, n_req=10000, warmup=500):
+    """Serving configuration: requests of log-uniform [64, 65536] cells, half
+    on the 9/21 and half on the 53/325 mechanism (both resident), FP32.
+    Capacity of the one-launch-per-request form measured closed-loop, then
+    both forms replay one seeded Poisson trace at 0.8x that capacity."""
+    srcs = [synth.make_mechanism(9, 21), synth.make_mechanism(53, 325)]
+    dev = [annkin.Mechanism(s) for s in srcs]
+    nmax = 65536
+    pools = _serving_pools(torch, annkin, srcs, nmax)
+    _, sizes, which = synth.make_trace(n_req + warmup, 1.0, seed=2000)
+    sizes = np.minimum(sizes, nmax)
+    # capacity: closed loop, 8 outstanding, one launch per request
+    srv = annkin.Server(batching=False, max_inflight=3)
+    outstanding, t0, cells = [], time.perf_counter(), 0
+    m = min(3000, len(sizes))
+    for i in range(m):
+        k, n = int(which[i]), int(sizes[i])
+        T, P, Y, O = pools[k]
+        outstanding.append(srv.submit(dev[k], T[:n], P[:n], Y[:, :n], O[:, :n]))
+        cells += n
+        if len(outstanding) >= 8:
+            r = outstanding.pop(0)
+            r.wait(120.0)
+            r.free()
+    for r in outstanding:
+        r.wait(120.0)
+        r.free()
+    cap_s = m / (time.perf_counter() - t0)
+    srv.close()
+    rate = 0.8 * cap_s
+    arrivals, _, _ = synth.make_trace(n_req + warmup, rate, seed=2000)
+    out = {"workload": "requests of log-uniform [64, 65536] cells, 50/50 9sp/21rxn and "
+                       "53sp/325rxn mechanisms, FP32, Poisson arrivals",
+           "capacity_one_launch_req_per_s": cap_s, "offered_req_per_s": rate,
+           "requests": n_req, "warmup_requests": warmup}
+    for name, batching in (("one_launch_per_request", False), ("continuous_batching", True)):
+        srv = annkin.Server(batching=batching, max_inflight=3, arena_bytes=1 << 30)
+        st = _run_trace(annkin, srv, dev, pools, arrivals, sizes, which, warmup)
+        srv.close()
+        out[name] = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                     "cells_per_s": st["cells_per_s"], "completed": st["completed"],
+                     "batches": st["batches"], "launches": st["launches"]}
+    for d in dev:
+        d.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +200,7 @@ def main():
     ap.add_argument("--workload", default="c1_full", choices=list(synth.WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--only-main", action="store_true",
                     help="time only the main FP32 leg (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -180,7 +278,7 @@ def main():
     }
 
     if args.only_main:
-        args.no_fp64 = args.no_cpu_baseline = True
+        args.no_fp64 = args.no_cpu_baseline = args.no_serving = True
     if not args.no_fp64:
         T64, P64, Y64 = (t.double() for t in (T32, P32, Y32))
         wall64, ms64, om64 = time_path(torch, annkin, mech, T64, P64, Y64,
@@ -208,6 +306,9 @@ def main():
                                     P32[:m].contiguous(), Y32[:, :m].contiguous(),
                                     args.steps, args.warmup)
         result["c1_65536_cells_per_s"] = m * args.steps / wall_s
+
+    if not args.no_serving:
+        result["serving"] = serving_bench(torch, annkin)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(src, T, P, Y)

@@ -168,6 +168,81 @@ int ak_eval_vjp(const ak_mechanism *mech, ak_precision prec, const void *T, cons
  */
 int ak_error_count(const ak_mechanism *mech, void *stream, int64_t *n_bad_cells);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of many callers' source-term requests.
+ *
+ * The paper's use is an MPI rank offloading its cells to the GPU (Sec. 1,
+ * Sec. 3.2).  A server accepts such offloads from many host threads at once:
+ * requests are queued FIFO and admitted while their bytes fit a device arena
+ * and fewer than max_inflight batches are on the device; each admitted batch
+ * is copied in, evaluated by ONE fused launch per precision covering all its
+ * requests (mechanisms may differ), and copied back, while later requests
+ * keep being admitted as memory and batch slots free up.  With batching = 0
+ * every request is its own batch (one launch per request), for comparison.
+ * Results equal ak_eval_source's up to the rounding order of the omega
+ * accumulation.
+ */
+typedef struct ak_server ak_server;   /* opaque */
+typedef struct ak_request ak_request; /* opaque */
+
+typedef struct {
+    int32_t device;             /* HIP device of the server (mechanisms must match) */
+    int32_t max_inflight;       /* batches on the device at once (0: 3; at most 16) */
+    int32_t max_batch_requests; /* requests per batch (0: 64; at most 4096) */
+    int32_t batching;           /* 1: continuous batching, 0: one launch per request */
+    int64_t max_batch_cells;    /* cells per batch (0: 2^21) */
+    size_t arena_bytes;         /* device arena for staged requests (0: 1 GiB) */
+} ak_server_config;
+
+typedef struct {
+    int64_t submitted, completed, cancelled, failed; /* requests since the last reset */
+    int64_t batches, launches, cells;                /* device work since the last reset */
+    int64_t queue_depth;                             /* queued now */
+    int32_t inflight, pad;                           /* batches on the device now */
+    size_t arena_bytes, arena_used;
+    double p50_ms, p99_ms, mean_ms, max_ms;          /* submit -> host-visible result */
+    double cells_per_s;                              /* cells / (last completion - first submit) */
+} ak_server_stats;
+
+/* Create a server: allocates the device arena, max_inflight streams (default
+ * priority) and descriptor tables, and starts the batcher and completion
+ * threads.  Errors: AK_EINVAL, AK_ENOMEM, AK_EDEVICE. */
+int ak_server_create(const ak_server_config *cfg, ak_server **out);
+
+/*
+ * Submit one request: n_cells states in HOST memory (T[n], P[n], Y[NS][ldY];
+ * float or double by `prec`), results written to HOST omega[NS][ldO] before
+ * the request completes.  Page-locked host buffers give asynchronous copies.
+ * The buffers must stay valid until the request has completed or been
+ * cancelled.  Returns at once.  Errors: AK_EINVAL (null, n_cells <= 0,
+ * ld < n_cells, mechanism on another device), AK_E2BIG (request larger than
+ * the arena), AK_ENOMEM.
+ */
+int ak_server_submit(ak_server *srv, const ak_mechanism *mech, ak_precision prec, const void *T,
+                     const void *P, const void *Y, int64_t ldY, int64_t n_cells, void *omega,
+                     int64_t ldO, ak_request **out);
+
+/* Wait for a request: 0 when its results are in omega; AK_ETIMEDOUT after
+ * timeout_s seconds (< 0: no limit); AK_ECANCELED; AK_EDEVICE if its batch
+ * failed. */
+int ak_request_wait(ak_request *req, double timeout_s);
+
+/* Cancel a request that is still queued: 0 if cancelled, 1 if it was
+ * already admitted to the device (it then completes normally). */
+int ak_request_cancel(ak_request *req);
+
+/* Free a completed, failed or cancelled request (AK_EINVAL while pending). */
+int ak_request_free(ak_request *req);
+
+/* Counters and latency percentiles since the last reset. */
+int ak_server_get_stats(ak_server *srv, ak_server_stats *out);
+int ak_server_reset_stats(ak_server *srv);
+
+/* Stop the server: queued requests are cancelled, admitted ones complete,
+ * then device resources are released.  Requests stay valid for
+ * ak_request_wait / ak_request_free. */
+int ak_server_destroy(ak_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,6 +44,21 @@ class MechanismDesc(C.Structure):
     ]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32),
+                ("max_batch_requests", C.c_int32), ("batching", C.c_int32),
+                ("max_batch_cells", C.c_int64), ("arena_bytes", C.c_size_t)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("cancelled", C.c_int64),
+                ("failed", C.c_int64), ("batches", C.c_int64), ("launches", C.c_int64),
+                ("cells", C.c_int64), ("queue_depth", C.c_int64), ("inflight", C.c_int32),
+                ("pad", C.c_int32), ("arena_bytes", C.c_size_t), ("arena_used", C.c_size_t),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("max_ms", C.c_double), ("cells_per_s", C.c_double)]
+
+
 def lib():
     """Load libannkin.so (fails loudly if it has not been built)."""
     global _lib
@@ -63,6 +78,16 @@ def lib():
         h.ak_error_count.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]
         h.ak_eval_jacobian.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+        h.ak_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]
+        h.ak_server_submit.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_int64,
+                                       C.POINTER(C.c_void_p)]
+        h.ak_request_wait.argtypes = [C.c_void_p, C.c_double]
+        h.ak_request_cancel.argtypes = [C.c_void_p]
+        h.ak_request_free.argtypes = [C.c_void_p]
+        h.ak_server_get_stats.argtypes = [C.c_void_p, C.POINTER(ServerStats)]
+        h.ak_server_reset_stats.argtypes = [C.c_void_p]
+        h.ak_server_destroy.argtypes = [C.c_void_p]
         h.ak_eval_vjp.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                   C.c_int64, C.c_void_p, C.c_void_p]
@@ -256,3 +281,98 @@ def source_term(mech: Mechanism, T, P, Y):
 def jacobian(mech: Mechanism, T, P, Y):
     """Alias of eval_jacobian."""
     return eval_jacobian(mech, T, P, Y)
+
+
+# ---------------------------------------------------------------------------
+# serving
+
+def _host_ptr(a):
+    """Address of a host buffer: a CPU torch tensor or a numpy array."""
+    if hasattr(a, "data_ptr"):
+        if a.is_cuda:
+            raise TypeError("server requests take host buffers")
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _host_info(a):
+    if hasattr(a, "data_ptr"):
+        return a.dtype, tuple(a.shape), a.stride()
+    return a.dtype, a.shape, tuple(s // a.itemsize for s in a.strides)
+
+
+class Request:
+    """One submitted request.  Keeps its host buffers alive until freed."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def wait(self, timeout: float = -1.0) -> None:
+        _check(lib().ak_request_wait(self._h, float(timeout)))
+
+    def cancel(self) -> bool:
+        """True if the request was still queued and is now cancelled."""
+        return lib().ak_request_cancel(self._h) == 0
+
+    def free(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(lib().ak_request_free(self._h))
+            self._h = None
+            self._keep = None
+
+
+class Server:
+    """Continuous-batching source-term server on one GPU (see annkin.h)."""
+
+    def __init__(self, device: int | None = None, max_inflight: int = 3,
+                 max_batch_requests: int = 64, batching: bool = True,
+                 max_batch_cells: int = 1 << 21, arena_bytes: int = 1 << 30):
+        if device is None:
+            device = _torch().cuda.current_device()
+        cfg = ServerConfig(int(device), int(max_inflight), int(max_batch_requests),
+                           1 if batching else 0, int(max_batch_cells), int(arena_bytes))
+        h = C.c_void_p()
+        _check(lib().ak_server_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    def submit(self, mech: Mechanism, T, P, Y, out) -> Request:
+        """Queue one request: host T [n], P [n], Y [NS, ldY-strided], results
+        into host out [NS, ldO-strided]; float32 or float64 buffers."""
+        dt, shp, st = _host_info(Y)
+        n = shp[1]
+        ns = mech.n_species
+        if shp[0] != ns or st[1] != 1:
+            raise ValueError("Y must be [NS, n] with unit cell stride")
+        odt, oshp, ost = _host_info(out)
+        if oshp != (ns, n) or ost[1] != 1:
+            raise ValueError("out must be [NS, n] with unit cell stride")
+        name = str(dt)
+        prec = AK_FP32 if "float32" in name else AK_FP64 if "float64" in name else None
+        if prec is None:
+            raise TypeError("float32 or float64 buffers")
+        ldY = st[0] if ns > 1 else n
+        ldO = ost[0] if ns > 1 else n
+        h = C.c_void_p()
+        _check(lib().ak_server_submit(self._h, mech.handle, prec, _host_ptr(T), _host_ptr(P),
+                                      _host_ptr(Y), ldY, n, _host_ptr(out), ldO, C.byref(h)))
+        return Request(h, (T, P, Y, out, mech))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().ak_server_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_ if f != "pad"}
+
+    def reset_stats(self) -> None:
+        _check(lib().ak_server_reset_stats(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ak_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

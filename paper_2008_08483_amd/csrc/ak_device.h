@@ -78,6 +78,15 @@ struct MechView {
     ShapeRun runs[kMaxRuns];
 };
 
+// One request of a fused multi-request launch (device-resident table).
+struct BatchDesc {
+    MechView m;
+    const void *T, *P, *Y;
+    void *om;
+    int64_t ldY, ldO, n;
+    int64_t block_begin;     // first workgroup of this request
+};
+
 // LDS tile: per (species k, cell c) a 24-byte entry at
 //     k * species_stride(tile) + c * kEntry
 // holding {double a, double v, accumulator (float or double)}.

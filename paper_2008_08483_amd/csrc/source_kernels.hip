@@ -170,22 +170,21 @@ __device__ __forceinline__ void all_reactions(const MechView &m, int wave, unsig
     }
 }
 
-// IO: float (AK_FP32) or double (AK_FP64).  Grid: one workgroup per tile of
-// m.tile cells; block = 64 * WAVES threads; dynamic LDS = ns * m.tile * 24 B.
-// lane_zero must be 0 (see load_rxn).
+// One tile of m.tile cells starting at cell tile_idx * m.tile (IO: float for
+// AK_FP32, double for AK_FP64); block = 64 * WAVES threads; dynamic LDS =
+// ns * m.tile * 24 B.  lane_zero must be 0 (see load_rxn).
 template <typename IO, bool F64, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void source_kernel(MechView m, const IO *__restrict__ T,
-                                                           const IO *__restrict__ P,
-                                                           const IO *__restrict__ Y, int64_t ldY,
-                                                           int64_t n, IO *__restrict__ om,
-                                                           int64_t ldO, uint32_t zero)
+__device__ __forceinline__ void source_tile(const MechView &m, const IO *__restrict__ T,
+                                            const IO *__restrict__ P,
+                                            const IO *__restrict__ Y, int64_t ldY, int64_t n,
+                                            IO *__restrict__ om, int64_t ldO, uint32_t zero,
+                                            int64_t tile_idx, unsigned char *lds)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = m.tile;
     const bool active = lane < tile;               // owns an LDS column
-    const int64_t cell = (int64_t)blockIdx.x * tile + lane;
+    const int64_t cell = tile_idx * tile + lane;
     const bool valid = active && cell < n;          // owns a real cell
     const uint32_t sstride = species_stride(tile);
     // lanes past the tile read column 0 (harmless) and never write
@@ -261,6 +260,36 @@ __global__ __launch_bounds__(64 * WAVES) void source_kernel(MechView m, const IO
     if (wave == 0 && valid && bad) atomicAdd(m.err, 1ull);
 }
 
+template <typename IO, bool F64, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void source_kernel(MechView m, const IO *__restrict__ T,
+                                                           const IO *__restrict__ P,
+                                                           const IO *__restrict__ Y, int64_t ldY,
+                                                           int64_t n, IO *__restrict__ om,
+                                                           int64_t ldO, uint32_t zero)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    source_tile<IO, F64, WAVES>(m, T, P, Y, ldY, n, om, ldO, zero, blockIdx.x, lds);
+}
+
+// Several requests in one launch: request r owns workgroups
+// [d[r].block_begin, d[r].block_begin + ceil(n_r / tile_r)); each workgroup
+// finds its request in the descriptor table and runs that request's tile.
+template <typename IO, bool F64, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void source_batch_kernel(const BatchDesc *__restrict__ d,
+                                                                 int nreq, uint32_t zero)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {                 // last r with block_begin <= b
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+    }
+    const BatchDesc &r = d[lo];
+    source_tile<IO, F64, WAVES>(r.m, (const IO *)r.T, (const IO *)r.P, (const IO *)r.Y, r.ldY,
+                                r.n, (IO *)r.om, r.ldO, zero, b - r.block_begin, lds);
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 
@@ -281,6 +310,29 @@ static hipError_t launch_source(const MechView &m, const void *T, const void *P,
 }
 
 size_t source_lds_bytes(int ns, int tile) { return (size_t)ns * species_stride(tile); }
+
+hipError_t source_batch_launch(bool f64, const BatchDesc *d_desc, int nreq, int64_t blocks,
+                               size_t lds, hipStream_t st)
+{
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (f64) {
+        auto fn = source_batch_kernel<double, true, AK_SOURCE_WAVES>;
+        hipError_t e = hipFuncSetAttribute((const void *)fn,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * AK_SOURCE_WAVES), lds, st, d_desc,
+                           nreq, 0u);
+    } else {
+        auto fn = source_batch_kernel<float, false, AK_SOURCE_WAVES>;
+        hipError_t e = hipFuncSetAttribute((const void *)fn,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * AK_SOURCE_WAVES), lds, st, d_desc,
+                           nreq, 0u);
+    }
+    return hipGetLastError();
+}
 
 hipError_t source_launch(const MechView &m, bool f64, const void *T, const void *P,
                          const void *Y, int64_t ldY, int64_t n, void *om, int64_t ldO,

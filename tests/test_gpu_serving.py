@@ -1,0 +1,184 @@
+"""GPU tests of the serving loop: results in a mixed, concurrent request
+stream equal each request evaluated alone (ak_eval_source) within rounding
+of the omega accumulation, and match the oracle; memory-based admission,
+cancellation, shutdown and statistics."""
+
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_08483_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ak():
+    from paper_2008_08483_amd import annkin
+    return annkin
+
+
+@pytest.fixture(scope="module")
+def mechs(ak):
+    out = {}
+    for ns, nr in ((9, 21), (53, 325)):
+        src = synth.make_mechanism(ns, nr)
+        out[ns] = (src, ak.Mechanism(src))
+    return out
+
+
+def _request_states(src, n, seed, dtype):
+    T, P, Y = synth.make_states(src, n, seed, (800.0, 2800.0), (1.0, 20.0), 0.3, dtype=dtype)
+    return T, P, Y
+
+
+def _pinned(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+
+
+def _alone(torch, ak, m, T, P, Y):
+    Tt, Pt, Yt = (torch.tensor(a, device="cuda") for a in (T, P, Y))
+    om = ak.eval_source(m, Tt, Pt, Yt)
+    torch.cuda.synchronize()
+    return om.cpu().numpy()
+
+
+@pytest.mark.parametrize("batching", [True, False])
+def test_mixed_concurrent_stream_equals_alone(torch, ak, mechs, batching):
+    srv = ak.Server(max_inflight=3, batching=batching, arena_bytes=256 << 20)
+    rng = np.random.default_rng(3)
+    specs = []
+    for i in range(60):
+        ns = 9 if rng.random() < 0.5 else 53
+        dt = np.float32 if rng.random() < 0.7 else np.float64
+        n = int(np.round(np.exp(rng.uniform(np.log(64), np.log(6000)))))
+        specs.append((i, ns, dt, n))
+    results = {}
+    lock = threading.Lock()
+
+    def client(part):
+        for i, ns, dt, n in part:
+            src, m = mechs[ns]
+            T, P, Y = _request_states(src, n, 500 + i, dt)
+            # Y inside a wider buffer: a strided host leading dimension
+            Yb = np.zeros((ns, n + 7), dtype=dt)
+            Yb[:, :n] = Y
+            Tp, Pp, Yp = _pinned(torch, T), _pinned(torch, P), _pinned(torch, Yb)
+            out = torch.zeros((ns, n), dtype=torch.float32 if dt == np.float32 else torch.float64).pin_memory()
+            req = srv.submit(m, Tp, Pp, Yp[:, :n], out)
+            req.wait(60.0)
+            req.free()
+            with lock:
+                results[i] = (T, P, Y, out.numpy().copy())
+
+    threads = [threading.Thread(target=client, args=(specs[k::4],)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert len(results) == len(specs)
+    st = srv.stats()
+    print("server stats", st, flush=True)
+    assert st["completed"] == len(specs) and st["failed"] == 0
+    assert st["p99_ms"] >= st["p50_ms"] > 0 and st["cells_per_s"] > 0
+    if not batching:
+        assert st["batches"] == len(specs)
+    srv.close()
+    for i, ns, dt, n in specs:
+        src, m = mechs[ns]
+        T, P, Y, om = results[i]
+        alone = _alone(torch, ak, m, T, P, Y)
+        _, S, _ = oracle.source(src, T.astype(np.float64), P.astype(np.float64),
+                                Y.astype(np.float64), scales=True)
+        # same kernel, same tiling: only the accumulation order can differ
+        if dt == np.float32:
+            assert np.all(np.abs(om.astype(np.float64) - alone) <= 1e-6 * S), i
+        else:
+            assert np.all(np.abs(om - alone) <= 1e-13 * S), i
+        ref = oracle.source(src, T.astype(np.float64), P.astype(np.float64), Y.astype(np.float64))
+        tol = 1e-5 if dt == np.float32 else 1e-12
+        assert np.all(np.abs(om.astype(np.float64) - ref) <= tol * S), i
+
+
+def test_continuous_batching_fuses_requests(torch, ak, mechs):
+    """Requests queued while a batch runs are admitted together: fewer
+    batches than requests."""
+    src, m = mechs[53]
+    srv = ak.Server(max_inflight=1, batching=True, arena_bytes=512 << 20)
+    T, P, Y = _request_states(src, 4000, 77, np.float32)
+    Tp, Pp, Yp = _pinned(torch, T), _pinned(torch, P), _pinned(torch, Y)
+    outs = [torch.zeros((53, 4000), dtype=torch.float32).pin_memory() for _ in range(40)]
+    reqs = [srv.submit(m, Tp, Pp, Yp, o) for o in outs]
+    for r in reqs:
+        r.wait(60.0)
+        r.free()
+    st = srv.stats()
+    print("stats", st, flush=True)
+    assert st["completed"] == 40
+    assert st["batches"] < 40
+    assert st["launches"] == st["batches"]          # one fused launch per batch (FP32 only)
+    alone = _alone(torch, ak, m, T, P, Y)
+    for o in outs:
+        assert np.allclose(o.numpy(), alone, rtol=1e-6, atol=0)
+    srv.close()
+
+
+def test_admission_limits_and_errors(torch, ak, mechs):
+    src, m = mechs[53]
+    srv = ak.Server(max_inflight=1, arena_bytes=4 << 20)
+    T, P, Y = _request_states(src, 20000, 5, np.float32)     # ~8.6 MB > arena
+    out = np.zeros((53, 20000), np.float32)
+    with pytest.raises(ak.AnnkinError) as e:
+        srv.submit(m, T, P, Y, out)
+    assert e.value.code == -4
+    # requests that each fit but not together are serialised by memory
+    T2, P2, Y2 = _request_states(src, 6000, 6, np.float32)   # ~2.6 MB each
+    outs = [np.zeros((53, 6000), np.float32) for _ in range(3)]
+    reqs = [srv.submit(m, T2, P2, Y2, o) for o in outs]
+    for r in reqs:
+        r.wait(60.0)
+        r.free()
+    alone = _alone(torch, ak, m, T2, P2, Y2)
+    for o in outs:
+        assert np.allclose(o, alone, rtol=1e-6, atol=0)
+    assert srv.stats()["arena_used"] == 0
+    srv.close()
+
+
+def test_cancel_and_shutdown(torch, ak, mechs):
+    src, m = mechs[53]
+    srv = ak.Server(max_inflight=1, batching=False)
+    T, P, Y = _request_states(src, 30000, 8, np.float32)
+    outs = [np.zeros((53, 30000), np.float32) for _ in range(12)]
+    reqs = [srv.submit(m, T, P, Y, o) for o in outs]
+    cancelled = [r.cancel() for r in reqs[::-1]][::-1]
+    assert any(cancelled)                       # the tail was still queued
+    for r, c in zip(reqs, cancelled):
+        if c:
+            with pytest.raises(ak.AnnkinError) as e:
+                r.wait(10.0)
+            assert e.value.code == -6
+        else:
+            r.wait(60.0)
+        r.free()
+    # shutdown with queued work: queued requests are cancelled, admitted drain
+    more = [srv.submit(m, T, P, Y, o) for o in outs[:6]]
+    srv.close()
+    codes = []
+    for r in more:
+        try:
+            r.wait(10.0)
+            codes.append(0)
+        except ak.AnnkinError as e:
+            codes.append(e.code)
+        r.free()
+    assert set(codes) <= {0, -6}
