@@ -192,6 +192,40 @@ def serving_bench(torch, annkin, n_req=10000, warmup=500):
     return out
 
 
+def deriv_bench(torch, annkin, steps=10):
+    """Differentiation configuration: 53/325 mechanism x 65,536 cells; the
+    dense 54 x 54 per-cell Jacobian and the VJP, FP64 and FP32 states."""
+    src, T, P, Y = synth.workload("c4")
+    mech = annkin.Mechanism(src)
+    n, nv = T.shape[0], src.n_species + 1
+    out = {"workload": f"{src.n_species}sp/{src.n_reactions}rxn synthetic mechanism x {n} cells"}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        Tt, Pt, Yt = (torch.tensor(a, dtype=dt, device="cuda") for a in (T, P, Y))
+        J = torch.empty((n, nv, nv), dtype=dt, device="cuda")
+        g = torch.randn((src.n_species, n), dtype=dt, device="cuda")
+        res = {}
+        for what, fn in (("jacobian", lambda: annkin.eval_jacobian(mech, Tt, Pt, Yt, out=J)),
+                         ("vjp", lambda: annkin.eval_vjp(mech, Tt, Pt, Yt, g))):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            res[what + "_ms"] = ms
+            res[what + "_per_s"] = n / (ms * 1e-3)
+        es = 8 if dt == torch.float64 else 4
+        res["jacobian_write_GBps"] = n * nv * nv * es / (res["jacobian_ms"] * 1e-3) / 1e9
+        res["jacobian_write_frac_of_hbm"] = res["jacobian_write_GBps"] * 1e9 / roofline.PEAK_HBM
+        out[name] = res
+        del Tt, Pt, Yt, J, g
+    mech.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +235,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-deriv", action="store_true")
     ap.add_argument("--only-main", action="store_true",
                     help="time only the main FP32 leg (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -278,7 +313,7 @@ def main():
     }
 
     if args.only_main:
-        args.no_fp64 = args.no_cpu_baseline = args.no_serving = True
+        args.no_fp64 = args.no_cpu_baseline = args.no_serving = args.no_deriv = True
     if not args.no_fp64:
         T64, P64, Y64 = (t.double() for t in (T32, P32, Y32))
         wall64, ms64, om64 = time_path(torch, annkin, mech, T64, P64, Y64,
@@ -306,6 +341,9 @@ def main():
                                     P32[:m].contiguous(), Y32[:, :m].contiguous(),
                                     args.steps, args.warmup)
         result["c1_65536_cells_per_s"] = m * args.steps / wall_s
+
+    if not args.no_deriv:
+        result["differentiation"] = deriv_bench(torch, annkin)
 
     if not args.no_serving:
         result["serving"] = serving_bench(torch, annkin)

@@ -31,6 +31,43 @@ struct Cell {
     double log2T, invT;
 };
 
+// 2^g and 2^-g in double from one polynomial evaluation: g = n + f with n
+// the nearest integer (|f| <= 1/2), 2^f = exp(f ln 2) by its Taylor series
+// split into even and odd parts E(f) + O(f), so that 2^-f = E(f) - O(f).
+// Degree 12 (error below one double ulp) or 10 (below 3e-13 relative).
+template <int DEG>
+__device__ __forceinline__ void exp2_pair(double g, double &pos, double &neg)
+{
+    // ln(2)^k / k!
+    constexpr double c[13] = {1.0,
+                              0.69314718055994530942,
+                              0.24022650695910071233,
+                              0.055504108664821579953,
+                              0.0096181291076284771620,
+                              0.0013333558146428443424,
+                              0.00015403530393381609954,
+                              0.000015252733804059840280,
+                              0.0000013215486790144309489,
+                              1.0178086009239699728e-7,
+                              7.0549116208011233099e-9,
+                              4.4455382718708114975e-10,
+                              2.5678435993488205142e-11};
+    const double n = __builtin_rint(g);
+    const double f = g - n;
+    const double f2 = f * f;
+    double E = c[DEG - (DEG & 1)];
+#pragma unroll
+    for (int k = DEG - (DEG & 1) - 2; k >= 0; k -= 2) E = __builtin_fma(E, f2, c[k]);
+    constexpr int top_odd = (DEG & 1) ? DEG : DEG - 1;
+    double O = c[top_odd];
+#pragma unroll
+    for (int k = top_odd - 2; k >= 1; k -= 2) O = __builtin_fma(O, f2, c[k]);
+    O *= f;
+    const int ni = (int)n;
+    pos = __builtin_ldexp(E + O, ni);
+    neg = __builtin_ldexp(E - O, -ni);
+}
+
 // omega accumulators are double in both paths: LDS float atomics stall the
 // LDS pipeline on gfx950 far more than double ones (measured), and double
 // accumulation costs nothing in accuracy.
@@ -201,6 +238,14 @@ __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restr
         if (active) *(double *)(lds + (uint32_t)k * sstride + lane_off) = yw;
     }
     if (wave < m.ns && active) *(double *)(lds + (uint32_t)wave * sstride + lane_off + 16) = psum;
+    double Tc = valid ? (double)T[cell] : 1000.0;
+    double Pc = valid ? (double)P[cell] : 1.0e5;
+    const bool tp_bad = !(Tc > 0.0) || !(Pc > 0.0) || !__builtin_isfinite(Tc) ||
+                        !__builtin_isfinite(Pc);
+    if (tp_bad) {
+        Tc = 1000.0;
+        Pc = 1.0e5;
+    }
     __syncthreads();
     // (2) mixture sum, same order in every wave
     double sigma = 0.0;
@@ -209,34 +254,40 @@ __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restr
         sigma += *(const double *)(lds + (uint32_t)w * sstride + lane_off + 16);
     __syncthreads();
 
-    double Tc = valid ? (double)T[cell] : 1000.0;
-    double Pc = valid ? (double)P[cell] : 1.0e5;
-    const bool bad = !(Tc > 0.0) || !(Pc > 0.0) || !__builtin_isfinite(Tc) ||
-                     !__builtin_isfinite(Pc) || !(sigma > 0.0) || !__builtin_isfinite(sigma);
-    if (bad) {
-        Tc = 1000.0;
-        Pc = 1.0e5;
-        sigma = 1.0;
-    }
-    const double lnT = log(Tc);
-    const double invT = 1.0 / Tc;
+    const bool bad = tp_bad || !(sigma > 0.0) || !__builtin_isfinite(sigma);
+    if (bad) sigma = 1.0;
+    const double lnT = log(Tc), invT = 1.0 / Tc;
     const double T2 = Tc * Tc, T3 = T2 * Tc, T4 = T3 * Tc;
     const double rho_hat = Pc / (kRu * Tc * sigma);   // C_k = rho_hat * Y_k / W_k
 
     // (3) Gibbs layer (Eqs. 10-11) and the exponentials of the chemical
-    //     potentials for this wave's species
+    //     potentials for this wave's species.  The NASA range is chosen per
+    //     cell; when the whole wave is on one side of T_mid only that
+    //     polynomial is evaluated.
     for (int k = wave; k < m.ns; k += WAVES) {
         const SpeciesRec &s = m.sp[k];
-        const double glo = s.lo[0] * lnT + s.lo[1] * Tc + s.lo[2] * T2 + s.lo[3] * T3 +
-                           s.lo[4] * T4 + s.lo[5] * invT + s.lo[6];
-        const double ghi = s.hi[0] * lnT + s.hi[1] * Tc + s.hi[2] * T2 + s.hi[3] * T3 +
-                           s.hi[4] * T4 + s.hi[5] * invT + s.hi[6];
-        const double g2 = (Tc >= s.T_mid) ? ghi : glo;
+        const bool high = Tc >= s.T_mid;
+        double g2;
+        if (__builtin_amdgcn_read_exec() == __ballot(high)) {
+            g2 = s.hi[0] * lnT + s.hi[1] * Tc + s.hi[2] * T2 + s.hi[3] * T3 + s.hi[4] * T4 +
+                 s.hi[5] * invT + s.hi[6];
+        } else if (__ballot(high) == 0) {
+            g2 = s.lo[0] * lnT + s.lo[1] * Tc + s.lo[2] * T2 + s.lo[3] * T3 + s.lo[4] * T4 +
+                 s.lo[5] * invT + s.lo[6];
+        } else {
+            const double glo = s.lo[0] * lnT + s.lo[1] * Tc + s.lo[2] * T2 + s.lo[3] * T3 +
+                               s.lo[4] * T4 + s.lo[5] * invT + s.lo[6];
+            const double ghi = s.hi[0] * lnT + s.hi[1] * Tc + s.hi[2] * T2 + s.hi[3] * T3 +
+                               s.hi[4] * T4 + s.hi[5] * invT + s.hi[6];
+            g2 = high ? ghi : glo;
+        }
+        double w, v;
+        exp2_pair<F64 ? 12 : 10>(g2, w, v);
         if (active) {
             double *e = (double *)(lds + (uint32_t)k * sstride + lane_off);
             const double yw = bad ? 0.0 : e[0];
-            e[0] = rho_hat * yw * exp2(g2);
-            e[1] = exp2(-g2);
+            e[0] = rho_hat * yw * w;
+            e[1] = v;
             e[2] = 0.0;
         }
     }
@@ -260,12 +311,16 @@ __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restr
     if (wave == 0 && valid && bad) atomicAdd(m.err, 1ull);
 }
 
+// Two 8-wave workgroups share a CU (4 waves per SIMD) only if each wave fits
+// in 128 VGPRs; without the cap the FP64 instantiation takes a few more and
+// drops to one workgroup per CU.
+#define AK_TWO_TILES_PER_CU __attribute__((amdgpu_waves_per_eu(4)))
+
 template <typename IO, bool F64, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void source_kernel(MechView m, const IO *__restrict__ T,
-                                                           const IO *__restrict__ P,
-                                                           const IO *__restrict__ Y, int64_t ldY,
-                                                           int64_t n, IO *__restrict__ om,
-                                                           int64_t ldO, uint32_t zero)
+__global__ __launch_bounds__(64 * WAVES) AK_TWO_TILES_PER_CU void
+source_kernel(MechView m, const IO *__restrict__ T, const IO *__restrict__ P,
+              const IO *__restrict__ Y, int64_t ldY, int64_t n, IO *__restrict__ om, int64_t ldO,
+              uint32_t zero)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     source_tile<IO, F64, WAVES>(m, T, P, Y, ldY, n, om, ldO, zero, blockIdx.x, lds);
@@ -275,8 +330,8 @@ __global__ __launch_bounds__(64 * WAVES) void source_kernel(MechView m, const IO
 // [d[r].block_begin, d[r].block_begin + ceil(n_r / tile_r)); each workgroup
 // finds its request in the descriptor table and runs that request's tile.
 template <typename IO, bool F64, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void source_batch_kernel(const BatchDesc *__restrict__ d,
-                                                                 int nreq, uint32_t zero)
+__global__ __launch_bounds__(64 * WAVES) AK_TWO_TILES_PER_CU void
+source_batch_kernel(const BatchDesc *__restrict__ d, int nreq, uint32_t zero)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int64_t b = blockIdx.x;
