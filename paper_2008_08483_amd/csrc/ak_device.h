@@ -27,26 +27,30 @@ struct SpeciesRec {
 };
 static_assert(sizeof(SpeciesRec) == 128, "SpeciesRec layout");
 
-// Per reaction (64 B), reactions stored sorted by shape (see ShapeRun).
-// Arrhenius layer (Eq. 6) in base 2:
+// Per reaction (32 B), reactions stored sorted by (shape, reversibility)
+// (see ShapeRun).  Arrhenius layer (Eq. 6) in base 2:
 //     log2 k_f = log2A + beta * log2 T + negEoR2 / T
-// off[0..nf) are the LDS byte offsets of the reactant molecules' species
-// rows (a species repeated nu' times), off[nf..nf+nr) those of the product
-// molecules; row offset = species * species_stride.
+// sp[0..nf) are the species of the reactant molecules (a species repeated
+// nu' times), sp[nf..nf+nr) those of the product molecules.  The record is
+// read with one scalar load per wave: the indices are bytes, so a mechanism
+// has at most kMaxSpecies species.
 struct RxnRec {
     double log2A;      // log2 of A in SI-kmol units
     double beta;
     double negEoR2;    // -(E/R) * log2(e), K
-    double rev;        // 1 reversible, 0 irreversible
-    uint32_t off[8];
+    uint8_t sp[8];
 };
-static_assert(sizeof(RxnRec) == 64, "RxnRec layout");
+static_assert(sizeof(RxnRec) == 32, "RxnRec layout");
 
+constexpr int kMaxSpecies = 256;
 constexpr int kMaxSide = 4;      // molecules per side
-constexpr int kMaxRuns = 16;     // shapes (nf, nr) in 1..4 x 1..4
+constexpr int kMaxRuns = 32;     // (nf, nr) in 1..4 x 1..4, reversible or not
 
+// Reactions [start, start + count) share nf, nr and reversibility
+// (rev 1 reversible, 0 irreversible).
 struct ShapeRun {
     int32_t nf, nr, start, count;
+    double rev;
 };
 
 // NASA-7 coefficients a1..a7 per species and range (112 B), for enthalpy
@@ -56,12 +60,13 @@ struct ThermoRec {
     double hi[7];
 };
 
-// Per reaction, in the same shape-sorted order as RxnRec (32 B): species of
-// the molecule slots (reactants first), molecule counts, and E/R.
+// Per reaction, in the same sorted order as RxnRec (32 B): species of the
+// molecule slots (reactants first), molecule counts, reversibility and E/R.
 struct RxnAux {
     uint16_t sp[8];
     uint8_t nf, nr;
-    uint8_t pad[6];
+    uint8_t rev;       // 1 reversible, 0 irreversible
+    uint8_t pad[5];
     double EoR;        // E/R, K
 };
 static_assert(sizeof(RxnAux) == 32, "RxnAux layout");

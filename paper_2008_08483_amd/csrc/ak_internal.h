@@ -37,8 +37,9 @@ hipError_t source_launch(const MechView &m, bool f64, const void *T, const void 
                          const void *Y, int64_t ldY, int64_t n, void *om, int64_t ldO,
                          hipStream_t st);
 
+// max_ns: the largest species count among the batch's mechanisms
 hipError_t source_batch_launch(bool f64, const BatchDesc *d_desc, int nreq, int64_t blocks,
-                               size_t lds, hipStream_t st);
+                               size_t lds, int max_ns, hipStream_t st);
 size_t jacobian_lds_bytes(int ns);
 hipError_t jacobian_launch(const MechView &m, int lds_max, bool f64, const void *T, const void *P,
                            const void *Y, int64_t ldY, int64_t n, void *J, int64_t ldJ,

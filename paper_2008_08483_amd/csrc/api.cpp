@@ -89,8 +89,11 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     if (!d || !out) return set_error(AK_EINVAL, "ak_load_mechanism: null argument");
     *out = nullptr;
     const int ns = d->n_species, nr = d->n_reactions;
-    if (ns < 1 || ns > 1024 || nr < 1)
+    if (ns < 1 || nr < 1)
         return set_error(AK_EINVAL, "ak_load_mechanism: bad sizes ns=%d nr=%d", ns, nr);
+    if (ns > kMaxSpecies)
+        return set_error(AK_EUNSUPPORTED, "ak_load_mechanism: %d species, at most %d supported",
+                         ns, kMaxSpecies);
     if (!d->W || !d->nu_f || !d->nu_r || !d->ln_A || !d->beta || !d->Ea || !d->nasa_low ||
         !d->nasa_high || !d->T_mid)
         return set_error(AK_EINVAL, "ak_load_mechanism: null array in descriptor");
@@ -122,7 +125,6 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     if (tile < 16)
         return set_error(AK_EUNSUPPORTED, "ak_load_mechanism: %d species do not fit the LDS tile",
                          ns);
-    const uint32_t sstride = species_stride(tile);
 
     std::vector<RxnRec> rx(nr);
     std::vector<RxnAux> aux(nr);
@@ -131,7 +133,7 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
         RxnRec &r = rx[j];
         std::memset(&r, 0, sizeof r);
         int nf = 0, np = 0, order = 0;
-        uint32_t reac[kMaxSide], prod[kMaxSide];
+        int reac[kMaxSide], prod[kMaxSide];
         for (int k = 0; k < ns; ++k) {
             const int a = d->nu_f[(size_t)j * ns + k], b = d->nu_r[(size_t)j * ns + k];
             if (a < 0 || b < 0)
@@ -140,28 +142,30 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
             if (nf + a > kMaxSide || np + b > kMaxSide)
                 return set_error(AK_EUNSUPPORTED,
                                  "reaction %d: more than %d molecules on one side", j, kMaxSide);
-            for (int t = 0; t < a; ++t) reac[nf++] = (uint32_t)k * sstride;
-            for (int t = 0; t < b; ++t) prod[np++] = (uint32_t)k * sstride;
+            for (int t = 0; t < a; ++t) reac[nf++] = k;
+            for (int t = 0; t < b; ++t) prod[np++] = k;
         }
         if (nf == 0 || np == 0)
             return set_error(AK_EUNSUPPORTED, "reaction %d: empty reactant or product side", j);
-        for (int t = 0; t < nf; ++t) r.off[t] = reac[t];
-        for (int t = 0; t < np; ++t) r.off[nf + t] = prod[t];
+        for (int t = 0; t < nf; ++t) r.sp[t] = (uint8_t)reac[t];
+        for (int t = 0; t < np; ++t) r.sp[nf + t] = (uint8_t)prod[t];
         // Arrhenius parameters: A from (cm^3/mol)^(order-1)/s to (m^3/kmol)^(order-1)/s
         r.log2A = (d->ln_A[j] + (order - 1) * std::log(1e-3)) * kLog2e;
         r.beta = d->beta[j];
         r.negEoR2 = -(d->Ea[j] * kCal / kRuMol) * kLog2e;
-        r.rev = (d->reversible == nullptr || d->reversible[j]) ? 1.0 : 0.0;
-        shape[j] = (nf - 1) * kMaxSide + (np - 1);
+        const bool rev = d->reversible == nullptr || d->reversible[j];
+        // sort key: shape, then reversible before irreversible
+        shape[j] = ((nf - 1) * kMaxSide + (np - 1)) * 2 + (rev ? 0 : 1);
         RxnAux &x = aux[j];
         std::memset(&x, 0, sizeof x);
-        for (int t = 0; t < nf; ++t) x.sp[t] = (uint16_t)(reac[t] / sstride);
-        for (int t = 0; t < np; ++t) x.sp[nf + t] = (uint16_t)(prod[t] / sstride);
+        for (int t = 0; t < nf; ++t) x.sp[t] = (uint16_t)reac[t];
+        for (int t = 0; t < np; ++t) x.sp[nf + t] = (uint16_t)prod[t];
         x.nf = (uint8_t)nf;
         x.nr = (uint8_t)np;
+        x.rev = rev ? 1 : 0;
         x.EoR = d->Ea[j] * kCal / kRuMol;
     }
-    // sort reactions by shape so each wave runs a uniform code path per run
+    // sort reactions by shape so that each wave runs one code path per run
     std::vector<int> order(nr);
     for (int j = 0; j < nr; ++j) order[j] = j;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return shape[a] < shape[b]; });
@@ -183,11 +187,11 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
         rxs[i] = rx[order[i]];
         auxs[i] = aux[order[i]];
         const int s = shape[order[i]];
-        if (view.nruns == 0 || (view.runs[view.nruns - 1].nf - 1) * kMaxSide +
-                                       (view.runs[view.nruns - 1].nr - 1) != s) {
+        if (i == 0 || shape[order[i - 1]] != s) {
             ShapeRun &run = view.runs[view.nruns++];
-            run.nf = s / kMaxSide + 1;
-            run.nr = s % kMaxSide + 1;
+            run.nf = s / 2 / kMaxSide + 1;
+            run.nr = s / 2 % kMaxSide + 1;
+            run.rev = (s & 1) ? 0.0 : 1.0;
             run.start = i;
             run.count = 0;
         }

@@ -145,7 +145,8 @@ __global__ __launch_bounds__(64 * kJacWaves) void jacobian_kernel(MechView m,
                     }
                 }
             }
-            const double qf = E * Ar, qr = R.rev * E * Ap;
+            const double rev = X.rev;
+            const double qf = E * Ar, qr = rev * E * Ap;
             const double dlnkf = (R.beta + X.EoR * invT) * invT;
             const double dn = (double)(nr - nf);
             const double dqT = qf * (dlnkf - nf * invT) - qr * (dlnkf - (dH - dn) * invT - nr * invT);
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(64 * kJacWaves) void jacobian_kernel(MechView m,
                     for (int l = 0; l < 8; ++l)
                         if (l != i && l < nm && ((l < nf) == reac)) loo *= a[l];
                     const double base = E * sw[X.sp[i]] * loo;
-                    dq[i] = reac ? base : -R.rev * base;
+                    dq[i] = reac ? base : -rev * base;
                 }
             }
 #pragma unroll
@@ -311,7 +312,8 @@ __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int til
                 qbar += e[2];
             }
         }
-        const double qf = Ek * Ar, qr = R.rev * Ek * Ap;
+        const double rev = X.rev;
+        const double qf = Ek * Ar, qr = rev * Ek * Ap;
         const int nr = nm - nf;
         const double dlnkf = (R.beta + X.EoR * invT) * invT;
         const double dqT = qf * (dlnkf - nf * invT) - qr * (dlnkf - (dH - (double)(nr - nf)) * invT - nr * invT);
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int til
             const bool reac = i < nf;
             for (int l = 0; l < nm; ++l)
                 if (l != i && ((l < nf) == reac)) loo *= a[l];
-            const double d = reac ? Ek * loo : -R.rev * Ek * loo;   // d q / d a_slot
+            const double d = reac ? Ek * loo : -rev * Ek * loo;   // d q / d a_slot
             if (active) lds_addd(E(X.sp[i]) + 4, qbar * d);
         }
     }

@@ -121,6 +121,7 @@ struct GpuExec {
             int nd = 0;
             int64_t blocks = 0;
             size_t lds = 0;
+            int max_ns = 0;
             for (Request *r : reqs) {
                 if (r->prec != prec) continue;
                 const ak_mechanism *m = (const ak_mechanism *)r->mech;
@@ -136,11 +137,13 @@ struct GpuExec {
                 d.block_begin = blocks;
                 blocks += (r->n + m->view.tile - 1) / m->view.tile;
                 lds = std::max(lds, source_lds_bytes(m->ns, m->view.tile));
+                max_ns = std::max(max_ns, m->ns);
             }
             if (!nd) continue;
             ok(hipMemcpyAsync(s->d_desc[p], s->h_desc[p], sizeof(BatchDesc) * nd,
                               hipMemcpyHostToDevice, s->st));
-            ok(source_batch_launch(prec == AK_FP64, s->d_desc[p], nd, blocks, lds, s->st));
+            ok(source_batch_launch(prec == AK_FP64, s->d_desc[p], nd, blocks, lds, max_ns,
+                                   s->st));
             s->nlaunch++;
         }
         for (Request *r : reqs) {

@@ -72,36 +72,18 @@ __device__ __forceinline__ void exp2_pair(double g, double &pos, double &neg)
 // LDS pipeline on gfx950 far more than double ones (measured), and double
 // accumulation costs nothing in accuracy.
 
-// Reaction record held in VGPRs.  Records are fetched with vector loads
-// (all lanes read the same address): scalar loads would share the LGKM
-// counter with the LDS traffic, and every wait for a record would then also
-// wait for all outstanding LDS reads and atomics.
-struct RxnV {
-    double log2A, beta, negEoR2, rev;
-    uint32_t off[8];
-};
-
-__device__ __forceinline__ RxnV load_rxn(const RxnRec *rx, int j, uint32_t lane_zero)
-{
-    // lane_zero is 0 at run time but not known uniform to the compiler,
-    // which keeps this a vector load
-    const uint4 *p = (const uint4 *)(rx + j + lane_zero);
-    const uint4 w0 = p[0], w1 = p[1], w2 = p[2], w3 = p[3];
-    RxnV r;
-    r.log2A = __builtin_bit_cast(double, make_uint2(w0.x, w0.y));
-    r.beta = __builtin_bit_cast(double, make_uint2(w0.z, w0.w));
-    r.negEoR2 = __builtin_bit_cast(double, make_uint2(w1.x, w1.y));
-    r.rev = __builtin_bit_cast(double, make_uint2(w1.z, w1.w));
-    r.off[0] = w2.x; r.off[1] = w2.y; r.off[2] = w2.z; r.off[3] = w2.w;
-    r.off[4] = w3.x; r.off[5] = w3.y; r.off[6] = w3.z; r.off[7] = w3.w;
-    return r;
-}
+// Reaction records are wave-uniform and read with scalar loads into SGPRs.
+// (Vector loads of a uniform address return the same 32 bytes to all 64
+// lanes and saturate the texture data path; measured.)  A scalar load
+// shares its wait counter with LDS instructions, but every wait for the next
+// pair's records comes where the loop waits for its LDS reads anyway.
 
 // One reaction's rate of progress q = q_f - q_r for this lane's cell, from
 // the LDS tile.  Also returns the LDS addresses of its molecules' entries.
 template <bool F64, int NF, int NR>
-__device__ __forceinline__ double rate_of_progress(const RxnV &R, const unsigned char *lds,
-                                                   uint32_t lane_off, const Cell c,
+__device__ __forceinline__ double rate_of_progress(const RxnRec &R, double rev,
+                                                   const unsigned char *lds, uint32_t lane_off,
+                                                   uint32_t sstride, const Cell c,
                                                    uint32_t (&addr)[NF + NR])
 {
     // Arrhenius layer, base 2 (Eq. 6)
@@ -109,7 +91,7 @@ __device__ __forceinline__ double rate_of_progress(const RxnV &R, const unsigned
     double Ar, Vr, Ap;
 #pragma unroll
     for (int i = 0; i < NF; ++i) {
-        addr[i] = lane_off + R.off[i];
+        addr[i] = lane_off + (uint32_t)R.sp[i] * sstride;
         const double *e = (const double *)(lds + addr[i]);
         const double a = e[0], v = e[1];
         Ar = i ? Ar * a : a;
@@ -117,12 +99,12 @@ __device__ __forceinline__ double rate_of_progress(const RxnV &R, const unsigned
     }
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        addr[NF + i] = lane_off + R.off[NF + i];
+        addr[NF + i] = lane_off + (uint32_t)R.sp[NF + i] * sstride;
         const double a = *(const double *)(lds + addr[NF + i]);
         Ap = i ? Ap * a : a;
     }
     // prod_reac a^nu' - rev * prod_prod a^nu''  (double: no cancellation loss)
-    const double D = __builtin_fma(-R.rev, Ap, Ar);
+    const double D = __builtin_fma(-rev, Ap, Ar);
     if constexpr (F64) {
         return exp2(t) * (Vr * D);
     } else {
@@ -141,44 +123,63 @@ __device__ __forceinline__ void lds_add(double *p, double x)
 }
 
 // Production layer (Eq. 2): -q into each reactant molecule's accumulator,
-// +q into each product molecule's.
+// +q into each product molecule's (nq = -q).
 template <int NF, int NR>
 __device__ __forceinline__ void scatter(unsigned char *lds, const uint32_t (&addr)[NF + NR],
-                                        double q)
+                                        double q, double nq)
 {
 #pragma unroll
-    for (int i = 0; i < NF; ++i) lds_add((double *)(lds + addr[i] + 16), -q);
+    for (int i = 0; i < NF; ++i) lds_add((double *)(lds + addr[i] + 16), nq);
 #pragma unroll
     for (int i = 0; i < NR; ++i) lds_add((double *)(lds + addr[NF + i] + 16), q);
 }
 
-// Reactions of one shape run: this wave takes reactions start+wave,
-// start+wave+WAVES, ...; two at a time so that their loads overlap, with the
-// next pair's records fetched while the current pair computes.
+// An LDS atomic reads its data VGPRs when the LDS executes it, so the
+// compiler waits for outstanding atomics before it reuses their data
+// registers.  Keeping a pair's q / -q registers allocated until the next
+// pair has waited for its own LDS reads (which drains the earlier atomics)
+// removes those waits.  The asm statement emits nothing and passes x through
+// unchanged; it is not volatile and touches no memory, so the record loads
+// stay scalar.
+__device__ __forceinline__ double hold(double x, double a, double b, double c, double d)
+{
+    asm("" : "+v"(x) : "v"(a), "v"(b), "v"(c), "v"(d));
+    return x;
+}
+
+// Reactions of one run: this wave takes reactions start+wave,
+// start+wave+WAVES, ...; two at a time so that their LDS reads overlap, with
+// the next pair's records requested while the current pair computes.
 template <bool F64, int NF, int NR, int WAVES>
 __device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun run, int wave,
                                              unsigned char *lds, uint32_t lane_off,
-                                             const Cell c, bool active, uint32_t lane_zero)
+                                             uint32_t sstride, const Cell c)
 {
     const int end = run.start + run.count;
     int j = run.start + wave;
     if (j >= end) return;
-    RxnV r1 = load_rxn(m.rx, j, lane_zero);
-    RxnV r2 = load_rxn(m.rx, j + WAVES < end ? j + WAVES : j, lane_zero);
+    const double rev = run.rev;
+    RxnRec r1 = m.rx[j];
+    RxnRec r2 = m.rx[j + WAVES < end ? j + WAVES : j];
+    double h1 = 0.0, h2 = 0.0, h3 = 0.0, h4 = 0.0;
     for (; j < end; j += 2 * WAVES) {
         const bool two = j + WAVES < end;
         const int jn = j + 2 * WAVES;
         const int jn1 = jn < end ? jn : j;
         const int jn2 = jn + WAVES < end ? jn + WAVES : jn1;
-        const RxnV n1 = load_rxn(m.rx, jn1, lane_zero);
-        const RxnV n2 = load_rxn(m.rx, jn2, lane_zero);
+        const RxnRec n1 = m.rx[jn1];
+        const RxnRec n2 = m.rx[jn2];
         uint32_t a1[NF + NR], a2[NF + NR];
-        const double q1 = rate_of_progress<F64, NF, NR>(r1, lds, lane_off, c, a1);
-        const double q2 = rate_of_progress<F64, NF, NR>(r2, lds, lane_off, c, a2);
-        if (active) {
-            scatter<NF, NR>(lds, a1, q1);
-            if (two) scatter<NF, NR>(lds, a2, q2);
-        }
+        const double q1 = hold(rate_of_progress<F64, NF, NR>(r1, rev, lds, lane_off, sstride, c, a1),
+                               h1, h2, h3, h4);
+        const double q2 = rate_of_progress<F64, NF, NR>(r2, rev, lds, lane_off, sstride, c, a2);
+        const double nq1 = -q1, nq2 = -q2;
+        scatter<NF, NR>(lds, a1, q1, nq1);
+        if (two) scatter<NF, NR>(lds, a2, q2, nq2);
+        h1 = q1;
+        h2 = nq1;
+        h3 = q2;
+        h4 = nq2;
         r1 = n1;
         r2 = n2;
     }
@@ -186,15 +187,14 @@ __device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun r
 
 template <bool F64, int WAVES>
 __device__ __forceinline__ void all_reactions(const MechView &m, int wave, unsigned char *lds,
-                                              uint32_t lane_off, const Cell c, bool active,
-                                              uint32_t lane_zero)
+                                              uint32_t lane_off, uint32_t sstride, const Cell c)
 {
     for (int r = 0; r < m.nruns; ++r) {
         const ShapeRun run = m.runs[r];
         const int s = (run.nf - 1) * 4 + (run.nr - 1);
 #define AK_CASE(a, b)                                                                          \
     case (a - 1) * 4 + (b - 1):                                                                \
-        reaction_run<F64, a, b, WAVES>(m, run, wave, lds, lane_off, c, active, lane_zero);     \
+        reaction_run<F64, a, b, WAVES>(m, run, wave, lds, lane_off, sstride, c);               \
         break;
         switch (s) {
             AK_CASE(1, 1) AK_CASE(1, 2) AK_CASE(1, 3) AK_CASE(1, 4)
@@ -207,39 +207,68 @@ __device__ __forceinline__ void all_reactions(const MechView &m, int wave, unsig
     }
 }
 
+// Inputs of one tile, loaded into registers before any LDS work so that all
+// of a wave's HBM reads are in flight at once: this wave's species
+// k = wave + i * WAVES (i < KMAX, k < ns), and T, P.  Lanes past the last
+// cell read nothing and take harmless defaults.
+template <typename IO, int KMAX>
+struct TileIn {
+    IO y[KMAX];
+    IO T, P;
+};
+
+template <typename IO, int KMAX, int WAVES>
+__device__ __forceinline__ void load_tile(const MechView &m, const IO *__restrict__ T,
+                                          const IO *__restrict__ P, const IO *__restrict__ Y,
+                                          int64_t ldY, int64_t n, int64_t tile_idx, int lane,
+                                          int wave, TileIn<IO, KMAX> &in)
+{
+    const int64_t cell = tile_idx * m.tile + lane;
+    const bool valid = cell < n;
+    in.T = valid ? T[cell] : (IO)1000.0;
+    in.P = valid ? P[cell] : (IO)1.0e5;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        const int k = wave + i * WAVES;
+        in.y[i] = (valid && k < m.ns) ? Y[k * ldY + cell] : (IO)1.0;
+    }
+}
+
 // One tile of m.tile cells starting at cell tile_idx * m.tile (IO: float for
-// AK_FP32, double for AK_FP64); block = 64 * WAVES threads; dynamic LDS =
-// ns * m.tile * 24 B.  lane_zero must be 0 (see load_rxn).
-template <typename IO, bool F64, int WAVES>
+// AK_FP32, double for AK_FP64); block = 64 * WAVES threads, lanes >= m.tile
+// already gone; dynamic LDS = ns * m.tile * 24 B; ns <= KMAX * WAVES.
+// `in` holds the tile's inputs (see load_tile).
+template <typename IO, bool F64, int WAVES, int KMAX>
 __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restrict__ T,
                                             const IO *__restrict__ P,
                                             const IO *__restrict__ Y, int64_t ldY, int64_t n,
-                                            IO *__restrict__ om, int64_t ldO, uint32_t zero,
-                                            int64_t tile_idx, unsigned char *lds)
+                                            IO *__restrict__ om, int64_t ldO, int64_t tile_idx,
+                                            const TileIn<IO, KMAX> &in, unsigned char *lds)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tile = m.tile;
-    const bool active = lane < tile;               // owns an LDS column
     const int64_t cell = tile_idx * tile + lane;
-    const bool valid = active && cell < n;          // owns a real cell
+    const bool valid = cell < n;                    // owns a real cell
     const uint32_t sstride = species_stride(tile);
-    // lanes past the tile read column 0 (harmless) and never write
-    const uint32_t lane_off = active ? (uint32_t)lane * kEntry : 0u;
-    const uint32_t lane_zero = (uint32_t)threadIdx.x & zero;
+    const uint32_t lane_off = (uint32_t)lane * kEntry;
 
     // (1) this wave's species: y_k = max(Y_k, 0) / W_k into the a-slot, and
     //     a partial mixture sum (NaN if any input is not finite)
     double psum = 0.0;
-    for (int k = wave; k < m.ns; k += WAVES) {
-        const double y = valid ? (double)Y[k * ldY + cell] : 1.0;
-        const double yw = __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
-        psum += __builtin_isfinite(y) ? yw : __builtin_nan("");
-        if (active) *(double *)(lds + (uint32_t)k * sstride + lane_off) = yw;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        const int k = wave + i * WAVES;
+        if (k < m.ns) {
+            const double y = (double)in.y[i];
+            const double yw = __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
+            psum += __builtin_isfinite(y) ? yw : __builtin_nan("");
+            *(double *)(lds + (uint32_t)k * sstride + lane_off) = yw;
+        }
     }
-    if (wave < m.ns && active) *(double *)(lds + (uint32_t)wave * sstride + lane_off + 16) = psum;
-    double Tc = valid ? (double)T[cell] : 1000.0;
-    double Pc = valid ? (double)P[cell] : 1.0e5;
+    if (wave < m.ns) *(double *)(lds + (uint32_t)wave * sstride + lane_off + 16) = psum;
+    double Tc = (double)in.T;
+    double Pc = (double)in.P;
     const bool tp_bad = !(Tc > 0.0) || !(Pc > 0.0) || !__builtin_isfinite(Tc) ||
                         !__builtin_isfinite(Pc);
     if (tp_bad) {
@@ -283,13 +312,11 @@ __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restr
         }
         double w, v;
         exp2_pair<F64 ? 12 : 10>(g2, w, v);
-        if (active) {
-            double *e = (double *)(lds + (uint32_t)k * sstride + lane_off);
-            const double yw = bad ? 0.0 : e[0];
-            e[0] = rho_hat * yw * w;
-            e[1] = v;
-            e[2] = 0.0;
-        }
+        double *e = (double *)(lds + (uint32_t)k * sstride + lane_off);
+        const double yw = bad ? 0.0 : e[0];
+        e[0] = rho_hat * yw * w;
+        e[1] = v;
+        e[2] = 0.0;
     }
     __syncthreads();
 
@@ -297,7 +324,7 @@ __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restr
     Cell cc;
     cc.log2T = lnT * kLog2e;
     cc.invT = invT;
-    all_reactions<F64, WAVES>(m, wave, lds, lane_off, cc, active, lane_zero);
+    all_reactions<F64, WAVES>(m, wave, lds, lane_off, sstride, cc);
     __syncthreads();
 
     // (5) store omega (species-major, coalesced over cells)
@@ -314,24 +341,38 @@ __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restr
 // Two 8-wave workgroups share a CU (4 waves per SIMD) only if each wave fits
 // in 128 VGPRs; without the cap the FP64 instantiation takes a few more and
 // drops to one workgroup per CU.
-#define AK_TWO_TILES_PER_CU __attribute__((amdgpu_waves_per_eu(4)))
+// With 32 species per wave held in registers (more than 128 species, when
+// the LDS holds one tile per CU anyway) the cap is relaxed to 256 VGPRs.
+#define AK_TWO_TILES_PER_CU __attribute__((amdgpu_waves_per_eu(KMAX > 16 ? 2 : 4)))
 
-template <typename IO, bool F64, int WAVES>
+// One tile per workgroup.  (A persistent variant that fetched the next
+// tile's inputs during the reactions ran slower at 53/325: two resident
+// workgroups per CU already overlap one tile's loads with the other's
+// reactions, and the tile loop kept the kernel arguments live in SGPRs,
+// which spilled inside the reaction loop.)
+template <typename IO, bool F64, int WAVES, int KMAX>
 __global__ __launch_bounds__(64 * WAVES) AK_TWO_TILES_PER_CU void
 source_kernel(MechView m, const IO *__restrict__ T, const IO *__restrict__ P,
-              const IO *__restrict__ Y, int64_t ldY, int64_t n, IO *__restrict__ om, int64_t ldO,
-              uint32_t zero)
+              const IO *__restrict__ Y, int64_t ldY, int64_t n, IO *__restrict__ om, int64_t ldO)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    source_tile<IO, F64, WAVES>(m, T, P, Y, ldY, n, om, ldO, zero, blockIdx.x, lds);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // Lanes past a tile narrower than 64 own no LDS column and leave at
+    // once; every wave keeps lanes 0..tile-1, so every wave still reaches
+    // each barrier, and no later branch has to mask the idle lanes.
+    if (lane >= m.tile) return;
+    TileIn<IO, KMAX> in;
+    load_tile<IO, KMAX, WAVES>(m, T, P, Y, ldY, n, blockIdx.x, lane, wave, in);
+    source_tile<IO, F64, WAVES, KMAX>(m, T, P, Y, ldY, n, om, ldO, blockIdx.x, in, lds);
 }
 
 // Several requests in one launch: request r owns workgroups
 // [d[r].block_begin, d[r].block_begin + ceil(n_r / tile_r)); each workgroup
 // finds its request in the descriptor table and runs that request's tile.
-template <typename IO, bool F64, int WAVES>
+template <typename IO, bool F64, int WAVES, int KMAX>
 __global__ __launch_bounds__(64 * WAVES) AK_TWO_TILES_PER_CU void
-source_batch_kernel(const BatchDesc *__restrict__ d, int nreq, uint32_t zero)
+source_batch_kernel(const BatchDesc *__restrict__ d, int nreq)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int64_t b = blockIdx.x;
@@ -341,60 +382,99 @@ source_batch_kernel(const BatchDesc *__restrict__ d, int nreq, uint32_t zero)
         if (d[mid].block_begin <= b) lo = mid; else hi = mid - 1;
     }
     const BatchDesc &r = d[lo];
-    source_tile<IO, F64, WAVES>(r.m, (const IO *)r.T, (const IO *)r.P, (const IO *)r.Y, r.ldY,
-                                r.n, (IO *)r.om, r.ldO, zero, b - r.block_begin, lds);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (lane >= r.m.tile) return;
+    TileIn<IO, KMAX> in;
+    load_tile<IO, KMAX, WAVES>(r.m, (const IO *)r.T, (const IO *)r.P, (const IO *)r.Y, r.ldY,
+                               r.n, b - r.block_begin, lane, wave, in);
+    source_tile<IO, F64, WAVES, KMAX>(r.m, (const IO *)r.T, (const IO *)r.P, (const IO *)r.Y,
+                                      r.ldY, r.n, (IO *)r.om, r.ldO, b - r.block_begin, in, lds);
 }
 
 // ---------------------------------------------------------------------------
 // host-side launchers
 
-template <typename IO, bool F64, int WAVES>
+// species per wave held in registers: ns <= KMAX * WAVES
+static int kmax_for(int ns)
+{
+    const int per = (ns + AK_SOURCE_WAVES - 1) / AK_SOURCE_WAVES;
+    return per <= 2 ? 2 : per <= 8 ? 8 : per <= 16 ? 16 : 32;
+}
+
+template <typename IO, bool F64, int WAVES, int KMAX>
 static hipError_t launch_source(const MechView &m, const void *T, const void *P, const void *Y,
                                 int64_t ldY, int64_t n, void *om, int64_t ldO, hipStream_t st)
 {
     const size_t lds = (size_t)m.ns * species_stride(m.tile);
-    auto fn = source_kernel<IO, F64, WAVES>;
+    auto fn = source_kernel<IO, F64, WAVES, KMAX>;
     hipError_t e = hipFuncSetAttribute((const void *)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = (n + m.tile - 1) / m.tile;
+    if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * WAVES), lds, st, m,
-                       (const IO *)T, (const IO *)P, (const IO *)Y, ldY, n, (IO *)om, ldO, 0u);
+                       (const IO *)T, (const IO *)P, (const IO *)Y, ldY, n, (IO *)om, ldO);
     return hipGetLastError();
+}
+
+template <typename IO, bool F64>
+static hipError_t launch_source_k(const MechView &m, const void *T, const void *P, const void *Y,
+                                  int64_t ldY, int64_t n, void *om, int64_t ldO, hipStream_t st)
+{
+    constexpr int W = AK_SOURCE_WAVES;
+    switch (kmax_for(m.ns)) {
+        case 2: return launch_source<IO, F64, W, 2>(m, T, P, Y, ldY, n, om, ldO, st);
+        case 8: return launch_source<IO, F64, W, 8>(m, T, P, Y, ldY, n, om, ldO, st);
+        case 16: return launch_source<IO, F64, W, 16>(m, T, P, Y, ldY, n, om, ldO, st);
+        default: return launch_source<IO, F64, W, 32>(m, T, P, Y, ldY, n, om, ldO, st);
+    }
 }
 
 size_t source_lds_bytes(int ns, int tile) { return (size_t)ns * species_stride(tile); }
 
+template <typename IO, bool F64, int KMAX>
+static hipError_t launch_batch(const BatchDesc *d_desc, int nreq, int64_t blocks, size_t lds,
+                               hipStream_t st)
+{
+    auto fn = source_batch_kernel<IO, F64, AK_SOURCE_WAVES, KMAX>;
+    hipError_t e = hipFuncSetAttribute((const void *)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * AK_SOURCE_WAVES), lds, st, d_desc,
+                       nreq);
+    return hipGetLastError();
+}
+
 hipError_t source_batch_launch(bool f64, const BatchDesc *d_desc, int nreq, int64_t blocks,
-                               size_t lds, hipStream_t st)
+                               size_t lds, int max_ns, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const int k = kmax_for(max_ns);
     if (f64) {
-        auto fn = source_batch_kernel<double, true, AK_SOURCE_WAVES>;
-        hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * AK_SOURCE_WAVES), lds, st, d_desc,
-                           nreq, 0u);
-    } else {
-        auto fn = source_batch_kernel<float, false, AK_SOURCE_WAVES>;
-        hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * AK_SOURCE_WAVES), lds, st, d_desc,
-                           nreq, 0u);
+        switch (k) {
+            case 2: return launch_batch<double, true, 2>(d_desc, nreq, blocks, lds, st);
+            case 8: return launch_batch<double, true, 8>(d_desc, nreq, blocks, lds, st);
+            case 16: return launch_batch<double, true, 16>(d_desc, nreq, blocks, lds, st);
+            default: return launch_batch<double, true, 32>(d_desc, nreq, blocks, lds, st);
+        }
     }
-    return hipGetLastError();
+    switch (k) {
+        case 2: return launch_batch<float, false, 2>(d_desc, nreq, blocks, lds, st);
+        case 8: return launch_batch<float, false, 8>(d_desc, nreq, blocks, lds, st);
+        case 16: return launch_batch<float, false, 16>(d_desc, nreq, blocks, lds, st);
+        default: return launch_batch<float, false, 32>(d_desc, nreq, blocks, lds, st);
+    }
 }
 
 hipError_t source_launch(const MechView &m, bool f64, const void *T, const void *P,
                          const void *Y, int64_t ldY, int64_t n, void *om, int64_t ldO,
                          hipStream_t st)
 {
-    if (f64) return launch_source<double, true, AK_SOURCE_WAVES>(m, T, P, Y, ldY, n, om, ldO, st);
-    return launch_source<float, false, AK_SOURCE_WAVES>(m, T, P, Y, ldY, n, om, ldO, st);
+    if (f64) return launch_source_k<double, true>(m, T, P, Y, ldY, n, om, ldO, st);
+    return launch_source_k<float, false>(m, T, P, Y, ldY, n, om, ldO, st);
 }
 
 }  // namespace ak

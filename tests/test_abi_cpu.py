@@ -43,6 +43,9 @@ def test_argument_errors_without_gpu(lib):
     d = annkin.MechanismDesc()
     d.n_species = 0
     assert lib.ak_load_mechanism(C.byref(d), 0, C.byref(out)) == -1
+    d.n_species, d.n_reactions = 257, 1          # species indices are bytes
+    assert lib.ak_load_mechanism(C.byref(d), 0, C.byref(out)) == -7
+    assert b"257 species" in lib.ak_last_error()
     assert lib.ak_eval_source(None, 0, None, None, None, 0, 0, None, 0, None) == -1
     assert lib.ak_free_mechanism(None) == 0
     assert lib.ak_mechanism_n_species(None) == -1

@@ -105,6 +105,29 @@ def test_jacobian_111_species(torch, ak):
     _jac_check(src, T, P, Y, J.cpu().numpy(), 1e-11)
 
 
+def test_jacobian_and_vjp_irreversible(torch, ak):
+    """Irreversible reactions (q_r = 0) in both derivative kernels."""
+    import dataclasses
+    base = synth.make_mechanism(53, 325, seed=1)
+    rev = base.reversible.copy()
+    rev[np.random.default_rng(77).random(325) < 0.3] = 0
+    src = dataclasses.replace(base, reversible=rev)
+    m = ak.Mechanism(src)
+    T, P, Y = synth.make_states(src, 300, 79)
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    J = ak.eval_jacobian(m, Tt, Pt, Yt)
+    g = np.random.default_rng(12).standard_normal((53, 300))
+    gY, gT = ak.eval_vjp(m, Tt, Pt, Yt, *_dev(torch, torch.float64, g))
+    torch.cuda.synchronize()
+    Jr, Ja = _jac_check(src, T, P, Y, J.cpu().numpy(), 1e-11)
+    Jr, Ja = Jr[:, :53, :].astype(np.float64), Ja[:, :53, :].astype(np.float64)
+    ref = np.einsum("ik,ikc->ic", g.T, Jr)
+    scale = np.einsum("ik,ikc->ic", np.abs(g.T), Ja)
+    got = np.concatenate([gY.cpu().numpy().T, gT.cpu().numpy()[:, None]], axis=1)
+    assert float((np.abs(got - ref) / scale).max()) <= 1e-11
+    m.close()
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_vjp_against_oracle_jacobian(torch, ak, dt):
     src, m = _mech(ak, 53, 325)

@@ -272,6 +272,46 @@ def test_c2_fp64(torch, ak):
     _check64(src, T, P, Y, om)
 
 
+def _with_irreversible(src, frac, seed):
+    """The mechanism with a seeded fraction of its reactions made irreversible
+    (q_r = 0, Sec. 2)."""
+    import dataclasses
+    rev = src.reversible.copy()
+    rev[np.random.default_rng(seed).random(rev.shape[0]) < frac] = 0
+    return dataclasses.replace(src, reversible=rev)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_irreversible_reactions(torch, ak, prec):
+    """Mixed reversible / irreversible reactions: the kernel groups reactions
+    by (shape, reversibility), so both kinds of run are exercised."""
+    src = _with_irreversible(synth.make_mechanism(53, 325, seed=1), 0.3, 77)
+    assert 0 < int(src.reversible.sum()) < 325
+    m = ak.Mechanism(src)
+    dt = np.float32 if prec == "fp32" else np.float64
+    T, P, Y = synth.make_states(src, 2500, 78, dtype=dt)
+    if prec == "fp32":
+        _check32(src, T, P, Y, _run(torch, ak, m, T, P, Y, torch.float32))
+    else:
+        _check64(src, T, P, Y, _run(torch, ak, m, T, P, Y, torch.float64))
+    m.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_200_species(torch, ak, prec):
+    """More than 128 species: 32 species per wave in registers and an LDS
+    tile of 34 cells, so the lanes past the tile leave at kernel entry."""
+    src = synth.make_mechanism(200, 600, seed=5)
+    m = ak.Mechanism(src)
+    dt = np.float32 if prec == "fp32" else np.float64
+    T, P, Y = synth.make_states(src, 701, 55, dtype=dt)
+    if prec == "fp32":
+        _check32(src, T, P, Y, _run(torch, ak, m, T, P, Y, torch.float32))
+    else:
+        _check64(src, T, P, Y, _run(torch, ak, m, T, P, Y, torch.float64))
+    m.close()
+
+
 def test_abi_argument_errors(torch, ak):
     import ctypes as C
     src, m = _mech(ak, 9, 21)
