@@ -72,9 +72,11 @@ typedef struct ak_mechanism ak_mechanism; /* opaque; owns its device tables */
  *   T_mid      [NS]      range switch temperature, K
  *   reversible [NR]      1 = reversible, 0 = irreversible (the indicator of
  *                        Sec. 2.4); NULL means all reversible
- * Limits: 1 <= NS <= 1024, NR >= 1, at most 4 reactant and 4 product
- * molecules per reaction counting multiplicity (sum of nu' <= 4,
- * sum of nu'' <= 4); otherwise AK_EUNSUPPORTED.
+ * Limits: NS >= 1 and NR >= 1 (else AK_EINVAL); NS <= 256, at most 4
+ * reactant and 4 product molecules per reaction counting multiplicity
+ * (sum of nu' <= 4, sum of nu'' <= 4), and a 16-cell LDS tile of
+ * 24 * NS bytes per cell must fit the device (NS <= 426 on gfx950);
+ * otherwise AK_EUNSUPPORTED.
  */
 typedef struct {
     int32_t n_species;
