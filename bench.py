@@ -8,8 +8,9 @@ default workload is the 53-species / 325-reaction synthetic mechanism over
 
 Prints one JSON line.  Extra keys: the FP64 path on the same workload,
 per-step latency percentiles, the FP32-vs-FP64 difference, the 65,536-cell
-precision configuration, the roofline of the kernel and the CPU oracle
-baseline.
+precision configuration, the roofline of the kernel, a saturation curve over
+batch size, the Jacobian and VJP, the serving loop, the 111/784 mechanism,
+and the CPU oracle on all host cores and on one.
 """
 
 from __future__ import annotations
@@ -93,6 +94,72 @@ def cpu_baseline(src, T, P, Y, target_s=12.0):
     return {"value": n / dt, "unit": "cells/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n} cells of the workload, double precision, "
                       f"{cores} OpenMP threads, {dt:.1f} s"}
+
+
+def cpu_single_core(src, T, P, Y, target_s=8.0):
+    """The same oracle on one host core (the paper's one-rank baseline)."""
+    import oracle
+    T64, P64, Y64 = (np.asarray(a, np.float64) for a in (T, P, Y))
+    n0 = min(512, T64.shape[0])
+    t0 = time.perf_counter()
+    oracle.source(src, T64[:n0], P64[:n0], Y64[:, :n0], n_threads=1)
+    dt0 = time.perf_counter() - t0
+    n = int(min(T64.shape[0], max(n0, n0 * target_s / max(dt0, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.source(src, T64[:n], P64[:n], Y64[:, :n], n_threads=1)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} cells of the workload, double precision, 1 thread, "
+                      f"{dt:.1f} s"}
+
+
+def kernel_ms(torch, annkin, mech, T, P, Y, reps=20, warmup=3):
+    """Median kernel time (HIP events on the launch stream) of eval_source."""
+    out = torch.empty((Y.shape[0], T.shape[0]), dtype=T.dtype, device="cuda")
+    for _ in range(warmup):
+        annkin.eval_source(mech, T, P, Y, out=out)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        annkin.eval_source(mech, T, P, Y, out=out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def saturation(torch, annkin, mech, T, P, Y):
+    """FP32 throughput against batch size: the first n cells of the
+    workload, n = 2^6 .. 2^20 (the analogue of the paper's cells-per-rank
+    sweep, Sec. 3.2)."""
+    out = []
+    for e in range(6, 21, 2):
+        n = 1 << e
+        if n > T.shape[0]:
+            break
+        ms = kernel_ms(torch, annkin, mech, T[:n], P[:n], Y[:, :n])
+        out.append({"n_cells": n, "kernel_ms": ms, "cells_per_s": n / (ms * 1e-3)})
+    return out
+
+
+def c2_bench(torch, annkin):
+    """The 111-species / 784-reaction mechanism over 2^20 cells, both paths."""
+    src, T, P, Y = synth.workload("c2", dtype=np.float32)
+    mech = annkin.Mechanism(src)
+    n = T.shape[0]
+    res = {"workload": f"{src.n_species}sp/{src.n_reactions}rxn synthetic mechanism x {n} "
+                       "cells"}
+    for name, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        Tt, Pt, Yt = (torch.tensor(a, device="cuda").to(dt) for a in (T, P, Y))
+        ms = kernel_ms(torch, annkin, mech, Tt, Pt, Yt, reps=10)
+        res[name] = {"kernel_ms": ms, "cells_per_s": n / (ms * 1e-3)}
+        del Tt, Pt, Yt
+    slots = roofline.method_slots(src.nu_f, src.nu_r)
+    res["roofline_frac_fp32"] = slots * n / (res["fp32"]["kernel_ms"] * 1e-3) / \
+        roofline.PEAK_VALU_SLOTS
+    mech.close()
+    return res
 
 
 def _serving_pools(torch, annkin, mechs, nmax):
@@ -236,6 +303,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-deriv", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--no-saturation", action="store_true")
     ap.add_argument("--only-main", action="store_true",
                     help="time only the main FP32 leg (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -314,6 +383,7 @@ def main():
 
     if args.only_main:
         args.no_fp64 = args.no_cpu_baseline = args.no_serving = args.no_deriv = True
+        args.no_c2 = args.no_saturation = True
     if not args.no_fp64:
         T64, P64, Y64 = (t.double() for t in (T32, P32, Y32))
         wall64, ms64, om64 = time_path(torch, annkin, mech, T64, P64, Y64,
@@ -342,6 +412,9 @@ def main():
                                     args.steps, args.warmup)
         result["c1_65536_cells_per_s"] = m * args.steps / wall_s
 
+    if args.workload == "c1_full" and not args.no_saturation:
+        result["saturation_fp32"] = saturation(torch, annkin, mech, T32, P32, Y32)
+
     if not args.no_deriv:
         result["differentiation"] = deriv_bench(torch, annkin)
 
@@ -350,8 +423,14 @@ def main():
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(src, T, P, Y)
+        result["cpu_oracle_1core"] = cpu_single_core(src, T, P, Y)
 
     mech.close()
+    del T32, P32, Y32, om32
+
+    if args.workload == "c1_full" and not args.no_c2:
+        result["c2_111x784"] = c2_bench(torch, annkin)
+
     print(json.dumps(result), flush=True)
 
 

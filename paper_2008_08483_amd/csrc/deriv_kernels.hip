@@ -56,39 +56,42 @@ __device__ __forceinline__ double gibbs2(const SpeciesRec &s, double lnT, double
 }
 
 // ---------------------------------------------------------------------------
-// Jacobian: one wave per cell, lane = reaction.
+// Jacobian: one workgroup of kJacWaves waves per cell, thread = reaction.
 //
-// LDS per wave (doubles): J[(ns+1)^2] then per species C, a, v, w, h, cp, dcp,
-// omega, u.  J holds G_km (and d omega_k/dT in the last column) during the
-// reaction sweep and the finished Jacobian afterwards.
-template <typename IO, int kJacWaves>
-__global__ __launch_bounds__(64 * kJacWaves) void jacobian_kernel(MechView m,
-                                                                  const IO *__restrict__ Tin,
-                                                                  const IO *__restrict__ Pin,
-                                                                  const IO *__restrict__ Y,
-                                                                  int64_t ldY, int64_t n,
-                                                                  IO *__restrict__ Jout,
-                                                                  int64_t ldJ)
+// LDS per cell (doubles): J[(ns+1)^2] then per species C, a, v, w, h, cp,
+// dcp, omega, u.  J holds G_km (and d omega_k/dT in the last column) during
+// the reaction sweep and the finished Jacobian afterwards.  The per-cell LDS
+// (27.6 KB at 53 species) lets several cells share a CU, and all of a
+// workgroup's lanes share the sweep, the assembly and the store.
+constexpr int kJacWaves = 4;
+constexpr int kJacThreads = 64 * kJacWaves;
+
+template <typename IO>
+__global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
+                                                               const IO *__restrict__ Tin,
+                                                               const IO *__restrict__ Pin,
+                                                               const IO *__restrict__ Y,
+                                                               int64_t ldY, int64_t n,
+                                                               IO *__restrict__ Jout,
+                                                               int64_t ldJ)
 {
     extern __shared__ __attribute__((aligned(16))) double jl[];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int ns = m.ns, nv = ns + 1;
-    const int per_wave = nv * nv + 9 * ns;
-    double *Jw = jl + (size_t)wave * per_wave;
+    double *Jw = jl;
     double *sC = Jw + nv * nv, *sa = sC + ns, *sv = sa + ns, *sw = sv + ns, *sh = sw + ns,
            *scp = sh + ns, *sdcp = scp + ns, *som = sdcp + ns, *su = som + ns;
-    const int64_t cell = (int64_t)blockIdx.x * kJacWaves + wave;
-    const bool valid = cell < n;
+    const int64_t cell = blockIdx.x;
 
-    double T = valid ? (double)Tin[cell] : 1000.0;
-    double P = valid ? (double)Pin[cell] : 1.0e5;
+    // cell state and mixture sum: every wave, same order (lane = species)
+    double T = (double)Tin[cell];
+    double P = (double)Pin[cell];
     bool bad = !(T > 0.0) || !(P > 0.0) || !__builtin_isfinite(T) || !__builtin_isfinite(P);
-    // mixture sum (lane = species)
     double ysum = 0.0;
     bool ybad = false;
     for (int k = lane; k < ns; k += 64) {
-        const double y = valid ? (double)Y[k * ldY + cell] : 1.0;
+        const double y = (double)Y[k * ldY + cell];
         ybad |= !__builtin_isfinite(y);
         ysum += __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
     }
@@ -101,9 +104,9 @@ __global__ __launch_bounds__(64 * kJacWaves) void jacobian_kernel(MechView m,
     }
     const double lnT = log(T), invT = 1.0 / T, T2 = T * T, T3 = T2 * T, T4 = T3 * T;
     const double rho = P / (kRu * T * sigma);
-    for (int k = lane; k < ns; k += 64) {
+    for (int k = tid; k < ns; k += kJacThreads) {
         const SpeciesRec &s = m.sp[k];
-        const double y = bad ? 0.0 : __builtin_fmax(valid ? (double)Y[k * ldY + cell] : 1.0, 0.0);
+        const double y = bad ? 0.0 : __builtin_fmax((double)Y[k * ldY + cell], 0.0);
         const double C = rho * y * s.inv_W;
         const double g2 = gibbs2(s, lnT, T, T2, T3, T4, invT);
         const double w = exp2(g2), v = exp2(-g2);
@@ -118,66 +121,63 @@ __global__ __launch_bounds__(64 * kJacWaves) void jacobian_kernel(MechView m,
         som[k] = 0.0;
         su[k] = 0.0;
     }
-    for (int i = lane; i < nv * nv; i += 64) Jw[i] = 0.0;
+    for (int i = tid; i < nv * nv; i += kJacThreads) Jw[i] = 0.0;
     __syncthreads();
 
     const double log2T = lnT * kLog2e;
-    for (int j0 = 0; j0 < m.nr; j0 += 64) {
-        const int j = j0 + lane;
-        if (j < m.nr) {
-            const RxnRec R = m.rx[j];
-            const RxnAux X = m.aux[j];
-            const int nf = X.nf, nr = X.nr, nm = nf + nr;
-            const double kf = exp2(__builtin_fma(R.beta, log2T, __builtin_fma(R.negEoR2, invT, R.log2A)));
-            double a[8], Ar = 1.0, Ap = 1.0, E = kf, dH = 0.0;
+    for (int j = tid; j < m.nr; j += kJacThreads) {
+        const RxnRec R = m.rx[j];
+        const RxnAux X = m.aux[j];
+        const int nf = X.nf, nr = X.nr, nm = nf + nr;
+        const double kf = exp2(__builtin_fma(R.beta, log2T, __builtin_fma(R.negEoR2, invT, R.log2A)));
+        double a[8], Ar = 1.0, Ap = 1.0, E = kf, dH = 0.0;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                if (i < nm) {
-                    const int s = X.sp[i];
-                    a[i] = sa[s];
-                    if (i < nf) {
-                        Ar *= a[i];
-                        E *= sv[s];
-                        dH -= sh[s];
-                    } else {
-                        Ap *= a[i];
-                        dH += sh[s];
-                    }
+        for (int i = 0; i < 8; ++i) {
+            if (i < nm) {
+                const int s = X.sp[i];
+                a[i] = sa[s];
+                if (i < nf) {
+                    Ar *= a[i];
+                    E *= sv[s];
+                    dH -= sh[s];
+                } else {
+                    Ap *= a[i];
+                    dH += sh[s];
                 }
             }
-            const double rev = X.rev;
-            const double qf = E * Ar, qr = rev * E * Ap;
-            const double dlnkf = (R.beta + X.EoR * invT) * invT;
-            const double dn = (double)(nr - nf);
-            const double dqT = qf * (dlnkf - nf * invT) - qr * (dlnkf - (dH - dn) * invT - nr * invT);
-            const double wu = nf * qf - nr * qr;
-            const double qn = qf - qr;
-            // d q_net / dC at each molecule slot (leave-one-out products)
-            double dq[8];
+        }
+        const double rev = X.rev;
+        const double qf = E * Ar, qr = rev * E * Ap;
+        const double dlnkf = (R.beta + X.EoR * invT) * invT;
+        const double dn = (double)(nr - nf);
+        const double dqT = qf * (dlnkf - nf * invT) - qr * (dlnkf - (dH - dn) * invT - nr * invT);
+        const double wu = nf * qf - nr * qr;
+        const double qn = qf - qr;
+        // d q_net / dC at each molecule slot (leave-one-out products)
+        double dq[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                if (i < nm) {
-                    double loo = 1.0;
-                    const bool reac = i < nf;
+        for (int i = 0; i < 8; ++i) {
+            if (i < nm) {
+                double loo = 1.0;
+                const bool reac = i < nf;
 #pragma unroll
-                    for (int l = 0; l < 8; ++l)
-                        if (l != i && l < nm && ((l < nf) == reac)) loo *= a[l];
-                    const double base = E * sw[X.sp[i]] * loo;
-                    dq[i] = reac ? base : -rev * base;
-                }
+                for (int l = 0; l < 8; ++l)
+                    if (l != i && l < nm && ((l < nf) == reac)) loo *= a[l];
+                const double base = E * sw[X.sp[i]] * loo;
+                dq[i] = reac ? base : -rev * base;
             }
+        }
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                if (r < nm) {
-                    const int k = X.sp[r];
-                    const double sg = r < nf ? -1.0 : 1.0;
-                    lds_addd(&som[k], sg * qn);
-                    lds_addd(&su[k], sg * wu);
-                    lds_addd(&Jw[k * nv + ns], sg * dqT);
+        for (int r = 0; r < 8; ++r) {
+            if (r < nm) {
+                const int k = X.sp[r];
+                const double sg = r < nf ? -1.0 : 1.0;
+                lds_addd(&som[k], sg * qn);
+                lds_addd(&su[k], sg * wu);
+                lds_addd(&Jw[k * nv + ns], sg * dqT);
 #pragma unroll
-                    for (int c = 0; c < 8; ++c)
-                        if (c < nm) lds_addd(&Jw[k * nv + X.sp[c]], sg * dq[c]);
-                }
+                for (int c = 0; c < 8; ++c)
+                    if (c < nm) lds_addd(&Jw[k * nv + X.sp[c]], sg * dq[c]);
             }
         }
     }
@@ -186,14 +186,14 @@ __global__ __launch_bounds__(64 * kJacWaves) void jacobian_kernel(MechView m,
     // assembly of the composition columns (the temperature column already
     // holds the full d omega_k/dT: dq/dT above includes -(n_f q_f - n_r q_r)/T)
     const double inv_sigma = 1.0 / sigma;
-    for (int i = lane; i < ns * nv; i += 64) {
+    for (int i = tid; i < ns * nv; i += kJacThreads) {
         const int k = i / nv, c = i - k * nv;
         if (c < ns) {
-            const double ycl = (valid ? (double)Y[c * ldY + cell] : 1.0) >= 0.0 ? 1.0 : 0.0;
+            const double ycl = (double)Y[c * ldY + cell] >= 0.0 ? 1.0 : 0.0;
             Jw[i] = ycl * (rho * Jw[i] - su[k] * inv_sigma) * m.sp[c].inv_W;
         }
     }
-    // temperature row
+    // temperature-row sums: every wave, same order
     double num = 0.0, den = 0.0, omcp = 0.0, cdcp = 0.0;
     for (int k = lane; k < ns; k += 64) {
         num += kRu * T * sh[k] * som[k];
@@ -206,12 +206,13 @@ __global__ __launch_bounds__(64 * kJacWaves) void jacobian_kernel(MechView m,
     omcp = wave_sum(omcp);
     cdcp = wave_sum(cdcp);
     __syncthreads();
-    for (int c = lane; c < nv; c += 64) {
+    // temperature row: column c of d omega_T / dx
+    for (int c = tid; c < nv; c += kJacThreads) {
         double dnum = 0.0;
         for (int k = 0; k < ns; ++k) dnum += kRu * T * sh[k] * Jw[k * nv + c];
         double dden;
         if (c < ns) {
-            const double ycl = (valid ? (double)Y[c * ldY + cell] : 1.0) >= 0.0 ? 1.0 : 0.0;
+            const double ycl = (double)Y[c * ldY + cell] >= 0.0 ? 1.0 : 0.0;
             dden = ycl * (kRu * scp[c] * rho - den * inv_sigma) * m.sp[c].inv_W;
         } else {
             dnum += omcp;
@@ -220,19 +221,83 @@ __global__ __launch_bounds__(64 * kJacWaves) void jacobian_kernel(MechView m,
         Jw[ns * nv + c] = -(dnum * den - num * dden) / (den * den);
     }
     __syncthreads();
-    if (valid) {
-        const IO nan = __builtin_nan("");
-        IO *o = Jout + cell * ldJ;
-        for (int i = lane; i < nv * nv; i += 64) o[i] = bad ? nan : (IO)Jw[i];
-        if (lane == 0 && bad) atomicAdd(m.err, 1ull);
-    }
+    const IO nan = __builtin_nan("");
+    IO *o = Jout + cell * ldJ;
+    for (int i = tid; i < nv * nv; i += kJacThreads) o[i] = bad ? nan : (IO)Jw[i];
+    if (tid == 0 && bad) atomicAdd(m.err, 1ull);
 }
 
 // ---------------------------------------------------------------------------
-// VJP: lane = cell, tile of m.tile cells shared by the workgroup's waves.
+// VJP: lane = cell, tile of `tile` cells shared by the workgroup's waves.
 // LDS entry per (species, cell), 40 B: a, v, omega_bar, h/RT, a_bar.
+// Reactions are walked in the forward kernel's (shape, reversibility) runs so
+// that each molecule loop is unrolled for its shape.
 constexpr int kVjpEntry = 40;
 constexpr int kVjpWaves = 8;
+
+struct VjpCell {
+    double log2T, invT;
+};
+
+// One reaction's contribution: q_bar = sum_k nu_kj omega_bar_k; a_bar of each
+// molecule slot += q_bar dq/da_slot (LDS atomics); s += q_bar (n_f q_f -
+// n_r q_r); T_bar += q_bar dq/dT.
+template <int NF, int NR>
+__device__ __forceinline__ void vjp_reaction(const RxnRec &R, double rev, unsigned char *vl,
+                                             uint32_t lane_off, uint32_t sstride,
+                                             const VjpCell c, double &s_acc, double &tbar)
+{
+    constexpr int NM = NF + NR;
+    const double t = __builtin_fma(R.beta, c.log2T, __builtin_fma(R.negEoR2, c.invT, R.log2A));
+    double a[NM];
+    double *e[NM];
+    double Vr = 1.0, dH = 0.0, qbar = 0.0;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        e[i] = (double *)(vl + lane_off + (uint32_t)R.sp[i] * sstride);
+        a[i] = e[i][0];
+        if (i < NF) {
+            Vr *= e[i][1];
+            dH -= e[i][3];
+            qbar -= e[i][2];
+        } else {
+            dH += e[i][3];
+            qbar += e[i][2];
+        }
+    }
+    double Ar = 1.0, Ap = 1.0;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        if (i < NF) Ar *= a[i]; else Ap *= a[i];
+    }
+    const double Ek = exp2(t) * Vr;              // k_f prod_reac v
+    const double qf = Ek * Ar, qr = rev * Ek * Ap;
+    const double EoR = -R.negEoR2 * 0.69314718055994530942;   // E/R
+    const double dlnkf = (R.beta + EoR * c.invT) * c.invT;
+    const double dqT = qf * (dlnkf - NF * c.invT) -
+                       qr * (dlnkf - (dH - (double)(NR - NF)) * c.invT - NR * c.invT);
+    s_acc += qbar * (NF * qf - NR * qr);
+    tbar += qbar * dqT;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        double loo = 1.0;
+#pragma unroll
+        for (int l = 0; l < NM; ++l)
+            if (l != i && ((l < NF) == (i < NF))) loo *= a[l];
+        const double d = i < NF ? Ek * loo : -rev * Ek * loo;   // d q / d a_slot
+        lds_addd(e[i] + 4, qbar * d);
+    }
+}
+
+template <int NF, int NR>
+__device__ __forceinline__ void vjp_run(const MechView &m, const ShapeRun run, int wave,
+                                        unsigned char *vl, uint32_t lane_off, uint32_t sstride,
+                                        const VjpCell c, double &s_acc, double &tbar)
+{
+    const int end = run.start + run.count;
+    for (int j = run.start + wave; j < end; j += kVjpWaves)
+        vjp_reaction<NF, NR>(m.rx[j], run.rev, vl, lane_off, sstride, c, s_acc, tbar);
+}
 
 template <typename IO>
 __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int tile,
@@ -248,24 +313,31 @@ __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int til
     __shared__ double partial[kVjpWaves][2][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const bool active = lane < tile;
+    // lanes past the tile own no LDS column; every wave keeps lanes 0..tile-1
+    if (lane >= tile) return;
     const int64_t cell = (int64_t)blockIdx.x * tile + lane;
-    const bool valid = active && cell < n;
+    const bool valid = cell < n;
     const uint32_t sstride = (uint32_t)tile * kVjpEntry;
-    const uint32_t lane_off = active ? (uint32_t)lane * kVjpEntry : 0u;
+    const uint32_t lane_off = (uint32_t)lane * kVjpEntry;
     auto E = [&](int k) { return (double *)(vl + (uint32_t)k * sstride + lane_off); };
 
     double T = valid ? (double)Tin[cell] : 1000.0;
     double P = valid ? (double)Pin[cell] : 1.0e5;
-    // mixture sum: every wave, same order
-    double sigma = 0.0;
-    bool bad = !(T > 0.0) || !(P > 0.0) || !__builtin_isfinite(T) || !__builtin_isfinite(P);
-    for (int k = 0; k < m.ns; ++k) {
+    // this wave's species: y_k^+ / W_k into the a-slot, partial mixture sums
+    // (NaN for a non-finite input) meeting in LDS
+    double psum = 0.0;
+    for (int k = wave; k < m.ns; k += kVjpWaves) {
         const double y = valid ? (double)Y[k * ldY + cell] : 1.0;
-        bad |= !__builtin_isfinite(y);
-        sigma += __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
+        const double yw = __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
+        psum += __builtin_isfinite(y) ? yw : __builtin_nan("");
+        E(k)[0] = yw;
     }
-    bad |= !(sigma > 0.0);
+    partial[wave][0][lane] = psum;
+    __syncthreads();
+    double sigma = 0.0;
+    for (int w = 0; w < kVjpWaves; ++w) sigma += partial[w][0][lane];
+    bool bad = !(T > 0.0) || !(P > 0.0) || !__builtin_isfinite(T) || !__builtin_isfinite(P) ||
+               !(sigma > 0.0) || !__builtin_isfinite(sigma);
     if (bad) {
         T = 1000.0;
         P = 1.0e5;
@@ -275,63 +347,42 @@ __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int til
     const double rho = P / (kRu * T * sigma);
     for (int k = wave; k < m.ns; k += kVjpWaves) {
         const SpeciesRec &s = m.sp[k];
-        const double y = bad ? 0.0 : __builtin_fmax(valid ? (double)Y[k * ldY + cell] : 1.0, 0.0);
         const double g2 = gibbs2(s, lnT, T, T2, T3, T4, invT);
         const Thermo1 th = nasa(m.th[k], T, s.T_mid);
-        if (active) {
-            double *e = E(k);
-            e[0] = rho * y * s.inv_W * exp2(g2);
-            e[1] = exp2(-g2);
-            e[2] = valid ? (double)G[k * ldG + cell] : 0.0;
-            e[3] = th.h;
-            e[4] = 0.0;
-        }
+        double *e = E(k);
+        const double yw = bad ? 0.0 : e[0];
+        e[0] = rho * yw * exp2(g2);
+        e[1] = exp2(-g2);
+        e[2] = valid ? (double)G[k * ldG + cell] : 0.0;
+        e[3] = th.h;
+        e[4] = 0.0;
     }
-    __syncthreads();
+    __syncthreads();      // also: every wave has read `partial` above
 
-    // reverse sweep over reactions (this wave: every kVjpWaves-th reaction)
-    const double log2T = lnT * kLog2e;
+    // reverse sweep over reactions (this wave: every kVjpWaves-th reaction
+    // of each run)
+    VjpCell c;
+    c.log2T = lnT * kLog2e;
+    c.invT = invT;
     double s_acc = 0.0, tbar = 0.0;
-    for (int j = wave; j < m.nr; j += kVjpWaves) {
-        const RxnRec &R = m.rx[j];
-        const RxnAux &X = m.aux[j];
-        const int nf = X.nf, nm = X.nf + X.nr;
-        const double kf = exp2(__builtin_fma(R.beta, log2T, __builtin_fma(R.negEoR2, invT, R.log2A)));
-        double a[8], Ar = 1.0, Ap = 1.0, Ek = kf, dH = 0.0, qbar = 0.0;
-        for (int i = 0; i < nm; ++i) {
-            const double *e = E(X.sp[i]);
-            a[i] = e[0];
-            if (i < nf) {
-                Ar *= a[i];
-                Ek *= e[1];
-                dH -= e[3];
-                qbar -= e[2];
-            } else {
-                Ap *= a[i];
-                dH += e[3];
-                qbar += e[2];
-            }
+    for (int r = 0; r < m.nruns; ++r) {
+        const ShapeRun run = m.runs[r];
+        const int sh = (run.nf - 1) * 4 + (run.nr - 1);
+#define AK_VCASE(a, b)                                                                         \
+    case (a - 1) * 4 + (b - 1):                                                                \
+        vjp_run<a, b>(m, run, wave, vl, lane_off, sstride, c, s_acc, tbar);                     \
+        break;
+        switch (sh) {
+            AK_VCASE(1, 1) AK_VCASE(1, 2) AK_VCASE(1, 3) AK_VCASE(1, 4)
+            AK_VCASE(2, 1) AK_VCASE(2, 2) AK_VCASE(2, 3) AK_VCASE(2, 4)
+            AK_VCASE(3, 1) AK_VCASE(3, 2) AK_VCASE(3, 3) AK_VCASE(3, 4)
+            AK_VCASE(4, 1) AK_VCASE(4, 2) AK_VCASE(4, 3) AK_VCASE(4, 4)
+            default: break;
         }
-        const double rev = X.rev;
-        const double qf = Ek * Ar, qr = rev * Ek * Ap;
-        const int nr = nm - nf;
-        const double dlnkf = (R.beta + X.EoR * invT) * invT;
-        const double dqT = qf * (dlnkf - nf * invT) - qr * (dlnkf - (dH - (double)(nr - nf)) * invT - nr * invT);
-        s_acc += qbar * (nf * qf - nr * qr);
-        tbar += qbar * dqT;
-        for (int i = 0; i < nm; ++i) {
-            double loo = 1.0;
-            const bool reac = i < nf;
-            for (int l = 0; l < nm; ++l)
-                if (l != i && ((l < nf) == reac)) loo *= a[l];
-            const double d = reac ? Ek * loo : -rev * Ek * loo;   // d q / d a_slot
-            if (active) lds_addd(E(X.sp[i]) + 4, qbar * d);
-        }
+#undef AK_VCASE
     }
-    if (active) {
-        partial[wave][0][lane] = s_acc;
-        partial[wave][1][lane] = tbar;
-    }
+    partial[wave][0][lane] = s_acc;
+    partial[wave][1][lane] = tbar;
     __syncthreads();
     double s_tot = 0.0, t_tot = 0.0;   // s = sum_j q_bar_j (n_f q_f - n_r q_r)_j
     for (int w = 0; w < kVjpWaves; ++w) {
@@ -362,43 +413,33 @@ static size_t jacobian_lds_per_cell(int ns)
     return ((size_t)(ns + 1) * (ns + 1) + 9 * (size_t)ns) * sizeof(double);
 }
 
-// LDS for one cell (the minimum a launch needs)
+// LDS of one cell's workgroup
 size_t jacobian_lds_bytes(int ns) { return jacobian_lds_per_cell(ns); }
 
-template <typename IO, int JW>
+template <typename IO>
 static hipError_t jacobian_launch_t(const MechView &m, const void *T, const void *P,
                                     const void *Y, int64_t ldY, int64_t n, void *J,
                                     int64_t ldJ, hipStream_t st)
 {
-    const size_t lds = JW * jacobian_lds_per_cell(m.ns);
-    const int64_t blocks = (n + JW - 1) / JW;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    auto fn = jacobian_kernel<IO, JW>;
+    if (n <= 0) return hipSuccess;
+    if (n > 0x7fffffff) return hipErrorInvalidValue;
+    const size_t lds = jacobian_lds_per_cell(m.ns);
+    auto fn = jacobian_kernel<IO>;
     hipError_t e = hipFuncSetAttribute((const void *)fn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * JW), lds, st, m, (const IO *)T,
+    hipLaunchKernelGGL(fn, dim3((unsigned)n), dim3(kJacThreads), lds, st, m, (const IO *)T,
                        (const IO *)P, (const IO *)Y, ldY, n, (IO *)J, ldJ);
     return hipGetLastError();
-}
-
-template <typename IO>
-static hipError_t jacobian_dispatch(const MechView &m, int lds_max, const void *T,
-                                    const void *P, const void *Y, int64_t ldY, int64_t n,
-                                    void *J, int64_t ldJ, hipStream_t st)
-{
-    const size_t per = jacobian_lds_per_cell(m.ns);
-    if (4 * per <= (size_t)lds_max) return jacobian_launch_t<IO, 4>(m, T, P, Y, ldY, n, J, ldJ, st);
-    if (2 * per <= (size_t)lds_max) return jacobian_launch_t<IO, 2>(m, T, P, Y, ldY, n, J, ldJ, st);
-    return jacobian_launch_t<IO, 1>(m, T, P, Y, ldY, n, J, ldJ, st);
 }
 
 hipError_t jacobian_launch(const MechView &m, int lds_max, bool f64, const void *T,
                            const void *P, const void *Y, int64_t ldY, int64_t n, void *J,
                            int64_t ldJ, hipStream_t st)
 {
-    if (f64) return jacobian_dispatch<double>(m, lds_max, T, P, Y, ldY, n, J, ldJ, st);
-    return jacobian_dispatch<float>(m, lds_max, T, P, Y, ldY, n, J, ldJ, st);
+    (void)lds_max;   // the caller checked jacobian_lds_bytes against it
+    if (f64) return jacobian_launch_t<double>(m, T, P, Y, ldY, n, J, ldJ, st);
+    return jacobian_launch_t<float>(m, T, P, Y, ldY, n, J, ldJ, st);
 }
 
 int vjp_tile(int ns, int lds_max)
