@@ -176,11 +176,14 @@ int ak_error_count(const ak_mechanism *mech, void *stream, int64_t *n_bad_cells)
  * The paper's use is an MPI rank offloading its cells to the GPU (Sec. 1,
  * Sec. 3.2).  A server accepts such offloads from many host threads at once:
  * requests are queued FIFO and admitted while their bytes fit a device arena
- * and fewer than max_inflight batches are on the device; each admitted batch
- * is copied in, evaluated by ONE fused launch per precision covering all its
- * requests (mechanisms may differ), and copied back, while later requests
- * keep being admitted as memory and batch slots free up.  With batching = 0
- * every request is its own batch (one launch per request), for comparison.
+ * and fewer than max_inflight batches are on the device; consecutive small
+ * requests (at most small_request_cells cells each) form one batch, which is
+ * copied in and evaluated by ONE fused launch per precision covering all its
+ * requests (mechanisms may differ); larger requests run alone.  Each request
+ * completes, and frees its arena range, as soon as its own result is copied
+ * back, while later requests keep being admitted as memory and batch slots
+ * free up.  With batching = 0 every request is its own batch (one launch per
+ * request), for comparison.
  * Results equal ak_eval_source's up to the rounding order of the omega
  * accumulation.
  */
@@ -192,8 +195,9 @@ typedef struct {
     int32_t max_inflight;       /* batches on the device at once (0: 3; at most 16) */
     int32_t max_batch_requests; /* requests per batch (0: 64; at most 4096) */
     int32_t batching;           /* 1: continuous batching, 0: one launch per request */
-    int64_t max_batch_cells;    /* cells per batch (0: 2^21) */
+    int64_t max_batch_cells;    /* cells per batch (0: 2^16) */
     size_t arena_bytes;         /* device arena for staged requests (0: 1 GiB) */
+    int64_t small_request_cells; /* larger requests are never fused (0: 4096) */
 } ak_server_config;
 
 typedef struct {

@@ -47,7 +47,8 @@ class MechanismDesc(C.Structure):
 class ServerConfig(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32),
                 ("max_batch_requests", C.c_int32), ("batching", C.c_int32),
-                ("max_batch_cells", C.c_int64), ("arena_bytes", C.c_size_t)]
+                ("max_batch_cells", C.c_int64), ("arena_bytes", C.c_size_t),
+                ("small_request_cells", C.c_int64)]
 
 
 class ServerStats(C.Structure):
@@ -327,11 +328,13 @@ class Server:
 
     def __init__(self, device: int | None = None, max_inflight: int = 3,
                  max_batch_requests: int = 64, batching: bool = True,
-                 max_batch_cells: int = 1 << 21, arena_bytes: int = 1 << 30):
+                 max_batch_cells: int = 1 << 16, arena_bytes: int = 1 << 30,
+                 small_request_cells: int = 4096):
         if device is None:
             device = _torch().cuda.current_device()
         cfg = ServerConfig(int(device), int(max_inflight), int(max_batch_requests),
-                           1 if batching else 0, int(max_batch_cells), int(arena_bytes))
+                           1 if batching else 0, int(max_batch_cells), int(arena_bytes),
+                           int(small_request_cells))
         h = C.c_void_p()
         _check(lib().ak_server_create(C.byref(cfg), C.byref(h)))
         self._h = h

@@ -3,17 +3,22 @@
 // Requests enter a FIFO queue.  A batcher thread admits queued requests in
 // order while (a) fewer than max_inflight batches are on the device, (b) the
 // head request's bytes fit in the device arena (first-fit allocator), and
-// (c) the batch limits (requests, cells) allow; the admitted requests form one
-// batch handed to the executor, which enqueues copies and one fused launch
-// per precision and returns at once.  A completion thread waits for batches
-// in submission order, releases their arena ranges and completes their
-// requests, which lets the batcher admit more.  Requests therefore join the
-// device while earlier batches are still running (continuous batching).
+// (c) the batch limits allow: requests of more than small_cells cells run
+// alone (their copies dwarf a launch, so fusing them would only delay the
+// others), smaller ones are fused up to max_batch_requests and
+// max_batch_cells.  The executor enqueues copies in, one fused launch per
+// precision and copies out, and returns at once.  A completion thread waits
+// for batches in submission order and, within a batch, for each request's
+// own copy-out, then frees that request's arena range and completes it, which
+// lets the batcher admit more.  Requests therefore join the device while
+// earlier batches are still running (continuous batching).
 //
 // Executor interface (duck-typed):
 //   void *launch(const std::vector<Request*> &batch);  // enqueue; returns a token
-//   int   wait(void *token);                           // block until done; 0 or error
+//   int   wait(void *token, size_t i);                 // block until request i's
+//                                                      // result is out; 0 or error
 //   void  release(void *token);
+//   int64_t launches(void *token);
 #pragma once
 #include <algorithm>
 #include <atomic>
@@ -112,7 +117,8 @@ struct SchedConfig {
     size_t arena_bytes = (size_t)1 << 30;
     int max_inflight = 3;
     int max_batch_requests = 64;
-    int64_t max_batch_cells = (int64_t)1 << 21;
+    int64_t max_batch_cells = (int64_t)1 << 16;
+    int64_t small_cells = 4096;   // larger requests are never fused
     bool batching = true;     // false: one request per batch (one launch per request)
 };
 
@@ -254,7 +260,9 @@ class Scheduler {
             int64_t cells = 0;
             while (!queue_.empty() && (int)b.reqs.size() < cfg_.max_batch_requests) {
                 Request *r = queue_.front();
-                if (!b.reqs.empty() && (!cfg_.batching || cells + r->n > cfg_.max_batch_cells))
+                const bool big = r->n > cfg_.small_cells;
+                if (!b.reqs.empty() &&
+                    (!cfg_.batching || big || cells + r->n > cfg_.max_batch_cells))
                     break;
                 const size_t off = arena_.alloc(r->bytes);
                 if (off == SIZE_MAX) break;   // head of line waits for memory
@@ -266,7 +274,7 @@ class Scheduler {
                 queue_.pop_front();
                 b.reqs.push_back(r);
                 cells += r->n;
-                if (!cfg_.batching) break;
+                if (!cfg_.batching || big) break;
             }
             if (b.reqs.empty()) {
                 // nothing fits until a batch completes
@@ -290,20 +298,14 @@ class Scheduler {
             cv_.wait(l, [this] { return !inflight_.empty() || (stop_ && batcher_done_); });
             if (inflight_.empty()) return;
             Batch b = inflight_.front();
-            l.unlock();
-            const int rc = exec_->wait(b.token);
-            l.lock();
-            inflight_.pop_front();
-            for (Request *r : b.reqs) {
+            for (size_t i = 0; i < b.reqs.size(); ++i) {
+                l.unlock();
+                const int rc = exec_->wait(b.token, i);
+                l.lock();
+                Request *r = b.reqs[i];
                 arena_.release(r->arena_off, r->bytes);
                 r->arena_off = SIZE_MAX;
-            }
-            arena_freed_ = true;
-            stats_.launches += exec_launches(b.token);
-            l.unlock();
-            exec_->release(b.token);
-            l.lock();
-            for (Request *r : b.reqs) {
+                arena_freed_ = true;
                 const double t = now_s();
                 if (rc == 0) {
                     stats_.completed++;
@@ -314,7 +316,14 @@ class Scheduler {
                     stats_.failed++;
                 }
                 finish(r, rc == 0 ? kDone : kFailed, rc);
+                cv_.notify_all();
             }
+            // the executor's slot is free before the batch leaves inflight_, so
+            // a batch the batcher admits next always finds a slot (the
+            // executor's lock is never held while taking this one)
+            stats_.launches += exec_launches(b.token);
+            exec_->release(b.token);
+            inflight_.pop_front();
             cv_.notify_all();
         }
     }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <string>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -27,18 +28,26 @@ static size_t request_bytes(int prec, int ns, int64_t n)
 struct GpuExec {
     struct Slot {
         hipStream_t st = nullptr;
-        hipEvent_t ev = nullptr;
+        std::vector<hipEvent_t> ev;      // per request of the batch: its copy-out done
         BatchDesc *d_desc[2] = {nullptr, nullptr};
         BatchDesc *h_desc[2] = {nullptr, nullptr};
         int nlaunch = 0;
         int rc = 0;
         bool busy = false;
+        std::string what;                // the failed HIP call, if any
     };
     int device = 0;
     unsigned char *arena = nullptr;
     int max_req = 64;
     std::vector<Slot> slots;
     std::mutex mu;
+    std::string last_error;          // the last failure (guarded by mu)
+
+    std::string error_text()
+    {
+        std::lock_guard<std::mutex> l(mu);
+        return last_error;
+    }
 
     int init(int dev, size_t arena_bytes, int inflight, int max_requests)
     {
@@ -52,9 +61,12 @@ struct GpuExec {
                              hipGetErrorString(e));
         slots.resize(inflight);
         for (Slot &s : slots) {
-            if ((e = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking)) != hipSuccess ||
-                (e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming)) != hipSuccess)
-                return hip_error(e, "ak_server_create: stream/event");
+            if ((e = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking)) != hipSuccess)
+                return hip_error(e, "ak_server_create: stream");
+            s.ev.assign(max_requests, nullptr);
+            for (hipEvent_t &ev : s.ev)
+                if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+                    return hip_error(e, "ak_server_create: events");
             for (int p = 0; p < 2; ++p) {
                 if ((e = hipMalloc((void **)&s.d_desc[p], sizeof(BatchDesc) * max_req)) !=
                         hipSuccess ||
@@ -76,7 +88,8 @@ struct GpuExec {
                 if (s.d_desc[p]) (void)hipFree(s.d_desc[p]);
                 if (s.h_desc[p]) (void)hipHostFree(s.h_desc[p]);
             }
-            if (s.ev) (void)hipEventDestroy(s.ev);
+            for (hipEvent_t ev : s.ev)
+                if (ev) (void)hipEventDestroy(ev);
             if (s.st) (void)hipStreamDestroy(s.st);
         }
         slots.clear();
@@ -84,7 +97,8 @@ struct GpuExec {
         arena = nullptr;
     }
 
-    // Enqueue copies in, one fused launch per precision, copies out, event.
+    // Enqueue copies in, one fused launch per precision, and per request its
+    // copy out followed by its event.
     void *launch(const std::vector<Request *> &reqs)
     {
         Slot *s = nullptr;
@@ -102,8 +116,12 @@ struct GpuExec {
         s->rc = 0;
         s->nlaunch = 0;
         hipError_t e = hipSuccess;
+        const char *step = "";
         auto ok = [&](hipError_t x) {
-            if (x != hipSuccess && e == hipSuccess) e = x;
+            if (x != hipSuccess && e == hipSuccess) {
+                e = x;
+                s->what = std::string(step) + ": " + hipGetErrorString(x);
+            }
             return x == hipSuccess;
         };
         for (Request *r : reqs) {
@@ -111,6 +129,7 @@ struct GpuExec {
             unsigned char *b = arena + r->arena_off;
             unsigned char *dT = b, *dP = dT + Arena::round(es * r->n);
             unsigned char *dY = dP + Arena::round(es * r->n);
+            step = "copy in";
             ok(hipMemcpyAsync(dT, r->T, es * r->n, hipMemcpyHostToDevice, s->st));
             ok(hipMemcpyAsync(dP, r->P, es * r->n, hipMemcpyHostToDevice, s->st));
             ok(hipMemcpy2DAsync(dY, es * r->n, r->Y, es * r->ldY, es * r->n, r->ns,
@@ -140,31 +159,45 @@ struct GpuExec {
                 max_ns = std::max(max_ns, m->ns);
             }
             if (!nd) continue;
+            step = "descriptor table";
             ok(hipMemcpyAsync(s->d_desc[p], s->h_desc[p], sizeof(BatchDesc) * nd,
                               hipMemcpyHostToDevice, s->st));
+            step = "fused launch";
             ok(source_batch_launch(prec == AK_FP64, s->d_desc[p], nd, blocks, lds, max_ns,
                                    s->st));
             s->nlaunch++;
         }
-        for (Request *r : reqs) {
+        for (size_t i = 0; i < reqs.size(); ++i) {
+            const Request *r = reqs[i];
             const size_t es = elem_size(r->prec);
             unsigned char *dO = arena + r->arena_off + 2 * Arena::round(es * r->n) +
                                 Arena::round(es * r->n * r->ns);
+            step = "copy out";
             ok(hipMemcpy2DAsync(r->om, es * r->ldO, dO, es * r->n, es * r->n, r->ns,
                                 hipMemcpyDeviceToHost, s->st));
+            step = "event";
+            ok(hipEventRecord(s->ev[i], s->st));
         }
-        ok(hipEventRecord(s->ev, s->st));
         if (e != hipSuccess) s->rc = AK_EDEVICE;
+        else s->what.clear();
         return s;
     }
 
-    int wait(void *token)
+    int wait(void *token, size_t i)
     {
         if (!token) return AK_EDEVICE;
         Slot *s = (Slot *)token;
         DeviceGuard g(device);
-        hipError_t e = hipEventSynchronize(s->ev);
-        if (e != hipSuccess) return AK_EDEVICE;
+        hipError_t e = hipEventSynchronize(s->ev[i]);
+        if (e != hipSuccess) {
+            std::lock_guard<std::mutex> l(mu);
+            last_error = std::string("event wait: ") + hipGetErrorString(e);
+            return AK_EDEVICE;
+        }
+        if (s->rc) {
+            std::lock_guard<std::mutex> l(mu);
+            last_error = s->what;
+        }
         return s->rc;
     }
 
@@ -204,7 +237,8 @@ int ak_server_create(const ak_server_config *c, ak_server **out)
     cfg.arena_bytes = c->arena_bytes ? c->arena_bytes : ((size_t)1 << 30);
     cfg.max_inflight = c->max_inflight > 0 ? c->max_inflight : 3;
     cfg.max_batch_requests = c->max_batch_requests > 0 ? c->max_batch_requests : 64;
-    cfg.max_batch_cells = c->max_batch_cells > 0 ? c->max_batch_cells : ((int64_t)1 << 21);
+    cfg.max_batch_cells = c->max_batch_cells > 0 ? c->max_batch_cells : ((int64_t)1 << 16);
+    cfg.small_cells = c->small_request_cells > 0 ? c->small_request_cells : 4096;
     cfg.batching = c->batching != 0;
     if (cfg.max_inflight > 16 || cfg.max_batch_requests > 4096)
         return set_error(AK_EINVAL, "ak_server_create: max_inflight <= 16, max_batch_requests <= 4096");
@@ -270,7 +304,9 @@ int ak_request_wait(ak_request *q, double timeout_s)
     const int rc = Scheduler<GpuExec>::wait(&q->r, timeout_s);
     if (rc == -5) return set_error(AK_ETIMEDOUT, "ak_request_wait: timed out");
     if (rc == -6) return set_error(AK_ECANCELED, "ak_request_wait: request was cancelled");
-    if (rc) return set_error(rc, "ak_request_wait: request failed");
+    if (rc)
+        return set_error(rc, "ak_request_wait: request failed (%s)",
+                         q->srv->exec.error_text().c_str());
     return AK_OK;
 }
 

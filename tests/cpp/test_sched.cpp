@@ -29,6 +29,10 @@ using namespace ak;
 // Mock executor: each launch records its batch; wait() blocks until the test
 // opens that batch's gate (or returns at once in auto mode).
 struct MockExec {
+    // slots like the GPU executor's: launch takes a free one (a null token if
+    // none is free, which fails the batch), release frees it
+    int nslots = 1 << 30;
+    int used_slots = 0;
     struct Tok {
         std::vector<int> ids;
         bool open = false;
@@ -47,6 +51,8 @@ struct MockExec {
         auto t = std::make_shared<Tok>();
         for (Request *r : b) t->ids.push_back((int)r->n);
         std::lock_guard<std::mutex> g(mu);
+        if (used_slots == nslots) return nullptr;
+        ++used_slots;
         if ((int)toks.size() == fail_batch) t->rc = -2;
         toks.push_back(t);
         const int o = ++outstanding;
@@ -56,8 +62,11 @@ struct MockExec {
         cv.notify_all();
         return t.get();
     }
-    int wait(void *p)
+    // request i of a batch; the batch counts as outstanding until its last
+    // request has been waited for
+    int wait(void *p, size_t i)
     {
+        if (!p) return -2;
         Tok *t = (Tok *)p;
         std::unique_lock<std::mutex> l(mu);
         if (autoc) {
@@ -67,10 +76,14 @@ struct MockExec {
         } else {
             cv.wait(l, [t] { return t->open; });
         }
-        --outstanding;
+        if (i + 1 == t->ids.size()) --outstanding;
         return t->rc;
     }
-    void release(void *) {}
+    void release(void *p)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        if (p) --used_slots;
+    }
     int64_t launches(void *) { return 1; }
     void open(size_t i)
     {
@@ -183,6 +196,36 @@ static void test_admission_by_memory_fifo()
     CHECK(s.submit(big.get()) == -4);        // larger than the arena
 }
 
+static void test_large_requests_run_alone()
+{
+    MockExec ex;
+    SchedConfig c;
+    c.arena_bytes = 1 << 20;
+    c.max_inflight = 1;
+    c.small_cells = 100;
+    Scheduler<MockExec> s(c, &ex);
+    auto g = req(1, 256);                     // occupies the only slot
+    CHECK(s.submit(g.get()) == 0);
+    ex.wait_batches(1);
+    auto a = req(11, 256), big = req(500, 256), b = req(12, 256), d = req(13, 256);
+    for (Request *r : {a.get(), big.get(), b.get(), d.get()}) CHECK(s.submit(r) == 0);
+    settle();
+    ex.open(0);
+    ex.wait_batches(2);
+    CHECK(ex.batch(1).size() == 1 && ex.batch(1)[0] == 11);   // stops before the large one
+    ex.open(1);
+    ex.wait_batches(3);
+    CHECK(ex.batch(2).size() == 1 && ex.batch(2)[0] == 500);  // the large one alone
+    ex.open(2);
+    ex.wait_batches(4);
+    auto b3 = ex.batch(3);
+    CHECK(b3.size() == 2 && b3[0] == 12 && b3[1] == 13);      // small ones fused again
+    ex.open(3);
+    for (Request *r : {a.get(), big.get(), b.get(), d.get()})
+        CHECK(Scheduler<MockExec>::wait(r, 5.0) == 0);
+    CHECK(s.arena_used() == 0);
+}
+
 static void test_inflight_limit_one_launch_per_request()
 {
     MockExec ex;
@@ -255,6 +298,7 @@ static void test_stress()
 {
     MockExec ex;
     ex.autoc = true;
+    ex.nslots = 3;                 // exactly max_inflight slots, as on the GPU
     SchedConfig c;
     c.arena_bytes = 64 * 1024;
     c.max_inflight = 3;
@@ -289,6 +333,7 @@ int main()
     test_arena();
     test_continuous_batching();
     test_admission_by_memory_fifo();
+    test_large_requests_run_alone();
     test_inflight_limit_one_launch_per_request();
     test_cancel_timeout_failure();
     test_shutdown();
