@@ -145,8 +145,8 @@ int ak_eval_source(const ak_mechanism *mech, ak_precision prec, const void *T, c
  * Y_m < 0 the column of Y_m is zero (the clamp); at Y_m = 0 the one-sided
  * derivative from above is returned.
  * Errors: as ak_eval_source, plus AK_EINVAL for ldJ < (NS+1)^2 and
- * AK_EUNSUPPORTED when (NS+1)^2 + 9 NS doubles exceed one workgroup's LDS
- * (NS > ~140 on gfx950).
+ * AK_EUNSUPPORTED when (NS+1)^2 + 11 NS + 257 doubles exceed one
+ * workgroup's LDS (NS > 135 on gfx950).
  */
 int ak_eval_jacobian(const ak_mechanism *mech, ak_precision prec, const void *T, const void *P,
                      const void *Y, int64_t ldY, int64_t n_cells, void *J, int64_t ldJ,

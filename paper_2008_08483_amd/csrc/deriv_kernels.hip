@@ -59,12 +59,15 @@ __device__ __forceinline__ double gibbs2(const SpeciesRec &s, double lnT, double
 // Jacobian: one workgroup of kJacWaves waves per cell, thread = reaction.
 //
 // LDS per cell (doubles): J[(ns+1)^2] then per species C, a, v, w, h, cp,
-// dcp, omega, u.  J holds G_km (and d omega_k/dT in the last column) during
-// the reaction sweep and the finished Jacobian afterwards.  The per-cell LDS
-// (27.6 KB at 53 species) lets several cells share a CU, and all of a
-// workgroup's lanes share the sweep, the assembly and the store.
+// dcp, omega, u, y and s = [Y >= 0]/W, then 4 x 64 partial sums.  J holds
+// G_km (and d omega_k/dT in the last column) during the reaction sweep and
+// the finished Jacobian afterwards.  The per-cell LDS (28 KB at 53 species)
+// lets several cells share a CU, and all of a workgroup's lanes share the
+// sweep, the assembly and the store.  The cell's mass fractions are read
+// from HBM once per workgroup (they lie NS cache lines apart).
 constexpr int kJacWaves = 4;
 constexpr int kJacThreads = 64 * kJacWaves;
+constexpr int kJacSpeciesVecs = 11;
 
 template <typename IO>
 __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
@@ -80,18 +83,27 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
     const int lane = tid & 63;
     const int ns = m.ns, nv = ns + 1;
     double *Jw = jl;
-    double *sC = Jw + nv * nv, *sa = sC + ns, *sv = sa + ns, *sw = sv + ns, *sh = sw + ns,
-           *scp = sh + ns, *sdcp = scp + ns, *som = sdcp + ns, *su = som + ns;
+    double *sC = Jw + ((nv * nv + 1) & ~1), *sa = sC + ns, *sv = sa + ns, *sw = sv + ns,
+           *sh = sw + ns, *scp = sh + ns, *sdcp = scp + ns, *som = sdcp + ns, *su = som + ns,
+           *sy = su + ns, *ss = sy + ns;
+    double *part = ss + ns;                       // [4][64]
     const int64_t cell = blockIdx.x;
 
-    // cell state and mixture sum: every wave, same order (lane = species)
+    // the cell's state: Y once into LDS, then the mixture sum in every wave
+    // (same order, lane = species)
+    for (int k = tid; k < ns; k += kJacThreads) sy[k] = (double)Y[k * ldY + cell];
+    for (int i = 2 * tid; i < nv * nv; i += 2 * kJacThreads) {
+        if (i + 1 < nv * nv) *(double2 *)&Jw[i] = make_double2(0.0, 0.0);
+        else Jw[i] = 0.0;
+    }
+    __syncthreads();
     double T = (double)Tin[cell];
     double P = (double)Pin[cell];
     bool bad = !(T > 0.0) || !(P > 0.0) || !__builtin_isfinite(T) || !__builtin_isfinite(P);
     double ysum = 0.0;
     bool ybad = false;
     for (int k = lane; k < ns; k += 64) {
-        const double y = (double)Y[k * ldY + cell];
+        const double y = sy[k];
         ybad |= !__builtin_isfinite(y);
         ysum += __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
     }
@@ -106,7 +118,7 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
     const double rho = P / (kRu * T * sigma);
     for (int k = tid; k < ns; k += kJacThreads) {
         const SpeciesRec &s = m.sp[k];
-        const double y = bad ? 0.0 : __builtin_fmax((double)Y[k * ldY + cell], 0.0);
+        const double y = bad ? 0.0 : __builtin_fmax(sy[k], 0.0);
         const double C = rho * y * s.inv_W;
         const double g2 = gibbs2(s, lnT, T, T2, T3, T4, invT);
         const double w = exp2(g2), v = exp2(-g2);
@@ -120,8 +132,8 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
         sdcp[k] = th.dcp;
         som[k] = 0.0;
         su[k] = 0.0;
+        ss[k] = (sy[k] >= 0.0 ? 1.0 : 0.0) * s.inv_W;
     }
-    for (int i = tid; i < nv * nv; i += kJacThreads) Jw[i] = 0.0;
     __syncthreads();
 
     const double log2T = lnT * kLog2e;
@@ -188,10 +200,7 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
     const double inv_sigma = 1.0 / sigma;
     for (int i = tid; i < ns * nv; i += kJacThreads) {
         const int k = i / nv, c = i - k * nv;
-        if (c < ns) {
-            const double ycl = (double)Y[c * ldY + cell] >= 0.0 ? 1.0 : 0.0;
-            Jw[i] = ycl * (rho * Jw[i] - su[k] * inv_sigma) * m.sp[c].inv_W;
-        }
+        if (c < ns) Jw[i] = ss[c] * (rho * Jw[i] - su[k] * inv_sigma);
     }
     // temperature-row sums: every wave, same order
     double num = 0.0, den = 0.0, omcp = 0.0, cdcp = 0.0;
@@ -206,24 +215,49 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
     omcp = wave_sum(omcp);
     cdcp = wave_sum(cdcp);
     __syncthreads();
-    // temperature row: column c of d omega_T / dx
-    for (int c = tid; c < nv; c += kJacThreads) {
-        double dnum = 0.0;
-        for (int k = 0; k < ns; ++k) dnum += kRu * T * sh[k] * Jw[k * nv + c];
-        double dden;
-        if (c < ns) {
-            const double ycl = (double)Y[c * ldY + cell] >= 0.0 ? 1.0 : 0.0;
-            dden = ycl * (kRu * scp[c] * rho - den * inv_sigma) * m.sp[c].inv_W;
-        } else {
-            dnum += omcp;
-            dden = -den * invT + cdcp;
+    // temperature row: column c of d omega_T / dx; sum_k h_k J[k][c] in four
+    // interleaved parts (thread = column c0 + lane, part = wave)
+    const int wave = tid >> 6;
+    for (int c0 = 0; c0 < nv; c0 += 64) {
+        const int c = c0 + lane;
+        double dn = 0.0;
+        if (c < nv)
+            for (int k = wave; k < ns; k += kJacWaves) dn += sh[k] * Jw[k * nv + c];
+        part[wave * 64 + lane] = dn;
+        __syncthreads();
+        if (wave == 0 && c < nv) {
+            double dnum = 0.0;
+            for (int w = 0; w < kJacWaves; ++w) dnum += part[w * 64 + lane];
+            dnum *= kRu * T;
+            double dden;
+            if (c < ns) {
+                dden = ss[c] * (kRu * scp[c] * rho - den * inv_sigma);
+            } else {
+                dnum += omcp;
+                dden = -den * invT + cdcp;
+            }
+            Jw[ns * nv + c] = -(dnum * den - num * dden) / (den * den);
         }
-        Jw[ns * nv + c] = -(dnum * den - num * dden) / (den * den);
+        __syncthreads();
     }
-    __syncthreads();
+    // store, 16 bytes at a time where the row of this cell is 16-byte aligned
     const IO nan = __builtin_nan("");
     IO *o = Jout + cell * ldJ;
-    for (int i = tid; i < nv * nv; i += kJacThreads) o[i] = bad ? nan : (IO)Jw[i];
+    const int nn = nv * nv;
+    bool wide = false;
+    if constexpr (sizeof(IO) == 8) wide = ((uintptr_t)o & 15) == 0;
+    if (wide) {
+        for (int i = 2 * tid; i < nn; i += 2 * kJacThreads) {
+            if (i + 1 < nn) {
+                const double2 x = *(const double2 *)&Jw[i];
+                *(double2 *)(o + i) = bad ? make_double2(nan, nan) : x;
+            } else {
+                o[i] = bad ? nan : (IO)Jw[i];
+            }
+        }
+    } else {
+        for (int i = tid; i < nn; i += kJacThreads) o[i] = bad ? nan : (IO)Jw[i];
+    }
     if (tid == 0 && bad) atomicAdd(m.err, 1ull);
 }
 
@@ -410,7 +444,8 @@ __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int til
 
 static size_t jacobian_lds_per_cell(int ns)
 {
-    return ((size_t)(ns + 1) * (ns + 1) + 9 * (size_t)ns) * sizeof(double);
+    const size_t nv2 = ((size_t)(ns + 1) * (ns + 1) + 1) & ~(size_t)1;
+    return (nv2 + kJacSpeciesVecs * (size_t)ns + 4 * 64) * sizeof(double);
 }
 
 // LDS of one cell's workgroup

@@ -136,21 +136,31 @@ __device__ __forceinline__ void scatter(unsigned char *lds, const uint32_t (&add
 
 // An LDS atomic reads its data VGPRs when the LDS executes it, so the
 // compiler waits for outstanding atomics before it reuses their data
-// registers.  Keeping a pair's q / -q registers allocated until the next
-// pair has waited for its own LDS reads (which drains the earlier atomics)
+// registers.  Keeping a group's q / -q registers allocated until the next
+// group has waited for its own LDS reads (which drains the earlier atomics)
 // removes those waits.  The asm statement emits nothing and passes x through
 // unchanged; it is not volatile and touches no memory, so the record loads
 // stay scalar.
-__device__ __forceinline__ double hold(double x, double a, double b, double c, double d)
+__device__ __forceinline__ double hold(double x, const double (&h)[4])
 {
-    asm("" : "+v"(x) : "v"(a), "v"(b), "v"(c), "v"(d));
+    asm("" : "+v"(x) : "v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]));
+    return x;
+}
+__device__ __forceinline__ double hold(double x, const double (&h)[8])
+{
+    asm("" : "+v"(x) : "v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "v"(h[4]), "v"(h[5]),
+        "v"(h[6]), "v"(h[7]));
     return x;
 }
 
+#ifndef AK_REACTION_GROUP
+#define AK_REACTION_GROUP 2
+#endif
+
 // Reactions of one run: this wave takes reactions start+wave,
-// start+wave+WAVES, ...; two at a time so that their LDS reads overlap, with
-// the next pair's records requested while the current pair computes.
-template <bool F64, int NF, int NR, int WAVES>
+// start+wave+WAVES, ...; U at a time so that their LDS reads overlap, with
+// the next group's records requested while the current group computes.
+template <bool F64, int NF, int NR, int WAVES, int U = AK_REACTION_GROUP>
 __device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun run, int wave,
                                              unsigned char *lds, uint32_t lane_off,
                                              uint32_t sstride, const Cell c)
@@ -159,29 +169,34 @@ __device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun r
     int j = run.start + wave;
     if (j >= end) return;
     const double rev = run.rev;
-    RxnRec r1 = m.rx[j];
-    RxnRec r2 = m.rx[j + WAVES < end ? j + WAVES : j];
-    double h1 = 0.0, h2 = 0.0, h3 = 0.0, h4 = 0.0;
-    for (; j < end; j += 2 * WAVES) {
-        const bool two = j + WAVES < end;
-        const int jn = j + 2 * WAVES;
-        const int jn1 = jn < end ? jn : j;
-        const int jn2 = jn + WAVES < end ? jn + WAVES : jn1;
-        const RxnRec n1 = m.rx[jn1];
-        const RxnRec n2 = m.rx[jn2];
-        uint32_t a1[NF + NR], a2[NF + NR];
-        const double q1 = hold(rate_of_progress<F64, NF, NR>(r1, rev, lds, lane_off, sstride, c, a1),
-                               h1, h2, h3, h4);
-        const double q2 = rate_of_progress<F64, NF, NR>(r2, rev, lds, lane_off, sstride, c, a2);
-        const double nq1 = -q1, nq2 = -q2;
-        scatter<NF, NR>(lds, a1, q1, nq1);
-        if (two) scatter<NF, NR>(lds, a2, q2, nq2);
-        h1 = q1;
-        h2 = nq1;
-        h3 = q2;
-        h4 = nq2;
-        r1 = n1;
-        r2 = n2;
+    RxnRec r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = m.rx[j + u * WAVES < end ? j + u * WAVES : j];
+    double h[2 * U];
+#pragma unroll
+    for (int i = 0; i < 2 * U; ++i) h[i] = 0.0;
+    for (; j < end; j += U * WAVES) {
+        RxnRec nx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = j + (U + u) * WAVES;
+            nx[u] = m.rx[k < end ? k : j];
+        }
+        uint32_t a[U][NF + NR];
+        double q[U];
+        q[0] = hold(rate_of_progress<F64, NF, NR>(r[0], rev, lds, lane_off, sstride, c, a[0]), h);
+#pragma unroll
+        for (int u = 1; u < U; ++u)
+            q[u] = rate_of_progress<F64, NF, NR>(r[u], rev, lds, lane_off, sstride, c, a[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double nq = -q[u];
+            if (u == 0 || j + u * WAVES < end) scatter<NF, NR>(lds, a[u], q[u], nq);
+            h[2 * u] = q[u];
+            h[2 * u + 1] = nq;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) r[u] = nx[u];
     }
 }
 
