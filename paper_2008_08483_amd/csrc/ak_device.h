@@ -80,6 +80,8 @@ struct MechView {
     unsigned long long *err;     // bad-cell counter
     int32_t ns, nr, nruns;
     int32_t tile;                // cells per workgroup tile (<= 64)
+    int32_t waves;               // waves per workgroup of the single-request kernel (8 or 16)
+    int32_t pad;
     ShapeRun runs[kMaxRuns];
 };
 

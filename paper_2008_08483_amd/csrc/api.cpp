@@ -182,6 +182,9 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     view.ns = ns;
     view.nr = nr;
     view.tile = tile;
+    // 8-wave workgroups when two tiles share a CU's LDS, else one tile of 16
+    // waves, so that a CU runs 16 waves either way
+    view.waves = 2 * (size_t)ns * tile * kEntry <= (size_t)lds_max ? 8 : 16;
     std::vector<int> rxn_order(order);
     for (int i = 0; i < nr; ++i) {
         rxs[i] = rx[order[i]];

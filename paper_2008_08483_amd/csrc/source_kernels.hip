@@ -353,11 +353,12 @@ __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restr
     if (wave == 0 && valid && bad) atomicAdd(m.err, 1ull);
 }
 
-// Two 8-wave workgroups share a CU (4 waves per SIMD) only if each wave fits
-// in 128 VGPRs; without the cap the FP64 instantiation takes a few more and
-// drops to one workgroup per CU.
-// With 32 species per wave held in registers (more than 128 species, when
-// the LDS holds one tile per CU anyway) the cap is relaxed to 256 VGPRs.
+// Two 8-wave workgroups (or one of 16 waves) fill a CU with 4 waves per SIMD
+// only if each wave fits in 128 VGPRs; without the cap the FP64
+// instantiation takes a few more and drops to one 8-wave workgroup per CU.
+// With 32 species per wave held in registers (more than 128 species in
+// 8-wave workgroups, when the LDS holds one tile per CU anyway) the cap is
+// relaxed to 256 VGPRs.
 #define AK_TWO_TILES_PER_CU __attribute__((amdgpu_waves_per_eu(KMAX > 16 ? 2 : 4)))
 
 // One tile per workgroup.  (A persistent variant that fetched the next
@@ -411,9 +412,9 @@ source_batch_kernel(const BatchDesc *__restrict__ d, int nreq)
 // host-side launchers
 
 // species per wave held in registers: ns <= KMAX * WAVES
-static int kmax_for(int ns)
+static int kmax_for(int ns, int waves = AK_SOURCE_WAVES)
 {
-    const int per = (ns + AK_SOURCE_WAVES - 1) / AK_SOURCE_WAVES;
+    const int per = (ns + waves - 1) / waves;
     return per <= 2 ? 2 : per <= 8 ? 8 : per <= 16 ? 16 : 32;
 }
 
@@ -434,17 +435,27 @@ static hipError_t launch_source(const MechView &m, const void *T, const void *P,
     return hipGetLastError();
 }
 
+template <typename IO, bool F64, int W>
+static hipError_t launch_source_w(const MechView &m, const void *T, const void *P, const void *Y,
+                                  int64_t ldY, int64_t n, void *om, int64_t ldO, hipStream_t st)
+{
+    switch (kmax_for(m.ns, W)) {
+        case 2: return launch_source<IO, F64, W, 2>(m, T, P, Y, ldY, n, om, ldO, st);
+        case 8: return launch_source<IO, F64, W, 8>(m, T, P, Y, ldY, n, om, ldO, st);
+        case 16: return launch_source<IO, F64, W, 16>(m, T, P, Y, ldY, n, om, ldO, st);
+        default:
+            // 16 waves hold at most 16 species each (ns <= 256)
+            if constexpr (W == 16) return hipErrorInvalidValue;
+            else return launch_source<IO, F64, W, 32>(m, T, P, Y, ldY, n, om, ldO, st);
+    }
+}
+
 template <typename IO, bool F64>
 static hipError_t launch_source_k(const MechView &m, const void *T, const void *P, const void *Y,
                                   int64_t ldY, int64_t n, void *om, int64_t ldO, hipStream_t st)
 {
-    constexpr int W = AK_SOURCE_WAVES;
-    switch (kmax_for(m.ns)) {
-        case 2: return launch_source<IO, F64, W, 2>(m, T, P, Y, ldY, n, om, ldO, st);
-        case 8: return launch_source<IO, F64, W, 8>(m, T, P, Y, ldY, n, om, ldO, st);
-        case 16: return launch_source<IO, F64, W, 16>(m, T, P, Y, ldY, n, om, ldO, st);
-        default: return launch_source<IO, F64, W, 32>(m, T, P, Y, ldY, n, om, ldO, st);
-    }
+    if (m.waves == 16) return launch_source_w<IO, F64, 16>(m, T, P, Y, ldY, n, om, ldO, st);
+    return launch_source_w<IO, F64, AK_SOURCE_WAVES>(m, T, P, Y, ldY, n, om, ldO, st);
 }
 
 size_t source_lds_bytes(int ns, int tile) { return (size_t)ns * species_stride(tile); }
