@@ -212,11 +212,12 @@ def _run_trace(annkin, srv, dev_mechs, pools, arrivals, sizes, which, warmup):
     return srv.stats()
 
 
-def serving_bench(torch, annkin, n_req=10000, warmup=500):
+def serving_bench(torch, annkin, n_req=10000, warmup=500, trials=3):
     """Serving configuration: requests of log-uniform [64, 65536] cells, half
     on the 9/21 and half on the 53/325 mechanism (both resident), FP32.
     Capacity of the one-launch-per-request form measured closed-loop, then
-    both forms replay one seeded Poisson trace at 0.8x that capacity."""
+    both forms replay one seeded Poisson trace at 0.8x that capacity, three
+    times each, interleaved."""
     srcs = [synth.make_mechanism(9, 21), synth.make_mechanism(53, 325)]
     dev = [annkin.Mechanism(s) for s in srcs]
     nmax = 65536
@@ -246,14 +247,24 @@ def serving_bench(torch, annkin, n_req=10000, warmup=500):
     out = {"workload": "requests of log-uniform [64, 65536] cells, 50/50 9sp/21rxn and "
                        "53sp/325rxn mechanisms, FP32, Poisson arrivals",
            "capacity_one_launch_req_per_s": cap_s, "offered_req_per_s": rate,
-           "requests": n_req, "warmup_requests": warmup}
-    for name, batching in (("one_launch_per_request", False), ("continuous_batching", True)):
-        srv = annkin.Server(batching=batching, max_inflight=3, arena_bytes=1 << 30)
-        st = _run_trace(annkin, srv, dev, pools, arrivals, sizes, which, warmup)
-        srv.close()
-        out[name] = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
-                     "cells_per_s": st["cells_per_s"], "completed": st["completed"],
-                     "batches": st["batches"], "launches": st["launches"]}
+           "requests": n_req, "warmup_requests": warmup, "trials": trials,
+           "note": "p50/p99 are medians over trials of the same seeded trace, the two "
+                   "modes interleaved"}
+    runs = {"one_launch_per_request": [], "continuous_batching": []}
+    for _ in range(trials):
+        for name, batching in (("one_launch_per_request", False), ("continuous_batching", True)):
+            srv = annkin.Server(batching=batching, max_inflight=3, arena_bytes=1 << 30)
+            st = _run_trace(annkin, srv, dev, pools, arrivals, sizes, which, warmup)
+            srv.close()
+            runs[name].append(st)
+    for name, sts in runs.items():
+        med = lambda k: float(np.median([st[k] for st in sts]))
+        out[name] = {"p50_ms": med("p50_ms"), "p99_ms": med("p99_ms"), "mean_ms": med("mean_ms"),
+                     "cells_per_s": med("cells_per_s"),
+                     "p50_ms_trials": [st["p50_ms"] for st in sts],
+                     "p99_ms_trials": [st["p99_ms"] for st in sts],
+                     "completed": sts[-1]["completed"], "batches": sts[-1]["batches"],
+                     "launches": sts[-1]["launches"]}
     for d in dev:
         d.close()
     return out

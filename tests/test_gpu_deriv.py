@@ -150,6 +150,25 @@ def test_vjp_against_oracle_jacobian(torch, ak, dt):
     assert float(err.max()) <= (1e-11 if dt == "f64" else 1e-6)
 
 
+def test_jacobian_and_vjp_tiny_mechanism(torch, ak):
+    """Three species and two reactions: fewer species than the VJP's waves."""
+    src = synth.make_mechanism(3, 2, seed=7)
+    m = ak.Mechanism(src)
+    T, P, Y = synth.make_states(src, 97, 82)
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    J = ak.eval_jacobian(m, Tt, Pt, Yt)
+    g = np.random.default_rng(13).standard_normal((3, 97))
+    gY, gT = ak.eval_vjp(m, Tt, Pt, Yt, *_dev(torch, torch.float64, g))
+    torch.cuda.synchronize()
+    Jr, Ja = _jac_check(src, T, P, Y, J.cpu().numpy(), 1e-11)
+    Jr, Ja = Jr[:, :3, :].astype(np.float64), Ja[:, :3, :].astype(np.float64)
+    ref = np.einsum("ik,ikc->ic", g.T, Jr)
+    scale = np.einsum("ik,ikc->ic", np.abs(g.T), Ja)
+    got = np.concatenate([gY.cpu().numpy().T, gT.cpu().numpy()[:, None]], axis=1)
+    assert float((np.abs(got - ref) / scale).max()) <= 1e-11
+    m.close()
+
+
 def test_vjp_dot_product_identity(torch, ak):
     """<g, J v> = <J^T g, v> with the GPU Jacobian and the GPU VJP."""
     src, m = _mech(ak, 53, 325)

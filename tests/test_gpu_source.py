@@ -312,6 +312,19 @@ def test_200_species(torch, ak, prec):
     m.close()
 
 
+@pytest.mark.parametrize("ns,nr", [(3, 2), (5, 4)])
+def test_fewer_species_than_waves(torch, ak, ns, nr):
+    """Mechanisms smaller than a workgroup's 8 waves: some waves own no
+    species and only join the reaction sweep."""
+    src = synth.make_mechanism(ns, nr, seed=7)
+    m = ak.Mechanism(src)
+    T, P, Y = synth.make_states(src, 333, 81)
+    _check64(src, T, P, Y, _run(torch, ak, m, T, P, Y, torch.float64))
+    T32, P32, Y32 = synth.make_states(src, 333, 81, dtype=np.float32)
+    _check32(src, T32, P32, Y32, _run(torch, ak, m, T32, P32, Y32, torch.float32))
+    m.close()
+
+
 def test_abi_argument_errors(torch, ak):
     import ctypes as C
     src, m = _mech(ak, 9, 21)
