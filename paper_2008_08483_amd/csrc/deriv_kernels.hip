@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
 // Reactions are walked in the forward kernel's (shape, reversibility) runs so
 // that each molecule loop is unrolled for its shape.
 constexpr int kVjpEntry = 40;
-constexpr int kVjpWaves = 8;
+constexpr int kVjpWaves = 16;
 
 struct VjpCell {
     double log2T, invT;
