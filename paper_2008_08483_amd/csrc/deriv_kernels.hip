@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include "ak_device.h"
+#include "ak_math.h"
 
 namespace ak {
 
@@ -121,7 +122,8 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
         const double y = bad ? 0.0 : __builtin_fmax(sy[k], 0.0);
         const double C = rho * y * s.inv_W;
         const double g2 = gibbs2(s, lnT, T, T2, T3, T4, invT);
-        const double w = exp2(g2), v = exp2(-g2);
+        double w, v;
+        exp2_pair<12>(g2, w, v);
         const Thermo1 th = nasa(m.th[k], T, s.T_mid);
         sC[k] = C;
         sa[k] = C * w;
@@ -141,7 +143,8 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
         const RxnRec R = m.rx[j];
         const RxnAux X = m.aux[j];
         const int nf = X.nf, nr = X.nr, nm = nf + nr;
-        const double kf = exp2(__builtin_fma(R.beta, log2T, __builtin_fma(R.negEoR2, invT, R.log2A)));
+        const double kf =
+            scale_exp2(1.0, __builtin_fma(R.beta, log2T, __builtin_fma(R.negEoR2, invT, R.log2A)));
         double a[8], Ar = 1.0, Ap = 1.0, E = kf, dH = 0.0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -304,7 +307,7 @@ __device__ __forceinline__ void vjp_reaction(const RxnRec &R, double rev, unsign
     for (int i = 0; i < NM; ++i) {
         if (i < NF) Ar *= a[i]; else Ap *= a[i];
     }
-    const double Ek = exp2(t) * Vr;              // k_f prod_reac v
+    const double Ek = scale_exp2(Vr, t);         // k_f prod_reac v
     const double qf = Ek * Ar, qr = rev * Ek * Ap;
     const double EoR = -R.negEoR2 * 0.69314718055994530942;   // E/R
     const double dlnkf = (R.beta + EoR * c.invT) * c.invT;
@@ -385,8 +388,10 @@ __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int til
         const Thermo1 th = nasa(m.th[k], T, s.T_mid);
         double *e = E(k);
         const double yw = bad ? 0.0 : e[0];
-        e[0] = rho * yw * exp2(g2);
-        e[1] = exp2(-g2);
+        double w, v;
+        exp2_pair<12>(g2, w, v);
+        e[0] = rho * yw * w;
+        e[1] = v;
         e[2] = valid ? (double)G[k * ldG + cell] : 0.0;
         e[3] = th.h;
         e[4] = 0.0;
