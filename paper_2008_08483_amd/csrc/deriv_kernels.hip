@@ -168,18 +168,29 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
         const double dqT = qf * (dlnkf - nf * invT) - qr * (dlnkf - (dH - dn) * invT - nr * invT);
         const double wu = nf * qf - nr * qr;
         const double qn = qf - qr;
-        // d q_net / dC at each molecule slot (leave-one-out products)
+        // d q_net / dC at each molecule slot: the product of the other
+        // molecules of the same side, as prefix times suffix products
+        double pre[8], suf[8];
+        double p = 1.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i == nf) p = 1.0;
+            pre[i] = p;
+            if (i < nm) p *= a[i];
+        }
+        p = 1.0;
+#pragma unroll
+        for (int i = 7; i >= 0; --i) {
+            if (i == nf - 1) p = 1.0;
+            suf[i] = p;
+            if (i < nm) p *= a[i];
+        }
         double dq[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             if (i < nm) {
-                double loo = 1.0;
-                const bool reac = i < nf;
-#pragma unroll
-                for (int l = 0; l < 8; ++l)
-                    if (l != i && l < nm && ((l < nf) == reac)) loo *= a[l];
-                const double base = E * sw[X.sp[i]] * loo;
-                dq[i] = reac ? base : -rev * base;
+                const double base = E * sw[X.sp[i]] * (pre[i] * suf[i]);
+                dq[i] = i < nf ? base : -rev * base;
             }
         }
 #pragma unroll
@@ -201,9 +212,10 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
     // assembly of the composition columns (the temperature column already
     // holds the full d omega_k/dT: dq/dT above includes -(n_f q_f - n_r q_r)/T)
     const double inv_sigma = 1.0 / sigma;
-    for (int i = tid; i < ns * nv; i += kJacThreads) {
-        const int k = i / nv, c = i - k * nv;
-        if (c < ns) Jw[i] = ss[c] * (rho * Jw[i] - su[k] * inv_sigma);
+    const int wave = tid >> 6;
+    for (int k = wave; k < ns; k += kJacWaves) {   // row k by one wave, lane = column
+        const double uk = su[k] * inv_sigma;
+        for (int c = lane; c < ns; c += 64) Jw[k * nv + c] = ss[c] * (rho * Jw[k * nv + c] - uk);
     }
     // temperature-row sums: every wave, same order
     double num = 0.0, den = 0.0, omcp = 0.0, cdcp = 0.0;
@@ -220,7 +232,6 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
     __syncthreads();
     // temperature row: column c of d omega_T / dx; sum_k h_k J[k][c] in four
     // interleaved parts (thread = column c0 + lane, part = wave)
-    const int wave = tid >> 6;
     for (int c0 = 0; c0 < nv; c0 += 64) {
         const int c = c0 + lane;
         double dn = 0.0;
