@@ -34,7 +34,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_source_f32_53x325_1M.json
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("source_kernels.hip", "ak_device.h"):
+    for f in ("source_kernels.hip", "ak_device.h", "ak_math.h"):
         with open(os.path.join(ROOT, "paper_2008_08483_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
