@@ -392,6 +392,32 @@ def test_jacobian_conservation_and_homogeneity():
         assert np.abs(JY).max() <= 1e-12 * (np.abs(Ji[:, :ns]) @ np.abs(Y[:, i])).max()
 
 
+@pytest.mark.parametrize("ns,nr", [(9, 21), (53, 325)])
+def test_jacobian_at_equilibrium(ns, nr):
+    """At detailed balance q_f = q_r = q for every reaction, so
+    d omega / d ln C = -nu^T diag(q) nu (symmetric, negative semidefinite);
+    the composition block of the (Y, T) Jacobian is that matrix times
+    d ln C_l / d Y_m = delta_lm / Y_m - 1 / (sigma W_m), sigma = sum Y / W."""
+    mech = synth.make_mechanism(ns, nr)
+    rng = np.random.default_rng(11)
+    for T in (1000.0, 2200.0):
+        lam = rng.uniform(-14.0, -8.0, mech.n_elements)
+        P, Y = _equilibrium_state(mech, T, lam)
+        J = np.asarray(oracle.jacobian(mech, [T], [P], Y[:, None], precision="ld"), float)[0]
+        q = np.asarray(oracle.rates(mech, T, P, Y, precision="ld")["qf"], float)
+        nu = (mech.nu_r - mech.nu_f).astype(float)             # [reaction][species]
+        K = -(nu.T * q) @ nu
+        assert np.abs(K - K.T).max() <= 1e-12 * np.abs(K).max()
+        assert np.linalg.eigvalsh(K).max() <= 1e-10 * np.abs(K).max()
+        W = mech.W.astype(float)
+        sigma = float((Y / W).sum())
+        dlnC = np.diag(1.0 / Y) - 1.0 / (sigma * W)[None, :]   # [l][m]
+        expect = K @ dlnC
+        got = J[:ns, :ns]
+        scale = np.abs(K).max(axis=1, keepdims=True) * np.abs(dlnC).max()
+        assert float((np.abs(got - expect) / scale).max()) < 1e-10, T
+
+
 def test_jacobian_ld_matches_f64():
     mech, T, P, Y = synth.workload("c0", n_cells=16)
     a = oracle.jacobian(mech, T, P, Y)
