@@ -186,6 +186,19 @@ __device__ __forceinline__ void all_reactions(const MechView &m, int wave, unsig
     }
 }
 
+// Gibbs-layer output in base 2 for one species and cell (Eqs. 10-11): the
+// NASA range is chosen per cell (both polynomials are evaluated: a wave's
+// cells straddle T_mid more often than not).
+__device__ __forceinline__ double gibbs_g2(const SpeciesRec &sr, double T, double lnT, double T2,
+                                           double T3, double T4, double invT)
+{
+    const double glo = sr.lo[0] * lnT + sr.lo[1] * T + sr.lo[2] * T2 + sr.lo[3] * T3 +
+                       sr.lo[4] * T4 + sr.lo[5] * invT + sr.lo[6];
+    const double ghi = sr.hi[0] * lnT + sr.hi[1] * T + sr.hi[2] * T2 + sr.hi[3] * T3 +
+                       sr.hi[4] * T4 + sr.hi[5] * invT + sr.hi[6];
+    return T >= sr.T_mid ? ghi : glo;
+}
+
 // Inputs of one tile, loaded into registers before any LDS work so that all
 // of a wave's HBM reads are in flight at once: this wave's species
 // k = wave + i * WAVES (i < KMAX, k < ns), and T, P.  Lanes past the last
@@ -232,20 +245,6 @@ __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restr
     const uint32_t sstride = species_stride(tile);
     const uint32_t lane_off = (uint32_t)lane * kEntry;
 
-    // (1) this wave's species: y_k = max(Y_k, 0) / W_k into the a-slot, and
-    //     a partial mixture sum (NaN if any input is not finite)
-    double psum = 0.0;
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-        const int k = wave + i * WAVES;
-        if (k < m.ns) {
-            const double y = (double)in.y[i];
-            const double yw = __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
-            psum += __builtin_isfinite(y) ? yw : __builtin_nan("");
-            *(double *)(lds + (uint32_t)k * sstride + lane_off) = yw;
-        }
-    }
-    if (wave < m.ns) *(double *)(lds + (uint32_t)wave * sstride + lane_off + 16) = psum;
     double Tc = (double)in.T;
     double Pc = (double)in.P;
     const bool tp_bad = !(Tc > 0.0) || !(Pc > 0.0) || !__builtin_isfinite(Tc) ||
@@ -254,48 +253,68 @@ __device__ __forceinline__ void source_tile(const MechView &m, const IO *__restr
         Tc = 1000.0;
         Pc = 1.0e5;
     }
+    const double lnT = log(Tc), invT = 1.0 / Tc;
+    const double T2 = Tc * Tc, T3 = T2 * Tc, T4 = T3 * Tc;
+
+    // (1) this wave's species k = wave + i * WAVES: y_k = max(Y_k, 0) / W_k
+    //     and a partial mixture sum (NaN if any input is not finite).  With
+    //     at most 8 species per wave the Gibbs layer (Eqs. 10-11) and the
+    //     exponentials of the chemical potentials are evaluated here too, all
+    //     species at once, so that their dependency chains overlap each other
+    //     and the mass fractions still in flight; with more they wait for (3)
+    //     and the exponentials are computed one species at a time.
+    constexpr bool kEarly = KMAX <= 8;
+    double w[KMAX], v[KMAX], yw[KMAX];
+    double psum = 0.0;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        const int k = wave + i * WAVES;
+        if (k < m.ns) {
+            const SpeciesRec &sr = m.sp[k];
+            if constexpr (kEarly)
+                exp2_pair<F64 ? 12 : 10>(gibbs_g2(sr, Tc, lnT, T2, T3, T4, invT), w[i], v[i]);
+            const double y = (double)in.y[i];
+            yw[i] = __builtin_fmax(y, 0.0) * sr.inv_W;
+            psum += __builtin_isfinite(y) ? yw[i] : __builtin_nan("");
+            if constexpr (!kEarly) *(double *)(lds + (uint32_t)k * sstride + lane_off) = yw[i];
+        }
+    }
+    if (wave < m.ns) *(double *)(lds + (uint32_t)wave * sstride + lane_off + 16) = psum;
     __syncthreads();
     // (2) mixture sum, same order in every wave
     double sigma = 0.0;
     const int nparts = m.ns < WAVES ? m.ns : WAVES;
-    for (int w = 0; w < nparts; ++w)
-        sigma += *(const double *)(lds + (uint32_t)w * sstride + lane_off + 16);
+    for (int p = 0; p < nparts; ++p)
+        sigma += *(const double *)(lds + (uint32_t)p * sstride + lane_off + 16);
     __syncthreads();
 
     const bool bad = tp_bad || !(sigma > 0.0) || !__builtin_isfinite(sigma);
     if (bad) sigma = 1.0;
-    const double lnT = log(Tc), invT = 1.0 / Tc;
-    const double T2 = Tc * Tc, T3 = T2 * Tc, T4 = T3 * Tc;
     const double rho_hat = Pc / (kRu * Tc * sigma);   // C_k = rho_hat * Y_k / W_k
 
-    // (3) Gibbs layer (Eqs. 10-11) and the exponentials of the chemical
-    //     potentials for this wave's species.  The NASA range is chosen per
-    //     cell; when the whole wave is on one side of T_mid only that
-    //     polynomial is evaluated.
-    for (int k = wave; k < m.ns; k += WAVES) {
-        const SpeciesRec &s = m.sp[k];
-        const bool high = Tc >= s.T_mid;
-        double g2;
-        if (__builtin_amdgcn_read_exec() == __ballot(high)) {
-            g2 = s.hi[0] * lnT + s.hi[1] * Tc + s.hi[2] * T2 + s.hi[3] * T3 + s.hi[4] * T4 +
-                 s.hi[5] * invT + s.hi[6];
-        } else if (__ballot(high) == 0) {
-            g2 = s.lo[0] * lnT + s.lo[1] * Tc + s.lo[2] * T2 + s.lo[3] * T3 + s.lo[4] * T4 +
-                 s.lo[5] * invT + s.lo[6];
-        } else {
-            const double glo = s.lo[0] * lnT + s.lo[1] * Tc + s.lo[2] * T2 + s.lo[3] * T3 +
-                               s.lo[4] * T4 + s.lo[5] * invT + s.lo[6];
-            const double ghi = s.hi[0] * lnT + s.hi[1] * Tc + s.hi[2] * T2 + s.hi[3] * T3 +
-                               s.hi[4] * T4 + s.hi[5] * invT + s.hi[6];
-            g2 = high ? ghi : glo;
+    // (3) the LDS entries of this wave's species: a = C e^{Gt}, v = e^{-Gt},
+    //     accumulator 0
+    if constexpr (kEarly) {
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
+            const int k = wave + i * WAVES;
+            if (k < m.ns) {
+                double *e = (double *)(lds + (uint32_t)k * sstride + lane_off);
+                e[0] = rho_hat * (bad ? 0.0 : yw[i]) * w[i];
+                e[1] = v[i];
+                e[2] = 0.0;
+            }
         }
-        double w, v;
-        exp2_pair<F64 ? 12 : 10>(g2, w, v);
-        double *e = (double *)(lds + (uint32_t)k * sstride + lane_off);
-        const double yw = bad ? 0.0 : e[0];
-        e[0] = rho_hat * yw * w;
-        e[1] = v;
-        e[2] = 0.0;
+    } else {
+        for (int k = wave; k < m.ns; k += WAVES) {
+            double wk, vk;
+            exp2_pair<F64 ? 12 : 10>(gibbs_g2(m.sp[k], Tc, lnT, T2, T3, T4, invT), wk, vk);
+            double *e = (double *)(lds + (uint32_t)k * sstride + lane_off);
+            const double ywk = bad ? 0.0 : e[0];
+            e[0] = rho_hat * ywk * wk;
+            e[1] = vk;
+            e[2] = 0.0;
+        }
     }
     __syncthreads();
 
