@@ -202,7 +202,7 @@ __device__ __forceinline__ double gibbs_g2(const SpeciesRec &sr, double T, doubl
 // Inputs of one tile, loaded into registers before any LDS work so that all
 // of a wave's HBM reads are in flight at once: this wave's species
 // k = wave + i * WAVES (i < KMAX, k < ns), and T, P.  Lanes past the last
-// cell read nothing and take harmless defaults.
+// cell hold cell 0's state.
 template <typename IO, int KMAX>
 struct TileIn {
     IO y[KMAX];
@@ -217,12 +217,19 @@ __device__ __forceinline__ void load_tile(const MechView &m, const IO *__restric
 {
     const int64_t cell = tile_idx * m.tile + lane;
     const bool valid = cell < n;
-    in.T = valid ? T[cell] : (IO)1000.0;
-    in.P = valid ? P[cell] : (IO)1.0e5;
+    // Every load is issued unconditionally, with no select after it: lanes
+    // past the last cell read cell 0 (their results are never stored) and
+    // slots past the last species read species 0 (never used).  A load under
+    // a branch, or followed by a select of a default, made the compiler wait
+    // for it right away, so the wave's loads went out one or two at a time
+    // instead of all together.
+    const int64_t c = valid ? cell : 0;
+    in.T = T[c];
+    in.P = P[c];
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
         const int k = wave + i * WAVES;
-        in.y[i] = (valid && k < m.ns) ? Y[k * ldY + cell] : (IO)1.0;
+        in.y[i] = Y[(k < m.ns ? k : 0) * ldY + c];
     }
 }
 
