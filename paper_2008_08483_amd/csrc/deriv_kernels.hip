@@ -347,7 +347,8 @@ __device__ __forceinline__ void vjp_run(const MechView &m, const ShapeRun run, i
         vjp_reaction<NF, NR>(m.rx[j], run.rev, vl, lane_off, sstride, c, s_acc, tbar);
 }
 
-template <typename IO>
+// KV: species per wave held in registers (ns <= KV * kVjpWaves)
+template <typename IO, int KV>
 __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int tile,
                                                              const IO *__restrict__ Tin,
                                                              const IO *__restrict__ Pin,
@@ -369,16 +370,33 @@ __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int til
     const uint32_t lane_off = (uint32_t)lane * kVjpEntry;
     auto E = [&](int k) { return (double *)(vl + (uint32_t)k * sstride + lane_off); };
 
-    double T = valid ? (double)Tin[cell] : 1000.0;
-    double P = valid ? (double)Pin[cell] : 1.0e5;
+    // all of this wave's inputs requested at once, with no branch or select
+    // after the loads (which would make the compiler wait for each in turn):
+    // lanes past the last cell read cell 0 and slots past the last species
+    // read species 0, and neither result is stored
+    const int64_t c0 = valid ? cell : 0;
+    double T = (double)Tin[c0];
+    double P = (double)Pin[c0];
+    IO yv[KV], gv[KV];
+#pragma unroll
+    for (int i = 0; i < KV; ++i) {
+        const int k = wave + i * kVjpWaves;
+        const int64_t kk = k < m.ns ? k : 0;
+        yv[i] = Y[kk * ldY + c0];
+        gv[i] = G[kk * ldG + c0];
+    }
     // this wave's species: y_k^+ / W_k into the a-slot, partial mixture sums
     // (NaN for a non-finite input) meeting in LDS
     double psum = 0.0;
-    for (int k = wave; k < m.ns; k += kVjpWaves) {
-        const double y = valid ? (double)Y[k * ldY + cell] : 1.0;
-        const double yw = __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
-        psum += __builtin_isfinite(y) ? yw : __builtin_nan("");
-        E(k)[0] = yw;
+#pragma unroll
+    for (int i = 0; i < KV; ++i) {
+        const int k = wave + i * kVjpWaves;
+        if (k < m.ns) {
+            const double y = (double)yv[i];
+            const double yw = __builtin_fmax(y, 0.0) * m.sp[k].inv_W;
+            psum += __builtin_isfinite(y) ? yw : __builtin_nan("");
+            E(k)[0] = yw;
+        }
     }
     partial[wave][0][lane] = psum;
     __syncthreads();
@@ -393,19 +411,23 @@ __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int til
     }
     const double lnT = log(T), invT = 1.0 / T, T2 = T * T, T3 = T2 * T, T4 = T3 * T;
     const double rho = P / (kRu * T * sigma);
-    for (int k = wave; k < m.ns; k += kVjpWaves) {
-        const SpeciesRec &s = m.sp[k];
-        const double g2 = gibbs2(s, lnT, T, T2, T3, T4, invT);
-        const Thermo1 th = nasa(m.th[k], T, s.T_mid);
-        double *e = E(k);
-        const double yw = bad ? 0.0 : e[0];
-        double w, v;
-        exp2_pair<12>(g2, w, v);
-        e[0] = rho * yw * w;
-        e[1] = v;
-        e[2] = valid ? (double)G[k * ldG + cell] : 0.0;
-        e[3] = th.h;
-        e[4] = 0.0;
+#pragma unroll
+    for (int i = 0; i < KV; ++i) {
+        const int k = wave + i * kVjpWaves;
+        if (k < m.ns) {
+            const SpeciesRec &s = m.sp[k];
+            const double g2 = gibbs2(s, lnT, T, T2, T3, T4, invT);
+            const Thermo1 th = nasa(m.th[k], T, s.T_mid);
+            double *e = E(k);
+            const double yw = bad ? 0.0 : e[0];
+            double w, v;
+            exp2_pair<12>(g2, w, v);
+            e[0] = rho * yw * w;
+            e[1] = v;
+            e[2] = (double)gv[i];
+            e[3] = th.h;
+            e[4] = 0.0;
+        }
     }
     __syncthreads();      // also: every wave has read `partial` above
 
@@ -441,10 +463,12 @@ __global__ __launch_bounds__(64 * kVjpWaves) void vjp_kernel(MechView m, int til
     }
     const IO nan = __builtin_nan("");
     // Y_bar_m = [Y_m >= 0] (rho w_m a_bar_m - s/sigma) / W_m; T_bar = sum q_bar dq/dT
-    for (int k = wave; k < m.ns; k += kVjpWaves) {
-        if (valid) {
+#pragma unroll
+    for (int i = 0; i < KV; ++i) {
+        const int k = wave + i * kVjpWaves;
+        if (k < m.ns && valid) {
             const double *e = E(k);
-            const double ycl = (double)Y[k * ldY + cell] >= 0.0 ? 1.0 : 0.0;
+            const double ycl = (double)yv[i] >= 0.0 ? 1.0 : 0.0;
             const double gy = ycl * (rho * e[4] / e[1] - s_tot / sigma) * m.sp[k].inv_W;
             GY[k * ldGY + cell] = bad ? nan : (IO)gy;
         }
@@ -500,31 +524,37 @@ int vjp_tile(int ns, int lds_max)
     return t > 64 ? 64 : t;
 }
 
+template <typename IO, int KV>
+static hipError_t vjp_launch_t(const MechView &m, int tile, const void *T, const void *P,
+                               const void *Y, int64_t ldY, int64_t n, const void *G, int64_t ldG,
+                               void *GY, int64_t ldGY, void *GT, int64_t blocks, hipStream_t st)
+{
+    const size_t lds = (size_t)m.ns * tile * kVjpEntry;
+    auto fn = vjp_kernel<IO, KV>;
+    hipError_t e = hipFuncSetAttribute((const void *)fn,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * kVjpWaves), lds, st, m, tile,
+                       (const IO *)T, (const IO *)P, (const IO *)Y, ldY, n, (const IO *)G, ldG,
+                       (IO *)GY, ldGY, (IO *)GT);
+    return hipGetLastError();
+}
+
 hipError_t vjp_launch(const MechView &m, int tile, bool f64, const void *T, const void *P,
                       const void *Y, int64_t ldY, int64_t n, const void *G, int64_t ldG,
                       void *GY, int64_t ldGY, void *GT, hipStream_t st)
 {
-    const size_t lds = (size_t)m.ns * tile * kVjpEntry;
     const int64_t blocks = (n + tile - 1) / tile;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const int per = (m.ns + kVjpWaves - 1) / kVjpWaves;   // ns <= 256: at most 16
     if (f64) {
-        auto fn = vjp_kernel<double>;
-        hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * kVjpWaves), lds, st, m, tile,
-                           (const double *)T, (const double *)P, (const double *)Y, ldY, n,
-                           (const double *)G, ldG, (double *)GY, ldGY, (double *)GT);
-    } else {
-        auto fn = vjp_kernel<float>;
-        hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * kVjpWaves), lds, st, m, tile,
-                           (const float *)T, (const float *)P, (const float *)Y, ldY, n,
-                           (const float *)G, ldG, (float *)GY, ldGY, (float *)GT);
+        if (per <= 4) return vjp_launch_t<double, 4>(m, tile, T, P, Y, ldY, n, G, ldG, GY, ldGY, GT, blocks, st);
+        if (per <= 8) return vjp_launch_t<double, 8>(m, tile, T, P, Y, ldY, n, G, ldG, GY, ldGY, GT, blocks, st);
+        return vjp_launch_t<double, 16>(m, tile, T, P, Y, ldY, n, G, ldG, GY, ldGY, GT, blocks, st);
     }
-    return hipGetLastError();
+    if (per <= 4) return vjp_launch_t<float, 4>(m, tile, T, P, Y, ldY, n, G, ldG, GY, ldGY, GT, blocks, st);
+    if (per <= 8) return vjp_launch_t<float, 8>(m, tile, T, P, Y, ldY, n, G, ldG, GY, ldGY, GT, blocks, st);
+    return vjp_launch_t<float, 16>(m, tile, T, P, Y, ldY, n, G, ldG, GY, ldGY, GT, blocks, st);
 }
 
 }  // namespace ak
