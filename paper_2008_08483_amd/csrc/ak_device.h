@@ -83,6 +83,13 @@ struct MechView {
     int32_t waves;               // waves per workgroup of the single-request kernel (8 or 16)
     int32_t pad;
     ShapeRun runs[kMaxRuns];
+    // The forward kernels' split of the reaction sweep: with W waves, wave w
+    // takes the contiguous range [seg8[w], seg8[w + 1]) of the sorted
+    // reactions (W = 8) or [seg16[w], seg16[w + 1]) (W = 16), ranges of
+    // about equal estimated cost.
+    int32_t seg8[9];
+    int32_t seg16[17];
+    int32_t pad3[2];
 };
 
 // One request of a fused multi-request launch (device-resident table).

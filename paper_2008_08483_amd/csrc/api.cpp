@@ -200,6 +200,24 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
         }
         view.runs[view.nruns - 1].count++;
     }
+    // contiguous per-wave ranges of the sorted reactions, split by an
+    // estimate of each reaction's LDS work (a read and an atomic add per
+    // molecule, on top of a fixed cost per reaction)
+    {
+        std::vector<double> cum(nr + 1, 0.0);
+        for (int i = 0; i < nr; ++i)
+            cum[i + 1] = cum[i] + 20.0 + 15.4 * auxs[i].nf + 13.9 * auxs[i].nr;
+        auto split = [&](int32_t *seg, int w) {
+            int i = 0;
+            for (int k = 0; k <= w; ++k) {
+                const double target = cum[nr] * k / w;
+                while (i < nr && cum[i] < target) ++i;
+                seg[k] = k == w ? nr : i;
+            }
+        };
+        split(view.seg8, 8);
+        split(view.seg16, 16);
+    }
 
     ak_mechanism *m = new (std::nothrow) ak_mechanism();
     if (!m) return set_error(AK_ENOMEM, "ak_load_mechanism: out of host memory");

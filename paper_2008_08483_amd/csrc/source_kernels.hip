@@ -121,29 +121,29 @@ __device__ __forceinline__ double hold(double x, const double (&h)[8])
 #define AK_REACTION_GROUP 2
 #endif
 
-// Reactions of one run: this wave takes reactions start+wave,
-// start+wave+WAVES, ...; U at a time so that their LDS reads overlap, with
-// the next group's records requested while the current group computes.
-template <bool F64, int NF, int NR, int WAVES, int U = AK_REACTION_GROUP>
-__device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun run, int wave,
-                                             unsigned char *lds, uint32_t lane_off,
+// The reactions of one run that lie in this wave's range [lo, hi) of the
+// sorted list, U consecutive ones at a time so that their LDS reads overlap,
+// with the next group's records requested while the current group computes.
+template <bool F64, int NF, int NR, int U = AK_REACTION_GROUP>
+__device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun run, int lo,
+                                             int hi, unsigned char *lds, uint32_t lane_off,
                                              uint32_t sstride, const Cell c)
 {
-    const int end = run.start + run.count;
-    int j = run.start + wave;
+    const int end = run.start + run.count < hi ? run.start + run.count : hi;
+    int j = run.start > lo ? run.start : lo;
     if (j >= end) return;
     const double rev = run.rev;
     RxnRec r[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) r[u] = m.rx[j + u * WAVES < end ? j + u * WAVES : j];
+    for (int u = 0; u < U; ++u) r[u] = m.rx[j + u < end ? j + u : j];
     double h[2 * U];
 #pragma unroll
     for (int i = 0; i < 2 * U; ++i) h[i] = 0.0;
-    for (; j < end; j += U * WAVES) {
+    for (; j < end; j += U) {
         RxnRec nx[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int k = j + (U + u) * WAVES;
+            const int k = j + U + u;
             nx[u] = m.rx[k < end ? k : j];
         }
         uint32_t a[U][NF + NR];
@@ -155,7 +155,7 @@ __device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun r
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const double nq = -q[u];
-            if (u == 0 || j + u * WAVES < end) scatter<NF, NR>(lds, a[u], q[u], nq);
+            if (u == 0 || j + u < end) scatter<NF, NR>(lds, a[u], q[u], nq);
             h[2 * u] = q[u];
             h[2 * u + 1] = nq;
         }
@@ -164,16 +164,24 @@ __device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun r
     }
 }
 
+// This wave's share of the sweep: the contiguous range of the sorted
+// reactions given by the mechanism's per-wave split, run by run.  (Taking
+// every WAVES-th reaction of each run instead left each wave only a few
+// reactions per run, and every run started its record pipeline afresh.)
 template <bool F64, int WAVES>
 __device__ __forceinline__ void all_reactions(const MechView &m, int wave, unsigned char *lds,
                                               uint32_t lane_off, uint32_t sstride, const Cell c)
 {
+    const int32_t *seg = WAVES == 16 ? m.seg16 : m.seg8;
+    const int lo = seg[wave], hi = seg[wave + 1];
     for (int r = 0; r < m.nruns; ++r) {
         const ShapeRun run = m.runs[r];
+        if (run.start >= hi) break;
+        if (run.start + run.count <= lo) continue;
         const int s = (run.nf - 1) * 4 + (run.nr - 1);
 #define AK_CASE(a, b)                                                                          \
     case (a - 1) * 4 + (b - 1):                                                                \
-        reaction_run<F64, a, b, WAVES>(m, run, wave, lds, lane_off, sstride, c);               \
+        reaction_run<F64, a, b>(m, run, lo, hi, lds, lane_off, sstride, c);                    \
         break;
         switch (s) {
             AK_CASE(1, 1) AK_CASE(1, 2) AK_CASE(1, 3) AK_CASE(1, 4)
