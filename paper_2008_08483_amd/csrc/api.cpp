@@ -201,12 +201,15 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
         view.runs[view.nruns - 1].count++;
     }
     // contiguous per-wave ranges of the sorted reactions, split by an
-    // estimate of each reaction's LDS work (a read and an atomic add per
-    // molecule, on top of a fixed cost per reaction)
+    // estimate of each reaction's sweep time: 16 + s^2 with s molecules (a
+    // fit of measured per-wave sweep times; per-molecule costs grow with s
+    // as the reaction's LDS reads and atomics contend)
     {
         std::vector<double> cum(nr + 1, 0.0);
-        for (int i = 0; i < nr; ++i)
-            cum[i + 1] = cum[i] + 20.0 + 15.4 * auxs[i].nf + 13.9 * auxs[i].nr;
+        for (int i = 0; i < nr; ++i) {
+            const double s = auxs[i].nf + auxs[i].nr;
+            cum[i + 1] = cum[i] + 16.0 + s * s;
+        }
         auto split = [&](int32_t *seg, int w) {
             int i = 0;
             for (int k = 0; k <= w; ++k) {
