@@ -42,6 +42,10 @@ struct RxnRec {
 };
 static_assert(sizeof(RxnRec) == 32, "RxnRec layout");
 
+// zero records after the last reaction in the device array (reads ahead of
+// a wave's range may touch them)
+constexpr int kRecordPad = 4;
+
 constexpr int kMaxSpecies = 256;
 constexpr int kMaxSide = 4;      // molecules per side
 constexpr int kMaxRuns = 32;     // (nf, nr) in 1..4 x 1..4, reversible or not

@@ -233,7 +233,7 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     // one device allocation holds every table
     const size_t o_sp = 0;
     const size_t o_rx = o_sp + ((sizeof(SpeciesRec) * ns + 255) & ~(size_t)255);
-    const size_t o_th = o_rx + ((sizeof(RxnRec) * nr + 255) & ~(size_t)255);
+    const size_t o_th = o_rx + ((sizeof(RxnRec) * (nr + kRecordPad) + 255) & ~(size_t)255);
     const size_t o_aux = o_th + ((sizeof(ThermoRec) * ns + 255) & ~(size_t)255);
     const size_t o_err = o_aux + ((sizeof(RxnAux) * nr + 255) & ~(size_t)255);
     const size_t bytes = o_err + 256;

@@ -120,6 +120,7 @@ __device__ __forceinline__ double hold(double x, const double (&h)[8])
 #ifndef AK_REACTION_GROUP
 #define AK_REACTION_GROUP 2
 #endif
+static_assert(2 * AK_REACTION_GROUP <= kRecordPad, "record reads ahead need the padding");
 
 // The reactions of one run that lie in this wave's range [lo, hi) of the
 // sorted list, U consecutive ones at a time so that their LDS reads overlap,
@@ -133,19 +134,20 @@ __device__ __forceinline__ void reaction_run(const MechView &m, const ShapeRun r
     int j = run.start > lo ? run.start : lo;
     if (j >= end) return;
     const double rev = run.rev;
+    // records through a running pointer: the array carries kRecordPad zero
+    // records past the last reaction, so the reads ahead of the range need
+    // no clamping (what they fetch past `end` is never used)
+    const RxnRec *rp = m.rx + j;
     RxnRec r[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) r[u] = m.rx[j + u < end ? j + u : j];
+    for (int u = 0; u < U; ++u) r[u] = rp[u];
     double h[2 * U];
 #pragma unroll
     for (int i = 0; i < 2 * U; ++i) h[i] = 0.0;
-    for (; j < end; j += U) {
+    for (; j < end; j += U, rp += U) {
         RxnRec nx[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = j + U + u;
-            nx[u] = m.rx[k < end ? k : j];
-        }
+        for (int u = 0; u < U; ++u) nx[u] = rp[U + u];
         uint32_t a[U][NF + NR];
         double q[U];
         q[0] = hold(rate_of_progress<F64, NF, NR>(r[0], rev, lds, lane_off, sstride, c, a[0]), h);
