@@ -27,11 +27,40 @@ __device__ __forceinline__ void lds_addd(double *p, double x)
     __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// x moved across lanes by one DPP pattern (both halves of the double);
+// lanes with no source lane take 0
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x)
+{
+    int w[2];
+    __builtin_memcpy(w, &x, 8);
+    w[0] = __builtin_amdgcn_update_dpp(0, w[0], CTRL, 0xf, 0xf, false);
+    w[1] = __builtin_amdgcn_update_dpp(0, w[1], CTRL, 0xf, 0xf, false);
+    double r;
+    __builtin_memcpy(&r, w, 8);
+    return r;
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), the same value in
+// every lane and in every wave for the same inputs: scans within rows of 16
+// lanes (row_shr 1, 2, 4, 8), then across rows (row_bcast 15, 31), which
+// leaves the total in lane 63.  DPP moves stay in the vector registers, where
+// a shuffle goes through the LDS crossbar.
 __device__ __forceinline__ double wave_sum(double x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    x += dpp_move<0x111>(x);
+    x += dpp_move<0x112>(x);
+    x += dpp_move<0x114>(x);
+    x += dpp_move<0x118>(x);
+    x += dpp_move<0x142>(x);
+    x += dpp_move<0x143>(x);
+    int w[2];
+    __builtin_memcpy(w, &x, 8);
+    w[0] = __builtin_amdgcn_readlane(w[0], 63);
+    w[1] = __builtin_amdgcn_readlane(w[1], 63);
+    double r;
+    __builtin_memcpy(&r, w, 8);
+    return r;
 }
 
 struct Thermo1 {
@@ -213,9 +242,16 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
     // holds the full d omega_k/dT: dq/dT above includes -(n_f q_f - n_r q_r)/T)
     const double inv_sigma = 1.0 / sigma;
     const int wave = tid >> 6;
-    for (int k = wave; k < ns; k += kJacWaves) {   // row k by one wave, lane = column
-        const double uk = su[k] * inv_sigma;
-        for (int c = lane; c < ns; c += 64) Jw[k * nv + c] = ss[c] * (rho * Jw[k * nv + c] - uk);
+    for (int c0 = 0; c0 < ns; c0 += 64) {          // lane = column, rows k split by wave
+        const int c = c0 + lane;
+        if (c < ns) {
+            const double ssc = ss[c];
+#pragma unroll 4
+            for (int k = wave; k < ns; k += kJacWaves) {
+                double *jp = &Jw[k * nv + c];
+                *jp = ssc * (rho * *jp - su[k] * inv_sigma);
+            }
+        }
     }
     // temperature-row sums: every wave, same order
     double num = 0.0, den = 0.0, omcp = 0.0, cdcp = 0.0;
