@@ -168,7 +168,12 @@ __global__ __launch_bounds__(kJacThreads) void jacobian_kernel(MechView m,
     __syncthreads();
 
     const double log2T = lnT * kLog2e;
-    for (int j = tid; j < m.nr; j += kJacThreads) {
+    // reactions are sorted by molecule count, so walking them from the end
+    // gives the first pass the expensive shapes and leaves the cheap ones for
+    // the partial second pass (a wave's predicated loops run to the largest
+    // molecule count among its lanes)
+    for (int jr = tid; jr < m.nr; jr += kJacThreads) {
+        const int j = m.nr - 1 - jr;
         const RxnRec R = m.rx[j];
         const RxnAux X = m.aux[j];
         const int nf = X.nf, nr = X.nr, nm = nf + nr;
