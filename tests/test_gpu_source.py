@@ -257,6 +257,18 @@ def test_full_size_sampled_fp32(torch, ak):
     _check32(src, T[idx], P[idx], Y[:, idx], om[:, idx])
 
 
+def test_full_size_sampled_fp64(torch, ak):
+    """The FP64 path on the same 53/325 x 2^20 states (upcast, as timed
+    beside the FP32 path); sampled cells against the oracle."""
+    src, m = _mech(ak, 53, 325)
+    _, T, P, Y = synth.workload("c1_full", dtype=np.float32)
+    T, P, Y = (np.asarray(a, np.float64) for a in (T, P, Y))
+    om = _run(torch, ak, m, T, P, Y, torch.float64)
+    idx = np.sort(np.random.default_rng(5).choice(T.shape[0], 1024, replace=False))
+    idx = np.concatenate([idx, [0, T.shape[0] - 1]])
+    _check64(src, T[idx], P[idx], Y[:, idx], om[:, idx])
+
+
 def test_c2_fp32_sampled(torch, ak):
     src, m = _mech(ak, 111, 784)
     _, T, P, Y = synth.workload("c2", n_cells=1 << 18, dtype=np.float32)
