@@ -150,6 +150,39 @@ def test_vjp_against_oracle_jacobian(torch, ak, dt):
     assert float(err.max()) <= (1e-11 if dt == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_jacobian_and_vjp_full_size_sampled(torch, ak, dt):
+    """53/325 x 65,536 cells in the benchmark's launch configuration (the
+    same states, cast to the precision); sampled cells against the oracle."""
+    src, m = _mech(ak, 53, 325)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    npdt = np.float64 if dt == "f64" else np.float32
+    tol = 1e-11 if dt == "f64" else 1e-6
+    _, T, P, Y = synth.workload("c4")
+    T, P, Y = (np.asarray(a, npdt) for a in (T, P, Y))
+    n = T.shape[0]
+    g = np.random.default_rng(21).standard_normal((53, n)).astype(npdt)
+    Tt, Pt, Yt, gt = _dev(torch, tdt, T, P, Y, g)
+    J = ak.eval_jacobian(m, Tt, Pt, Yt)
+    gY, gT = ak.eval_vjp(m, Tt, Pt, Yt, gt)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(22).choice(n, 96, replace=False))
+    idx = np.concatenate([[0], idx, [n - 1]])
+    it = torch.tensor(idx, device="cuda")
+    Js = J[it].cpu().numpy().astype(np.float64)
+    gYs = gY[:, it].cpu().numpy().astype(np.float64)
+    gTs = gT[it].cpu().numpy().astype(np.float64)
+    T64, P64, Y64, g64 = (np.asarray(a, np.float64) for a in (T[idx], P[idx], Y[:, idx], g[:, idx]))
+    Jr, Ja = _jac_check(src, T64, P64, Y64, Js, tol)
+    Jr, Ja = Jr[:, :53, :].astype(np.float64), Ja[:, :53, :].astype(np.float64)
+    ref = np.einsum("ik,ikc->ic", g64.T, Jr)
+    scale = np.einsum("ik,ikc->ic", np.abs(g64.T), Ja)
+    got = np.concatenate([gYs.T, gTs[:, None]], axis=1)
+    err = float((np.abs(got - ref) / scale).max())
+    print("vjp max err/scale", err, flush=True)
+    assert err <= tol
+
+
 def test_jacobian_and_vjp_tiny_mechanism(torch, ak):
     """Three species and two reactions: fewer species than the VJP's waves."""
     src = synth.make_mechanism(3, 2, seed=7)
