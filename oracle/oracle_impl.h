@@ -224,9 +224,15 @@ int SFX(ora_jacobian)(const ora_mech *m, int64_t n, const double *T, const doubl
     return SFX(ora_jacobian_scaled)(m, n, T, P, Y, ldY, J, 0, ldJ, n_threads);
 }
 
-/* As ora_jacobian, and (if Jabs is not NULL) the gross scale of every entry:
- * the same chain-rule sums with every term replaced by its absolute value,
- * the rounding-error scale for grading a Jacobian computed another way. */
+/* As ora_jacobian, and (if Jabs is not NULL) the gross scale of every entry,
+ * the rounding-error scale for grading a Jacobian computed another way:
+ *   rows k < NS:  S^J_kc = sum_j |nu_kj| (|d q_f,j / d x_c| + |d q_r,j / d x_c|)
+ * with d/dx_c the total derivative with respect to x_c = Y_c or T (the
+ * forward and reverse rates kept apart, so that their cancellation does not
+ * shrink the scale);
+ *   row NS (omega_T = -num/den): (|d num| |den| + |num| |d den|) / den^2 with
+ *   |d num| = sum_k |Ru T h_k| S^J_kc (+ sum_k |Ru cp_k omega_k| for c = T) and
+ *   |d den| = sum_k |Ru cp_k dC_k/dx_c| (+ sum_k |C_k Ru dcp_k| for c = T). */
 int SFX(ora_jacobian_scaled)(const ora_mech *m, int64_t n, const double *T, const double *P,
                              const double *Y, int64_t ldY, REAL *J, REAL *Jabs, int64_t ldJ,
                              int n_threads)
@@ -238,7 +244,7 @@ int SFX(ora_jacobian_scaled)(const ora_mech *m, int64_t n, const double *T, cons
 #pragma omp parallel
 #endif
     {
-        REAL *buf = (REAL *)malloc(sizeof(REAL) * (9 * ns + 2 * ns * nv + 2 * nv * nv));
+        REAL *buf = (REAL *)malloc(sizeof(REAL) * (10 * ns + 2 * ns * nv + 2 * nv * nv));
         if (!buf) {
             err = -1;
         } else {
@@ -247,7 +253,8 @@ int SFX(ora_jacobian_scaled)(const ora_mech *m, int64_t n, const double *T, cons
             REAL *dCdx = dqdC + ns;                   /* [ns][nv] */
             REAL *Jc = dCdx + ns * nv;                /* [nv][nv] */
             REAL *Ja = Jc + nv * nv;                  /* [nv][nv] gross scale */
-            REAL *dqdCa = Ja + nv * nv;               /* [ns] |dq_f/dC| + |dq_r/dC| */
+            REAL *dqfdC = Ja + nv * nv;               /* [ns] dq_f/dC_l */
+            REAL *dqrdC = dqfdC + ns;                 /* [ns] dq_r/dC_l */
 #ifdef _OPENMP
 #pragma omp for schedule(static)
 #endif
@@ -285,27 +292,24 @@ int SFX(ora_jacobian_scaled)(const ora_mech *m, int64_t n, const double *T, cons
                     REAL dlnkf = ((REAL)m->beta[j] + E_R / Ti) / Ti;
                     REAL dlnKc = (dH - dn) / Ti;
                     /* explicit temperature dependence at fixed C */
-                    REAL dqdT = qf * dlnkf - (rev ? qr * (dlnkf - dlnKc) : 0);
-                    REAL dqdTa = FABS(qf * dlnkf) + (rev ? FABS(qr * (dlnkf - dlnKc)) : 0);
-                    /* dq/dC_l, product rule on each power */
+                    REAL dqfdT = qf * dlnkf;
+                    REAL dqrdT = rev ? qr * (dlnkf - dlnKc) : 0;
+                    /* dq_f/dC_l and dq_r/dC_l, product rule on each power */
                     for (int l = 0; l < ns; ++l) {
-                        REAL d = 0, da = 0;
+                        dqfdC[l] = dqrdC[l] = 0;
                         if (nf[l]) {
                             REAL p = kf * (REAL)nf[l] * SFX(ipow)(C[l], nf[l] - 1);
                             for (int mm = 0; mm < ns; ++mm)
                                 if (mm != l && nf[mm]) p *= SFX(ipow)(C[mm], nf[mm]);
-                            d += p;
-                            da += FABS(p);
+                            dqfdC[l] = p;
                         }
                         if (nrr[l] && rev) {
                             REAL p = kr * (REAL)nrr[l] * SFX(ipow)(C[l], nrr[l] - 1);
                             for (int mm = 0; mm < ns; ++mm)
                                 if (mm != l && nrr[mm]) p *= SFX(ipow)(C[mm], nrr[mm]);
-                            d -= p;
-                            da += FABS(p);
+                            dqrdC[l] = p;
                         }
-                        dqdC[l] = d;
-                        dqdCa[l] = da;
+                        dqdC[l] = dqfdC[l] - dqrdC[l];
                     }
                     REAL qn = qf - qr;
                     for (int k = 0; k < ns; ++k) {
@@ -313,14 +317,15 @@ int SFX(ora_jacobian_scaled)(const ora_mech *m, int64_t n, const double *T, cons
                         if (!nu) continue;
                         om[k] += nu * qn;
                         for (int c = 0; c < nv; ++c) {
-                            REAL g = (c == ns) ? dqdT : 0;
-                            REAL ga = (c == ns) ? dqdTa : 0;
+                            /* total derivatives of q_f and q_r along x_c */
+                            REAL gf = (c == ns) ? dqfdT : 0;
+                            REAL gr = (c == ns) ? dqrdT : 0;
                             for (int l = 0; l < ns; ++l) {
-                                if (dqdC[l] != 0) g += dqdC[l] * dCdx[l * nv + c];
-                                if (dqdCa[l] != 0) ga += dqdCa[l] * FABS(dCdx[l * nv + c]);
+                                if (dqfdC[l] != 0) gf += dqfdC[l] * dCdx[l * nv + c];
+                                if (dqrdC[l] != 0) gr += dqrdC[l] * dCdx[l * nv + c];
                             }
-                            Jc[k * nv + c] += nu * g;
-                            Ja[k * nv + c] += FABS((REAL)nu) * ga;
+                            Jc[k * nv + c] += nu * (gf - gr);
+                            Ja[k * nv + c] += FABS((REAL)nu) * (FABS(gf) + FABS(gr));
                         }
                     }
                 }

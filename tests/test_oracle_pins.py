@@ -104,6 +104,87 @@ def test_hand_example_2_closed_form():
     assert abs(float((W * om.astype(float)).sum())) <= 1e-14 * float(W @ np.abs(om.astype(float)))
 
 
+def test_hand_example_scales_closed_form():
+    """Gross and net rate scales S = sum_j |nu| (q_f + q_r), N = sum_j |nu|
+    |q_f - q_r| in closed form: examples 1 and 2 (|nu| = 1) and example 3
+    (2 A <=> B, |nu_A| = 2)."""
+    g = _golden()
+    mp.mp.dps = 50
+    # example 1
+    e = g["example1"]
+    m = _Mech(e["W"], [[1, 0]], [[0, 1]], [math.log(e["A_cgs"])], [e["beta"]], [e["Ea_cal"]],
+              _nasa(e["nasa_a1"], e["nasa_a6"]))
+    _, S, N = oracle.source(m, [e["T"]], [e["P"]], np.array(e["Y"])[:, None], precision="ld",
+                            scales=True)
+    C = mp.mpf(e["P"]) / (RU * e["T"]) / 2
+    qf = mp.mpf(e["A_cgs"]) * C
+    qr = qf / mp.e
+    for k in range(2):
+        assert abs(float(S[k, 0]) - float(qf + qr)) <= 1e-15 * float(qf + qr)
+        assert abs(float(N[k, 0]) - float(qf - qr)) <= 1e-15 * float(qf - qr)
+    # example 2
+    e = g["example2"]
+    W = np.array(e["W"])
+    X = np.array(e["X"])
+    Y = X * W / (X * W).sum()
+    m = _Mech(W, [[1, 1, 0]], [[0, 0, 1]], [math.log(e["A_cgs"])], [e["beta"]], [e["Ea_cal"]],
+              _nasa(e["nasa_a1"], e["nasa_a6"]))
+    T_ = mp.mpf(e["T"])
+    kf = mp.mpf(10) ** 10 * T_ ** mp.mpf("0.5") * mp.exp(-mp.mpf(10000) * mp.mpf("4.184") / RU_MOL / T_)
+    lnKc = -mp.log(PREF / (RU * T_)) + 40000 / T_ + mp.mpf("2.5") - mp.mpf("2.5") * mp.log(T_)
+    Ct = mp.mpf(e["P"]) / (RU * T_)
+    qf = kf * (mp.mpf(X[0]) * Ct) * (mp.mpf(X[1]) * Ct)
+    qr = kf / mp.exp(lnKc) * (mp.mpf(X[2]) * Ct)
+    _, S, N = oracle.source(m, [e["T"]], [e["P"]], Y[:, None], precision="ld", scales=True)
+    for k in range(3):
+        assert abs(float(S[k, 0]) - float(qf + qr)) <= 1e-14 * float(qf + qr)
+        assert abs(float(N[k, 0]) - float(qf - qr)) <= 1e-14 * float(qf - qr)
+    # example 3: 2 A <=> B
+    e = g["example3"]
+    W = np.array(e["W"])
+    X = np.array(e["X"])
+    Y = X * W / (X * W).sum()
+    low = np.zeros((2, 7))
+    low[:, 0] = e["nasa_a1"]
+    low[:, 5] = e["nasa_a6"]
+    low[:, 6] = e["nasa_a7"]
+    m = _Mech(W, [[2, 0]], [[0, 1]], [math.log(e["A_cgs"])], [e["beta"]], [e["Ea_cal"]], low)
+    T_ = mp.mpf(e["T"])
+    a1 = mp.mpf(e["nasa_a1"][0])
+    dH = (a1 + mp.mpf(e["nasa_a6"][1]) / T_) - 2 * a1
+    dS = (a1 * mp.log(T_) + mp.mpf(e["nasa_a7"][1])) - 2 * (a1 * mp.log(T_) + mp.mpf(e["nasa_a7"][0]))
+    lnKc = -mp.log(PREF / (RU * T_)) + dS - dH
+    Ct = mp.mpf(e["P"]) / (RU * T_)
+    kf = mp.mpf(e["A_cgs"]) * mp.mpf("1e-3")
+    qf = kf * (mp.mpf(X[0]) * Ct) ** 2
+    qr = kf / mp.exp(lnKc) * (mp.mpf(X[1]) * Ct)
+    om, S, N = oracle.source(m, [e["T"]], [e["P"]], Y[:, None], precision="ld", scales=True)
+    for k, nu in ((0, -2), (1, 1)):
+        assert abs(float(om[k, 0]) - float(nu * (qf - qr))) <= 1e-14 * float(abs(nu) * (qf + qr))
+        assert abs(float(S[k, 0]) - float(abs(nu) * (qf + qr))) <= 1e-14 * float(abs(nu) * (qf + qr))
+        assert abs(float(N[k, 0]) - float(abs(nu) * abs(qf - qr))) <= 1e-14 * float(abs(nu) * (qf + qr))
+    r = oracle.rates(m, e["T"], e["P"], Y, precision="ld")
+    assert abs(float(mp.log(r["Kc"][0])) - float(lnKc)) < 1e-13
+
+
+def test_hand_example_1_temperature_source_closed_form():
+    """omega_T = T omega_B / (3.5 C_tot) for example 1 (see the golden file)."""
+    e = _golden()["example1"]
+    m = _Mech(e["W"], [[1, 0]], [[0, 1]], [math.log(e["A_cgs"])], [e["beta"]], [e["Ea_cal"]],
+              _nasa(e["nasa_a1"], e["nasa_a6"]))
+    mp.mp.dps = 50
+    T, P = e["T"], e["P"]
+    Ct = mp.mpf(P) / (RU * T)
+    qf = mp.mpf(e["A_cgs"]) * Ct / 2
+    omB = qf - qf / mp.e
+    expect = float(mp.mpf(T) * omB / (mp.mpf("3.5") * Ct))
+    got = float(oracle.temp_source(m, [T], [P], np.array(e["Y"])[:, None], precision="ld")[0])
+    assert abs(got - expect) <= 1e-15 * abs(expect)
+    # the double build agrees to rounding
+    got64 = float(oracle.temp_source(m, [T], [P], np.array(e["Y"])[:, None])[0])
+    assert abs(got64 - expect) <= 1e-13 * abs(expect)
+
+
 def test_irreversible_flag_drops_reverse_rate():
     g = _golden()["example2"]
     W = np.array(g["W"])
@@ -284,6 +365,47 @@ def test_ld_and_f64_agree():
 # 50-digit brute force on tiny mechanisms (Eqs. 2, 3, 5, 7, 8 directly)
 
 
+def _brute_force_rates(mech, T, P, Y):
+    """q_f and q_r of every reaction at 50 digits, straight from Eqs. 3, 5, 7, 8
+    with the ideal-gas concentrations and the NASA-7 forms, at the caller's
+    working precision (numerical differentiation raises it)."""
+    T = mp.mpf(T)
+    ns, nr = mech.nu_f.shape[1], mech.nu_f.shape[0]
+    y = [max(mp.mpf(v), 0) / mp.mpf(float(w)) for v, w in zip(Y, mech.W)]
+    C = [mp.mpf(P) / (RU * T) * v / sum(y) for v in y]
+    H, S = [], []
+    for k in range(ns):
+        a = mech.nasa_high[k] if T >= mech.T_mid[k] else mech.nasa_low[k]
+        a = [mp.mpf(float(x)) for x in a]
+        H.append(a[0] + a[1] * T / 2 + a[2] * T ** 2 / 3 + a[3] * T ** 3 / 4 + a[4] * T ** 4 / 5 + a[5] / T)
+        S.append(a[0] * mp.log(T) + a[1] * T + a[2] * T ** 2 / 2 + a[3] * T ** 3 / 3 + a[4] * T ** 4 / 4 + a[6])
+    qf, qr = [], []
+    for j in range(nr):
+        order = int(mech.nu_f[j].sum())
+        A = mp.exp(mp.mpf(float(mech.ln_A[j]))) * mp.mpf("1e-3") ** (order - 1)
+        kf = A * T ** mp.mpf(float(mech.beta[j])) * mp.exp(-mp.mpf(float(mech.Ea[j])) * mp.mpf("4.184") / RU_MOL / T)
+        nu = [int(mech.nu_r[j, k]) - int(mech.nu_f[j, k]) for k in range(ns)]
+        Kc = (PREF / (RU * T)) ** sum(nu) * mp.exp(sum(n * (S[k] - H[k]) for k, n in enumerate(nu)))
+        qf.append(kf * mp.fprod(C[k] ** int(mech.nu_f[j, k]) for k in range(ns)))
+        rev = mech.reversible is None or int(mech.reversible[j])
+        qr.append(kf / Kc * mp.fprod(C[k] ** int(mech.nu_r[j, k]) for k in range(ns)) if rev else mp.mpf(0))
+    return qf, qr
+
+
+def _brute_force_scales(mech, T, P, Y):
+    """(omega, S, N) at 50 digits from _brute_force_rates."""
+    qf, qr = _brute_force_rates(mech, T, P, Y)
+    ns, nr = mech.nu_f.shape[1], mech.nu_f.shape[0]
+    om, S, N = [mp.mpf(0)] * ns, [mp.mpf(0)] * ns, [mp.mpf(0)] * ns
+    for j in range(nr):
+        for k in range(ns):
+            nu = int(mech.nu_r[j, k]) - int(mech.nu_f[j, k])
+            om[k] += nu * (qf[j] - qr[j])
+            S[k] += abs(nu) * (qf[j] + qr[j])
+            N[k] += abs(nu) * abs(qf[j] - qr[j])
+    return om, S, N
+
+
 def _brute_force_omega(mech, T, P, Y):
     mp.mp.dps = 50
     T = mp.mpf(T)
@@ -312,6 +434,25 @@ def _brute_force_omega(mech, T, P, Y):
 
 def _ld_to_mp(x):
     return mp.mpf(np.format_float_scientific(np.longdouble(x), precision=24, unique=False))
+
+
+@pytest.mark.parametrize("seed", [3, 6])
+def test_brute_force_scales_tiny_mechanisms(seed):
+    """The oracle's S and N against 50-digit brute force (with irreversible
+    reactions, whose reverse rate is zero)."""
+    mech = synth.make_mechanism(4, 3, seed=seed)
+    mech.reversible = np.array([1, 0, 1], np.uint8)
+    rng = np.random.default_rng(seed + 100)
+    for _ in range(3):
+        T = float(rng.uniform(600, 2900))
+        P = float(rng.uniform(0.5, 30) * 101325)
+        Y = rng.dirichlet(np.full(4, 0.7))
+        om, S, N = oracle.source(mech, [T], [P], Y[:, None], precision="ld", scales=True)
+        bo, bS, bN = _brute_force_scales(mech, T, P, Y)
+        for k in range(4):
+            assert abs(_ld_to_mp(om[k, 0]) - bo[k]) <= mp.mpf("1e-17") * bS[k] + mp.mpf("1e-300")
+            assert abs(_ld_to_mp(S[k, 0]) - bS[k]) <= mp.mpf("1e-17") * bS[k] + mp.mpf("1e-300")
+            assert abs(_ld_to_mp(N[k, 0]) - bN[k]) <= mp.mpf("1e-17") * bS[k] + mp.mpf("1e-300")
 
 
 @pytest.mark.parametrize("seed", [3, 4, 5])
@@ -416,6 +557,54 @@ def test_jacobian_at_equilibrium(ns, nr):
         got = J[:ns, :ns]
         scale = np.abs(K).max(axis=1, keepdims=True) * np.abs(dlnC).max()
         assert float((np.abs(got - expect) / scale).max()) < 1e-10, T
+
+
+@pytest.mark.parametrize("case", ["example2", "tiny"])
+def test_jacobian_gross_scale_definition(case):
+    """The oracle's Jacobian gross scale S^J_kc = sum_j |nu_kj| (|d q_f/d x_c| +
+    |d q_r/d x_c|) against the same definition evaluated with 50-digit
+    numerical derivatives (mpmath) of the brute-force q_f and q_r of each
+    reaction, x = (Y_1..Y_NS, T) at fixed P; the scale also bounds the
+    entry: |J_kc| <= S^J_kc, and the temperature row's scale bounds its entry."""
+    if case == "example2":
+        g = _golden()["example2"]
+        W = np.array(g["W"])
+        X = np.array(g["X"])
+        Y = X * W / (X * W).sum()
+        mech = _Mech(W, [[1, 1, 0]], [[0, 0, 1]], [math.log(g["A_cgs"])], [g["beta"]],
+                     [g["Ea_cal"]], _nasa(g["nasa_a1"], g["nasa_a6"]))
+        T, P = g["T"], g["P"]
+    else:
+        mech = synth.make_mechanism(4, 3, seed=3)
+        rng = np.random.default_rng(5)
+        T, P, Y = 1700.0, 3.0e5, rng.dirichlet(np.full(4, 0.7))
+    ns, nr = mech.nu_f.shape[1], mech.nu_f.shape[0]
+    J, Ja = oracle.jacobian(mech, [T], [P], Y[:, None], precision="ld", scales=True)
+    J, Ja = J[0], Ja[0]
+    mp.mp.dps = 50
+    x0 = [mp.mpf(float(v)) for v in Y] + [mp.mpf(T)]
+
+    def rates_at(c, xc):
+        x = list(x0)
+        x[c] = xc
+        return _brute_force_rates(mech, x[ns], P, x[:ns])
+
+    dqf = [[None] * (ns + 1) for _ in range(nr)]
+    dqr = [[None] * (ns + 1) for _ in range(nr)]
+    for c in range(ns + 1):
+        for j in range(nr):
+            dqf[j][c] = mp.diff(lambda v: rates_at(c, v)[0][j], x0[c])
+            dqr[j][c] = mp.diff(lambda v: rates_at(c, v)[1][j], x0[c])
+    for k in range(ns):
+        for c in range(ns + 1):
+            sj = mp.mpf(0)
+            for j in range(nr):
+                nu = abs(int(mech.nu_r[j, k]) - int(mech.nu_f[j, k]))
+                sj += nu * (abs(dqf[j][c]) + abs(dqr[j][c]))
+            assert abs(_ld_to_mp(Ja[k, c]) - sj) <= mp.mpf("1e-15") * sj + mp.mpf("1e-300"), (k, c)
+            assert abs(float(J[k, c])) <= float(Ja[k, c]) * (1 + 1e-15)
+    for c in range(ns + 1):
+        assert abs(float(J[ns, c])) <= float(Ja[ns, c]) * (1 + 1e-15)
 
 
 def test_jacobian_ld_matches_f64():
