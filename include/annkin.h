@@ -103,12 +103,41 @@ const char *ak_version(void);
  * Convert and upload a mechanism to `device` (HIP ordinal): rate parameters
  * to SI-kmol units and base-2 logarithms, NASA coefficients to the
  * Gibbs-layer weights of Eq. 11 with the standard concentration folded in,
- * and the stoichiometry to per-reaction factor lists.  The call is
- * synchronous.  On success *out owns device memory until ak_free_mechanism.
- * Errors: AK_EINVAL (null/invalid desc), AK_EUNSUPPORTED, AK_EDEVICE,
- * AK_ENOMEM.
+ * and the stoichiometry to per-reaction factor lists.  Where the mechanism
+ * is small enough for one lane to hold a cell's whole state in registers
+ * (NS <= 64 for AK_FP32, NS <= 53 for AK_FP64), its source-term kernels are
+ * also generated with the stoichiometry written into the code and compiled
+ * for the device (hiprtc; a few seconds per precision, cached by text in
+ * the process and on disk under $AK_JIT_CACHE_DIR or $HOME/.cache/annkin,
+ * "off" disables the disk cache).  Larger mechanisms use the table-driven
+ * kernels.  The call is synchronous.  On success *out owns device memory
+ * until ak_free_mechanism.
+ * Errors: AK_EINVAL (null/invalid desc), AK_EUNSUPPORTED, AK_EDEVICE
+ * (including a failed compilation), AK_ENOMEM.
  */
 int ak_load_mechanism(const ak_mechanism_desc *desc, int device, ak_mechanism **out);
+
+/* Kernel choice of ak_load_mechanism_ex. */
+#define AK_KERNEL_AUTO 0   /* mechanism-compiled kernels where they fit (the default) */
+#define AK_KERNEL_TABLE 1  /* the table-driven kernels only (no compilation) */
+
+/* ak_load_mechanism with an explicit kernel choice (AK_KERNEL_*). */
+int ak_load_mechanism_ex(const ak_mechanism_desc *desc, int device, int kernels,
+                         ak_mechanism **out);
+
+/* 1 if ak_eval_source runs the mechanism-compiled kernel for this
+ * precision, 0 if the table-driven one, negative on bad arguments. */
+int ak_mechanism_compiled(const ak_mechanism *mech, ak_precision prec);
+
+/*
+ * Diagnostic, no device needed: the HIP source text the library generates
+ * for a mechanism and precision (what ak_load_mechanism compiles).  Writes
+ * at most cap bytes including the terminating NUL into buf (buf may be NULL
+ * with cap 0) and the full size including the NUL into *needed.
+ * Errors: as ak_load_mechanism's argument checks.
+ */
+int ak_jit_source(const ak_mechanism_desc *desc, ak_precision prec, char *buf, size_t cap,
+                  size_t *needed);
 
 /* Free a mechanism.  The caller must ensure no enqueued work still uses it
  * (synchronise the streams first).  NULL is a no-op. */

@@ -71,6 +71,11 @@ def lib():
         h.ak_last_error.restype = C.c_char_p
         h.ak_version.restype = C.c_char_p
         h.ak_load_mechanism.argtypes = [C.POINTER(MechanismDesc), C.c_int, C.POINTER(C.c_void_p)]
+        h.ak_load_mechanism_ex.argtypes = [C.POINTER(MechanismDesc), C.c_int, C.c_int,
+                                           C.POINTER(C.c_void_p)]
+        h.ak_mechanism_compiled.argtypes = [C.c_void_p, C.c_int]
+        h.ak_jit_source.argtypes = [C.POINTER(MechanismDesc), C.c_int, C.c_char_p, C.c_size_t,
+                                    C.POINTER(C.c_size_t)]
         h.ak_free_mechanism.argtypes = [C.c_void_p]
         h.ak_mechanism_n_species.argtypes = [C.c_void_p]
         h.ak_mechanism_n_reactions.argtypes = [C.c_void_p]
@@ -106,35 +111,59 @@ def _torch():
     return torch
 
 
+AK_KERNEL_AUTO = 0
+AK_KERNEL_TABLE = 1
+_KERNELS = {"auto": AK_KERNEL_AUTO, "table": AK_KERNEL_TABLE}
+
+
+def _desc(src):
+    """(MechanismDesc, arrays it points into) for a mechanism-like object."""
+    keep = {
+        "W": np.ascontiguousarray(src.W, np.float64),
+        "nu_f": np.ascontiguousarray(src.nu_f, np.int8),
+        "nu_r": np.ascontiguousarray(src.nu_r, np.int8),
+        "ln_A": np.ascontiguousarray(src.ln_A, np.float64),
+        "beta": np.ascontiguousarray(src.beta, np.float64),
+        "Ea": np.ascontiguousarray(src.Ea, np.float64),
+        "nasa_low": np.ascontiguousarray(src.nasa_low, np.float64),
+        "nasa_high": np.ascontiguousarray(src.nasa_high, np.float64),
+        "T_mid": np.ascontiguousarray(src.T_mid, np.float64),
+        "reversible": np.ascontiguousarray(src.reversible, np.uint8),
+    }
+    d = MechanismDesc(int(src.W.shape[0]), int(src.nu_f.shape[0]), *(keep[k].ctypes.data for k in (
+        "W", "nu_f", "nu_r", "ln_A", "beta", "Ea", "nasa_low", "nasa_high", "T_mid",
+        "reversible")))
+    return d, keep
+
+
+def jit_source(src, precision: str = "fp32") -> str:
+    """HIP source text the library generates for a mechanism (no GPU needed)."""
+    d, keep = _desc(src)
+    prec = {"fp32": AK_FP32, "fp64": AK_FP64}[precision]
+    need = C.c_size_t()
+    _check(lib().ak_jit_source(C.byref(d), prec, None, 0, C.byref(need)))
+    buf = C.create_string_buffer(need.value)
+    _check(lib().ak_jit_source(C.byref(d), prec, buf, need.value, C.byref(need)))
+    return buf.value.decode()
+
+
 class Mechanism:
     """A mechanism uploaded to one GPU.  ``src`` is any object with the
     attributes of ``synth.Mechanism`` (W, nu_f, nu_r, ln_A, beta, Ea,
-    nasa_low, nasa_high, T_mid, reversible)."""
+    nasa_low, nasa_high, T_mid, reversible).  ``kernels="auto"`` compiles
+    the mechanism into its own source-term kernels where it fits them;
+    ``"table"`` uses the table-driven kernels only."""
 
-    def __init__(self, src, device: int | None = None):
+    def __init__(self, src, device: int | None = None, kernels: str = "auto"):
         torch = _torch()
         if device is None:
             device = torch.cuda.current_device()
         self.device = int(device)
         self.n_species = int(src.W.shape[0])
         self.n_reactions = int(src.nu_f.shape[0])
-        keep = {
-            "W": np.ascontiguousarray(src.W, np.float64),
-            "nu_f": np.ascontiguousarray(src.nu_f, np.int8),
-            "nu_r": np.ascontiguousarray(src.nu_r, np.int8),
-            "ln_A": np.ascontiguousarray(src.ln_A, np.float64),
-            "beta": np.ascontiguousarray(src.beta, np.float64),
-            "Ea": np.ascontiguousarray(src.Ea, np.float64),
-            "nasa_low": np.ascontiguousarray(src.nasa_low, np.float64),
-            "nasa_high": np.ascontiguousarray(src.nasa_high, np.float64),
-            "T_mid": np.ascontiguousarray(src.T_mid, np.float64),
-            "reversible": np.ascontiguousarray(src.reversible, np.uint8),
-        }
-        d = MechanismDesc(self.n_species, self.n_reactions, *(keep[k].ctypes.data for k in (
-            "W", "nu_f", "nu_r", "ln_A", "beta", "Ea", "nasa_low", "nasa_high", "T_mid",
-            "reversible")))
+        d, self._keep = _desc(src)
         h = C.c_void_p()
-        _check(lib().ak_load_mechanism(C.byref(d), self.device, C.byref(h)))
+        _check(lib().ak_load_mechanism_ex(C.byref(d), self.device, _KERNELS[kernels], C.byref(h)))
         self._h = h
         self.name = getattr(src, "name", "mechanism")
 
@@ -152,6 +181,14 @@ class Mechanism:
             self.close()
         except Exception:
             pass
+
+    def compiled(self, dtype) -> bool:
+        """Whether eval_source runs the mechanism-compiled kernel for the
+        precision of ``dtype`` (torch.float32 or torch.float64)."""
+        rc = lib().ak_mechanism_compiled(self._h, _prec(dtype))
+        if rc < 0:
+            _check(rc)
+        return rc == 1
 
     def error_count(self, stream=None) -> int:
         """Read and reset the device-side bad-cell counter (synchronises)."""
@@ -297,13 +334,22 @@ def _host_ptr(a):
 
 
 def _host_info(a):
+    """(element type "float32" / "float64" / other, shape, strides in elements)
+    of a CPU torch tensor or a numpy array."""
     if hasattr(a, "data_ptr"):
-        return a.dtype, tuple(a.shape), a.stride()
-    return a.dtype, a.shape, tuple(s // a.itemsize for s in a.strides)
+        name, shape, strides = str(a.dtype), tuple(a.shape), tuple(a.stride())
+    else:
+        name, shape, strides = str(a.dtype), tuple(a.shape), tuple(
+            s // a.itemsize for s in a.strides)
+    kind = "float32" if "float32" in name else "float64" if "float64" in name else name
+    return kind, shape, strides
 
 
 class Request:
-    """One submitted request.  Keeps its host buffers alive until freed."""
+    """One submitted request.  Keeps its host buffers alive until it has
+    completed (or been cancelled) and been freed; dropping a pending request
+    cancels it if it is still queued and otherwise waits for it, so that no
+    copy into its buffers outlives them."""
 
     def __init__(self, handle, keep):
         self._h = handle
@@ -321,6 +367,17 @@ class Request:
             _check(lib().ak_request_free(self._h))
             self._h = None
             self._keep = None
+
+    def __del__(self):
+        try:
+            if self._h is not None and self._h.value:
+                if lib().ak_request_cancel(self._h) != 0:
+                    lib().ak_request_wait(self._h, -1.0)   # admitted: let its copies finish
+                lib().ak_request_free(self._h)
+                self._h = None
+                self._keep = None
+        except Exception:
+            pass
 
 
 class Server:
@@ -341,19 +398,29 @@ class Server:
 
     def submit(self, mech: Mechanism, T, P, Y, out) -> Request:
         """Queue one request: host T [n], P [n], Y [NS, ldY-strided], results
-        into host out [NS, ldO-strided]; float32 or float64 buffers."""
+        into host out [NS, ldO-strided]; all float32 or all float64.  T and P
+        must be contiguous; Y and out need unit cell stride."""
         dt, shp, st = _host_info(Y)
+        if len(shp) != 2:
+            raise ValueError("Y must be [NS, n]")
         n = shp[1]
         ns = mech.n_species
         if shp[0] != ns or st[1] != 1:
             raise ValueError("Y must be [NS, n] with unit cell stride")
-        odt, oshp, ost = _host_info(out)
-        if oshp != (ns, n) or ost[1] != 1:
-            raise ValueError("out must be [NS, n] with unit cell stride")
-        name = str(dt)
-        prec = AK_FP32 if "float32" in name else AK_FP64 if "float64" in name else None
+        prec = {"float32": AK_FP32, "float64": AK_FP64}.get(dt)
         if prec is None:
             raise TypeError("float32 or float64 buffers")
+        for what, a in (("T", T), ("P", P)):
+            adt, ashp, ast = _host_info(a)
+            if adt != dt:
+                raise TypeError(f"{what} must have Y's dtype {dt}, not {adt}")
+            if tuple(ashp) != (n,) or (n > 1 and ast[0] != 1):
+                raise ValueError(f"{what} must be a contiguous [n={n}] buffer")
+        odt, oshp, ost = _host_info(out)
+        if odt != dt:
+            raise TypeError(f"out must have Y's dtype {dt}, not {odt}")
+        if tuple(oshp) != (ns, n) or ost[1] != 1:
+            raise ValueError("out must be [NS, n] with unit cell stride")
         ldY = st[0] if ns > 1 else n
         ldO = ost[0] if ns > 1 else n
         h = C.c_void_p()

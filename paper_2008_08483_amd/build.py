@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libannkin.so")
 
-SOURCES = ["api.cpp", "server.cpp", "source_kernels.hip", "deriv_kernels.hip"]
+SOURCES = ["api.cpp", "jit.cpp", "server.cpp", "source_kernels.hip", "deriv_kernels.hip"]
 
 # Packed FP32 instructions stay disabled: every float op is a plain VALU op.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",
@@ -28,7 +28,7 @@ def build(out: str = LIB, defines: dict | None = None, verbose: bool = False) ->
     cmd = [hipcc, *HIPFLAGS, "-shared", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     for k, v in (defines or {}).items():
         cmd.append(f"-D{k}={v}")
-    cmd += ["-o", tmp, *sources()]
+    cmd += ["-o", tmp, *sources(), "-lhiprtc"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "ak_device.h"
+#include "ak_jit.h"
 
 struct ak_mechanism {
     int device = 0;
@@ -16,6 +17,7 @@ struct ak_mechanism {
     std::vector<ak::SpeciesRec> host_species;
     std::vector<ak::RxnRec> host_rxn;   // shape-sorted order
     std::vector<int> rxn_order;         // file index of each sorted reaction
+    ak::JitKernels jit[2];              // mechanism-compiled kernels per precision (FP64, FP32)
 };
 
 namespace ak {

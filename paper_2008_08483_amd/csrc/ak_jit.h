@@ -1,0 +1,78 @@
+// Mechanism-compiled source-term kernels: generation, compilation (hiprtc)
+// and launch.  Host-side only.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ak_device.h"
+
+namespace ak {
+
+// What the generator needs of a prepared mechanism (host copies, sorted
+// reaction order).
+struct JitMech {
+    int ns = 0, nr = 0;
+    const SpeciesRec *sp = nullptr;   // [ns]
+    const RxnRec *rx = nullptr;       // [nr]
+    const RxnAux *aux = nullptr;      // [nr]
+};
+
+// Generated kernels of one mechanism for one precision.
+//   ak_src(T, P, Y, ldY, n, om, ldO, SP, RX, err): one lane per cell.
+//   ak_src_batch(desc, nreq): the same for several requests of this
+//     mechanism in one launch (workgroup -> request by binary search).
+struct JitKernels {
+    const double *sp = nullptr;   // device copies of JitProgram::sp and ::rx
+    const double *rx = nullptr;
+    double T_lo = 0.0, T_hi = 0.0;
+    hipModule_t mod = nullptr;
+    hipFunction_t src = nullptr;
+    hipFunction_t batch = nullptr;
+    int block = 64;          // threads per workgroup of both kernels
+};
+
+// One request of a fused launch of generated kernels (device table).
+struct JitBatchDesc {
+    const void *T, *P, *Y;
+    void *om;
+    int64_t ldY, ldO, n;
+    int64_t block_begin;     // first workgroup of this request
+};
+
+// Whether the register-resident form suits a mechanism of this size: the
+// whole per-cell state (a, v and the omega accumulators) must fit the
+// register file of one lane.
+bool jit_suitable(int ns, bool f64);
+
+// Generated kernels of one mechanism and precision: the HIP source text of
+// both kernels and the constant tables they read (per species the Gibbs
+// layer, per reaction 3 doubles in the order of the mechanism's sorted
+// reactions).  In the FP32
+// path the kernels evaluate cells with T_lo <= T <= T_hi and report others
+// as bad (T_lo = T_hi = 0: no restriction).
+struct JitProgram {
+    std::string src;
+    std::vector<double> sp;   // 16 doubles per species (SpeciesRec layout)
+    std::vector<double> rx;
+    double T_lo = 0.0, T_hi = 0.0;
+};
+JitProgram jit_program(const JitMech &m, bool f64);
+
+// Compile the text for gfx950 with hiprtc; returns 0 or an AK_E* code (the
+// compiler log goes to `log`).  Results are cached in the process by text.
+int jit_compile(const std::string &src, std::vector<char> &code, std::string &log);
+
+// Load a code object on the current device.
+int jit_load(const std::vector<char> &code, JitKernels &out);
+void jit_unload(JitKernels &k);
+
+hipError_t jit_launch(const JitKernels &k, const void *T, const void *P, const void *Y,
+                      int64_t ldY, int64_t n, void *om, int64_t ldO, unsigned long long *err,
+                      hipStream_t st);
+hipError_t jit_batch_launch(const JitKernels &k, const JitBatchDesc *d_desc, int nreq,
+                            int64_t blocks, unsigned long long *err, hipStream_t st);
+
+}  // namespace ak

@@ -28,6 +28,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -102,6 +103,7 @@ struct Request {
     // state
     int state = kQueued;
     int rc = 0;
+    std::string error;         // why the request failed (set with state, under mu)
     double t_submit = 0, t_done = 0;
     std::mutex mu;
     std::condition_variable cv;
@@ -239,11 +241,12 @@ class Scheduler {
         void *token = nullptr;
     };
 
-    static void finish(Request *r, int state, int rc)
+    static void finish(Request *r, int state, int rc, std::string err = std::string())
     {
         std::lock_guard<std::mutex> l(r->mu);
         r->state = state;
         r->rc = rc;
+        r->error = std::move(err);
         r->t_done = now_s();
         r->cv.notify_all();
     }
@@ -300,7 +303,8 @@ class Scheduler {
             Batch b = inflight_.front();
             for (size_t i = 0; i < b.reqs.size(); ++i) {
                 l.unlock();
-                const int rc = exec_->wait(b.token, i);
+                std::string err;
+                const int rc = exec_->wait(b.token, i, &err);
                 l.lock();
                 Request *r = b.reqs[i];
                 arena_.release(r->arena_off, r->bytes);
@@ -315,7 +319,7 @@ class Scheduler {
                 } else {
                     stats_.failed++;
                 }
-                finish(r, rc == 0 ? kDone : kFailed, rc);
+                finish(r, rc == 0 ? kDone : kFailed, rc, std::move(err));
                 cv_.notify_all();
             }
             // the executor's slot is free before the batch leaves inflight_, so

@@ -14,6 +14,7 @@
 #include "annkin.h"
 #include "ak_device.h"
 #include "ak_internal.h"
+#include "ak_jit.h"
 
 namespace ak {
 
@@ -84,10 +85,24 @@ const char *ak_last_error(void) { return g_last_error.c_str(); }
 
 const char *ak_version(void) { return "annkin 0.1 (gfx950)"; }
 
-int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out)
+}  // extern "C"
+
+namespace ak {
+
+// Host-side preparation of a mechanism (no device needed): unit conversion,
+// Gibbs-layer weights, reaction records sorted by shape, per-wave sweep
+// ranges.  The device-dependent tile size is set by the caller.
+struct Prepared {
+    std::vector<SpeciesRec> sp;
+    std::vector<RxnRec> rx;         // shape-sorted order
+    std::vector<RxnAux> aux;        // same order
+    std::vector<ThermoRec> th;
+    std::vector<int> order;         // file index of each sorted reaction
+    MechView view;                  // runs and sweep ranges filled in
+};
+
+static int prepare(const ak_mechanism_desc *d, Prepared &p)
 {
-    if (!d || !out) return set_error(AK_EINVAL, "ak_load_mechanism: null argument");
-    *out = nullptr;
     const int ns = d->n_species, nr = d->n_reactions;
     if (ns < 1 || nr < 1)
         return set_error(AK_EINVAL, "ak_load_mechanism: bad sizes ns=%d nr=%d", ns, nr);
@@ -104,28 +119,13 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
         !finite_all(d->nasa_low, 7 * (size_t)ns) || !finite_all(d->nasa_high, 7 * (size_t)ns))
         return set_error(AK_EINVAL, "ak_load_mechanism: non-finite parameter");
 
-    std::vector<SpeciesRec> sp(ns);
+    p.sp.assign(ns, SpeciesRec{});
     for (int k = 0; k < ns; ++k) {
-        sp[k].inv_W = 1.0 / d->W[k];
-        sp[k].T_mid = d->T_mid[k];
-        gibbs_weights(&d->nasa_low[7 * k], sp[k].lo);
-        gibbs_weights(&d->nasa_high[7 * k], sp[k].hi);
+        p.sp[k].inv_W = 1.0 / d->W[k];
+        p.sp[k].T_mid = d->T_mid[k];
+        gibbs_weights(&d->nasa_low[7 * k], p.sp[k].lo);
+        gibbs_weights(&d->nasa_high[7 * k], p.sp[k].hi);
     }
-
-    DeviceGuard g(device);
-    if (!g.ok) return set_error(AK_EDEVICE, "ak_load_mechanism: cannot select device %d", device);
-    // tile: cells per workgroup, as many as the LDS holds (at most 64)
-    int lds_max = 0;
-    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
-                              device) != hipSuccess || lds_max <= 0)
-        return set_error(AK_EDEVICE, "ak_load_mechanism: cannot query LDS size of device %d",
-                         device);
-    lds_max = std::min(lds_max, 160 * 1024);
-    const int tile = std::min<int>(kMaxTile, lds_max / (ns * kEntry));
-    if (tile < 16)
-        return set_error(AK_EUNSUPPORTED, "ak_load_mechanism: %d species do not fit the LDS tile",
-                         ns);
-
     std::vector<RxnRec> rx(nr);
     std::vector<RxnAux> aux(nr);
     std::vector<int> shape(nr);
@@ -165,32 +165,29 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
         x.rev = rev ? 1 : 0;
         x.EoR = d->Ea[j] * kCal / kRuMol;
     }
-    // sort reactions by shape so that each wave runs one code path per run
-    std::vector<int> order(nr);
-    for (int j = 0; j < nr; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return shape[a] < shape[b]; });
-    std::vector<RxnRec> rxs(nr);
-    std::vector<RxnAux> auxs(nr);
-    std::vector<ThermoRec> th(ns);
+    // sort reactions by shape so that each wave of the table-driven kernels
+    // runs one code path per run
+    p.order.resize(nr);
+    for (int j = 0; j < nr; ++j) p.order[j] = j;
+    std::stable_sort(p.order.begin(), p.order.end(),
+                     [&](int a, int b) { return shape[a] < shape[b]; });
+    p.rx.resize(nr);
+    p.aux.resize(nr);
+    p.th.resize(ns);
     for (int k = 0; k < ns; ++k)
         for (int c = 0; c < 7; ++c) {
-            th[k].lo[c] = d->nasa_low[7 * k + c];
-            th[k].hi[c] = d->nasa_high[7 * k + c];
+            p.th[k].lo[c] = d->nasa_low[7 * k + c];
+            p.th[k].hi[c] = d->nasa_high[7 * k + c];
         }
-    MechView view;
+    MechView &view = p.view;
     std::memset(&view, 0, sizeof view);
     view.ns = ns;
     view.nr = nr;
-    view.tile = tile;
-    // 8-wave workgroups when two tiles share a CU's LDS, else one tile of 16
-    // waves, so that a CU runs 16 waves either way
-    view.waves = 2 * (size_t)ns * tile * kEntry <= (size_t)lds_max ? 8 : 16;
-    std::vector<int> rxn_order(order);
     for (int i = 0; i < nr; ++i) {
-        rxs[i] = rx[order[i]];
-        auxs[i] = aux[order[i]];
-        const int s = shape[order[i]];
-        if (i == 0 || shape[order[i - 1]] != s) {
+        p.rx[i] = rx[p.order[i]];
+        p.aux[i] = aux[p.order[i]];
+        const int s = shape[p.order[i]];
+        if (i == 0 || shape[p.order[i - 1]] != s) {
             ShapeRun &run = view.runs[view.nruns++];
             run.nf = s / 2 / kMaxSide + 1;
             run.nr = s / 2 % kMaxSide + 1;
@@ -204,22 +201,106 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     // estimate of each reaction's sweep time: 16 + s^2 with s molecules (a
     // fit of measured per-wave sweep times; per-molecule costs grow with s
     // as the reaction's LDS reads and atomics contend)
-    {
-        std::vector<double> cum(nr + 1, 0.0);
-        for (int i = 0; i < nr; ++i) {
-            const double s = auxs[i].nf + auxs[i].nr;
-            cum[i + 1] = cum[i] + 16.0 + s * s;
+    std::vector<double> cum(nr + 1, 0.0);
+    for (int i = 0; i < nr; ++i) {
+        const double s = p.aux[i].nf + p.aux[i].nr;
+        cum[i + 1] = cum[i] + 16.0 + s * s;
+    }
+    auto split = [&](int32_t *seg, int w) {
+        int i = 0;
+        for (int k = 0; k <= w; ++k) {
+            const double target = cum[nr] * k / w;
+            while (i < nr && cum[i] < target) ++i;
+            seg[k] = k == w ? nr : i;
         }
-        auto split = [&](int32_t *seg, int w) {
-            int i = 0;
-            for (int k = 0; k <= w; ++k) {
-                const double target = cum[nr] * k / w;
-                while (i < nr && cum[i] < target) ++i;
-                seg[k] = k == w ? nr : i;
-            }
-        };
-        split(view.seg8, 8);
-        split(view.seg16, 16);
+    };
+    split(view.seg8, 8);
+    split(view.seg16, 16);
+    return AK_OK;
+}
+
+static JitMech jit_view(const Prepared &p)
+{
+    JitMech j;
+    j.ns = (int)p.sp.size();
+    j.nr = (int)p.rx.size();
+    j.sp = p.sp.data();
+    j.rx = p.rx.data();
+    j.aux = p.aux.data();
+    return j;
+}
+
+}  // namespace ak
+
+extern "C" {
+
+int ak_jit_source(const ak_mechanism_desc *d, ak_precision prec, char *buf, size_t cap,
+                  size_t *needed)
+{
+    if (!d || !needed) return set_error(AK_EINVAL, "ak_jit_source: null argument");
+    if (prec != AK_FP32 && prec != AK_FP64)
+        return set_error(AK_EINVAL, "ak_jit_source: bad precision %d", (int)prec);
+    Prepared p;
+    int rc = prepare(d, p);
+    if (rc) return rc;
+    const std::string src = jit_program(jit_view(p), prec == AK_FP64).src;
+    *needed = src.size() + 1;
+    if (buf && cap > 0) {
+        const size_t n = std::min(cap - 1, src.size());
+        std::memcpy(buf, src.data(), n);
+        buf[n] = 0;
+    }
+    return AK_OK;
+}
+
+int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out)
+{
+    return ak_load_mechanism_ex(d, device, AK_KERNEL_AUTO, out);
+}
+
+int ak_load_mechanism_ex(const ak_mechanism_desc *d, int device, int kernels, ak_mechanism **out)
+{
+    if (!d || !out) return set_error(AK_EINVAL, "ak_load_mechanism: null argument");
+    *out = nullptr;
+    if (kernels != AK_KERNEL_AUTO && kernels != AK_KERNEL_TABLE)
+        return set_error(AK_EINVAL, "ak_load_mechanism: bad kernel choice %d", kernels);
+    Prepared p;
+    int rc = prepare(d, p);
+    if (rc) return rc;
+    const int ns = p.view.ns, nr = p.view.nr;
+
+    DeviceGuard g(device);
+    if (!g.ok) return set_error(AK_EDEVICE, "ak_load_mechanism: cannot select device %d", device);
+    // tile: cells per workgroup, as many as the LDS holds (at most 64)
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              device) != hipSuccess || lds_max <= 0)
+        return set_error(AK_EDEVICE, "ak_load_mechanism: cannot query LDS size of device %d",
+                         device);
+    lds_max = std::min(lds_max, 160 * 1024);
+    const int tile = std::min<int>(kMaxTile, lds_max / (ns * kEntry));
+    if (tile < 16)
+        return set_error(AK_EUNSUPPORTED, "ak_load_mechanism: %d species do not fit the LDS tile",
+                         ns);
+    MechView view = p.view;
+    view.tile = tile;
+    // 8-wave workgroups when two tiles share a CU's LDS, else one tile of 16
+    // waves, so that a CU runs 16 waves either way
+    view.waves = 2 * (size_t)ns * tile * kEntry <= (size_t)lds_max ? 8 : 16;
+
+    // the mechanism-compiled kernels (both precisions) where they fit
+    std::vector<char> code[2];
+    JitProgram prog[2];
+    bool use_jit[2] = {false, false};
+    for (int f = 0; f < 2; ++f) {
+        const bool f64 = f == AK_FP64;   // index = ak_precision
+        if (kernels != AK_KERNEL_AUTO || !jit_suitable(ns, f64)) continue;
+        prog[f] = jit_program(jit_view(p), f64);
+        std::string log;
+        rc = jit_compile(prog[f].src, code[f], log);
+        if (rc) return set_error(rc, "ak_load_mechanism: compiling the mechanism's kernels "
+                                     "failed: %s", log.c_str());
+        use_jit[f] = true;
     }
 
     ak_mechanism *m = new (std::nothrow) ak_mechanism();
@@ -236,12 +317,25 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     const size_t o_th = o_rx + ((sizeof(RxnRec) * (nr + kRecordPad) + 255) & ~(size_t)255);
     const size_t o_aux = o_th + ((sizeof(ThermoRec) * ns + 255) & ~(size_t)255);
     const size_t o_err = o_aux + ((sizeof(RxnAux) * nr + 255) & ~(size_t)255);
-    const size_t bytes = o_err + 256;
+    // tables of the compiled kernels, per precision: species, reactions
+    const size_t jsp_bytes = (sizeof(double) * 16 * ns + 255) & ~(size_t)255;
+    const size_t jrx_bytes = (sizeof(double) * 3 * nr + 255) & ~(size_t)255;
+    size_t o_jsp[2], o_jrx[2];
+    o_jsp[0] = o_err + 256;
+    o_jrx[0] = o_jsp[0] + jsp_bytes;
+    o_jsp[1] = o_jrx[0] + jrx_bytes;
+    o_jrx[1] = o_jsp[1] + jsp_bytes;
+    const size_t bytes = o_jrx[1] + jrx_bytes;
     std::vector<unsigned char> host(bytes, 0);
-    std::memcpy(&host[o_sp], sp.data(), sizeof(SpeciesRec) * ns);
-    std::memcpy(&host[o_rx], rxs.data(), sizeof(RxnRec) * nr);
-    std::memcpy(&host[o_th], th.data(), sizeof(ThermoRec) * ns);
-    std::memcpy(&host[o_aux], auxs.data(), sizeof(RxnAux) * nr);
+    for (int f = 0; f < 2; ++f)
+        if (use_jit[f]) {
+            std::memcpy(&host[o_jsp[f]], prog[f].sp.data(), sizeof(double) * 16 * ns);
+            std::memcpy(&host[o_jrx[f]], prog[f].rx.data(), sizeof(double) * 3 * nr);
+        }
+    std::memcpy(&host[o_sp], p.sp.data(), sizeof(SpeciesRec) * ns);
+    std::memcpy(&host[o_rx], p.rx.data(), sizeof(RxnRec) * nr);
+    std::memcpy(&host[o_th], p.th.data(), sizeof(ThermoRec) * ns);
+    std::memcpy(&host[o_aux], p.aux.data(), sizeof(RxnAux) * nr);
     unsigned char *dev = nullptr;
     if ((e = hipMalloc((void **)&dev, bytes)) != hipSuccess) {
         delete m;
@@ -260,9 +354,23 @@ int ak_load_mechanism(const ak_mechanism_desc *d, int device, ak_mechanism **out
     view.aux = (const RxnAux *)(dev + o_aux);
     view.err = (unsigned long long *)(dev + o_err);
     m->view = view;
-    m->host_species = std::move(sp);
-    m->host_rxn = std::move(rxs);
-    m->rxn_order = std::move(rxn_order);
+    for (int f = 0; f < 2; ++f) {
+        if (!use_jit[f]) continue;
+        rc = jit_load(code[f], m->jit[f]);
+        m->jit[f].sp = (const double *)(dev + o_jsp[f]);
+        m->jit[f].rx = (const double *)(dev + o_jrx[f]);
+        m->jit[f].T_lo = prog[f].T_lo;
+        m->jit[f].T_hi = prog[f].T_hi;
+        if (rc) {
+            for (int q = 0; q < 2; ++q) jit_unload(m->jit[q]);
+            (void)hipFree(dev);
+            delete m;
+            return rc;
+        }
+    }
+    m->host_species = std::move(p.sp);
+    m->host_rxn = std::move(p.rx);
+    m->rxn_order = std::move(p.order);
     *out = m;
     return AK_OK;
 }
@@ -271,12 +379,20 @@ int ak_free_mechanism(ak_mechanism *m)
 {
     if (!m) return AK_OK;
     DeviceGuard g(m->device);
+    for (int f = 0; f < 2; ++f) jit_unload(m->jit[f]);
     (void)hipFree(m->dev);
     delete m;
     return AK_OK;
 }
 
 int ak_mechanism_n_species(const ak_mechanism *m) { return m ? m->ns : -1; }
+
+int ak_mechanism_compiled(const ak_mechanism *m, ak_precision prec)
+{
+    if (!m || (prec != AK_FP32 && prec != AK_FP64))
+        return set_error(AK_EINVAL, "ak_mechanism_compiled: bad argument");
+    return m->jit[prec].src ? 1 : 0;
+}
 int ak_mechanism_n_reactions(const ak_mechanism *m) { return m ? m->nr : -1; }
 
 int ak_eval_source(const ak_mechanism *m, ak_precision prec, const void *T, const void *P,
@@ -294,8 +410,11 @@ int ak_eval_source(const ak_mechanism *m, ak_precision prec, const void *T, cons
     if (n > (int64_t)1 << 40) return set_error(AK_E2BIG, "ak_eval_source: n_cells too large");
     DeviceGuard g(m->device);
     if (!g.ok) return set_error(AK_EDEVICE, "ak_eval_source: cannot select device %d", m->device);
-    hipError_t e = source_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, omega, ldO,
-                                 (hipStream_t)stream);
+    const JitKernels &jk = m->jit[prec];   // indexed by ak_precision
+    hipError_t e = jk.src ? jit_launch(jk, T, P, Y, ldY, n, omega, ldO, m->view.err,
+                                       (hipStream_t)stream)
+                          : source_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, omega, ldO,
+                                          (hipStream_t)stream);
     if (e != hipSuccess) return hip_error(e, "ak_eval_source: launch");
     return AK_OK;
 }

@@ -1,0 +1,636 @@
+// Mechanism-compiled source-term kernels.
+//
+// The exact form of the paper (Eqs. 2, 4, 6, 7, 9-11) is evaluated with one
+// lane per cell and the cell's whole state in registers: per species
+//     a_k = C_k exp(Gt_k),  v_k = exp(-Gt_k)      (Gt: Gibbs-layer output)
+// and an omega accumulator.  The stoichiometry of the mechanism is written
+// into the kernel text, so every gather of a_k / v_k and every scatter into
+// omega_k names a register: there is no index arithmetic, no LDS and no
+// atomic, and the accumulation order of every omega_k is fixed by the text
+// (results are bitwise reproducible and independent of the batch).  The
+// numeric parameters (Gibbs-layer weights, Arrhenius layer) stay in the
+// mechanism's device tables and are read with scalar loads at constant
+// offsets.
+//
+// Per reaction (reactant molecules r, product molecules p, k_f from the
+// Arrhenius layer in base 2, t = log2 k_f):
+//     q_f - q_r = 2^t * prod_r v * (prod_r a - rev * prod_p a)
+// which is Eq. 4 re-associated with ln K_c = -sum_k nu_kj Gt_k (Eq. 11).
+// The FP32 path evaluates 2^t as 2^n * 2^f with the split in double and
+// 2^f (|f| <= 1/2) on the transcendental unit, and accumulates omega in
+// float; the FP64 path uses a degree-12 Taylor polynomial for 2^f and
+// accumulates in double.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include "annkin.h"
+#include "ak_internal.h"
+#include "ak_jit.h"
+
+namespace ak {
+
+namespace {
+
+struct Text {
+    std::string s;
+    void operator()(const char *fmt, ...) __attribute__((format(printf, 2, 3)))
+    {
+        char buf[1024];
+        va_list ap;
+        va_start(ap, fmt);
+        const int n = vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        if (n >= (int)sizeof buf) {
+            std::vector<char> big(n + 1);
+            va_start(ap, fmt);
+            vsnprintf(big.data(), big.size(), fmt, ap);
+            va_end(ap);
+            s.append(big.data(), n);
+        } else {
+            s.append(buf, n);
+        }
+    }
+};
+
+// exact decimal-free spelling of a double for the generated text
+std::string lit(double x)
+{
+    char b[64];
+    snprintf(b, sizeof b, "%a", x);
+    return b;
+}
+
+// ln(2)^k / k!, the Taylor coefficients of 2^f, rounded to double
+std::vector<double> exp2_taylor(int deg)
+{
+    std::vector<double> c(deg + 1);
+    long double t = 1.0L;
+    const long double ln2 = 0.693147180559945309417232121458176568L;
+    for (int k = 0; k <= deg; ++k) {
+        c[k] = (double)t;
+        t = t * ln2 / (long double)(k + 1);
+    }
+    return c;
+}
+
+}  // namespace
+
+bool jit_suitable(int ns, bool f64)
+{
+    // registers per species: a (double), v (float in the FP32 path, double
+    // in the FP64 path) and the accumulator (float / double); a lane has 512
+    // (256 of them usable directly by the vector ALU), some of which the
+    // rest of the kernel needs
+    const int per = f64 ? 6 : 4;
+    return ns * per <= 320;
+}
+
+namespace {
+
+// Gibbs-layer output in base 2 (the device weights of one species) at T
+double g2_host(const SpeciesRec &s, double T)
+{
+    const double *c = T >= s.T_mid ? s.hi : s.lo;
+    return c[0] * std::log(T) + c[1] * T + c[2] * T * T + c[3] * T * T * T +
+           c[4] * T * T * T * T + c[5] / T + c[6];
+}
+
+// Species of each reaction, each once.
+std::vector<std::vector<int>> reaction_species(const JitMech &m)
+{
+    std::vector<std::vector<int>> rs(m.nr);
+    for (int j = 0; j < m.nr; ++j)
+        for (int i = 0; i < m.aux[j].nf + m.aux[j].nr; ++i) {
+            const int k = m.aux[j].sp[i];
+            if (std::find(rs[j].begin(), rs[j].end(), k) == rs[j].end()) rs[j].push_back(k);
+        }
+    return rs;
+}
+
+// Order of the reactions in the generated code.  A species' registers are
+// live from its first reaction to its last, so the order is chosen greedily
+// to open few new species and close many at each step (ties: lowest index).
+std::vector<int> live_order(const JitMech &m, const std::vector<std::vector<int>> &rs)
+{
+    std::vector<int> left(m.ns, 0), order;
+    std::vector<char> open(m.ns, 0), done(m.nr, 0);
+    for (int j = 0; j < m.nr; ++j)
+        for (int k : rs[j]) left[k]++;
+    order.reserve(m.nr);
+    for (int step = 0; step < m.nr; ++step) {
+        int best = -1, bkey = 0, bclose = 0;
+        for (int j = 0; j < m.nr; ++j) {
+            if (done[j]) continue;
+            int opens = 0, closes = 0;
+            for (int k : rs[j]) {
+                opens += !open[k];
+                closes += left[k] == 1;
+            }
+            const int key = opens - closes;
+            if (best < 0 || key < bkey || (key == bkey && closes > bclose)) {
+                best = j;
+                bkey = key;
+                bclose = closes;
+            }
+        }
+        done[best] = 1;
+        order.push_back(best);
+        for (int k : rs[best]) {
+            open[k] = 1;
+            left[k]--;
+        }
+    }
+    return order;
+}
+
+}  // namespace
+
+// reactions per group of table reads (see below)
+static int kGroup = 2;
+
+JitProgram jit_program(const JitMech &m, bool f64)
+{
+    if (const char *g = std::getenv("AK_JIT_GROUP")) kGroup = std::max(1, std::atoi(g));
+    const int ns = m.ns, nr = m.nr;
+    const char *IO = f64 ? "double" : "float";
+    const char *AC = f64 ? "double" : "float";   // omega accumulator type
+    JitProgram prog;
+    prog.T_lo = 0.0;
+    prog.T_hi = 0.0;
+
+    // FP32 path: v'_k = 2^-(g'_k - h_k) stored as float, with h_k an integer
+    // shift that centres it over a temperature interval [T_lo, T_hi] on which
+    // |g_k - h_k| <= 60 for every species (so that a product of two stays
+    // well inside float range); the shifts of a reaction's reactants are
+    // folded into its log2 A.  Cells outside the interval are reported as
+    // bad.  If no interval containing 300-3000 K qualifies, v stays double.
+    std::vector<int> h(ns, 0);
+    std::vector<double> R(ns, 0.0);     // max |g_k - h_k| on the interval
+    bool vfloat = false;
+    if (!f64) {
+        const double cand[2][2] = {{200.0, 6000.0}, {300.0, 3000.0}};
+        for (const auto &iv : cand) {
+            bool ok = true;
+            for (int k = 0; k < ns && ok; ++k) {
+                double lo = 1e300, hi = -1e300;
+                for (int i = 0; i <= 600; ++i) {
+                    const double T = iv[0] * std::pow(iv[1] / iv[0], i / 600.0);
+                    const double g = g2_host(m.sp[k], T) + std::log2(m.sp[k].inv_W);
+                    lo = std::min(lo, g);
+                    hi = std::max(hi, g);
+                }
+                // both sides of T_mid near the switch
+                for (double T : {m.sp[k].T_mid, std::nextafter(m.sp[k].T_mid, 0.0)})
+                    if (T >= iv[0] && T <= iv[1]) {
+                        const double g = g2_host(m.sp[k], T) + std::log2(m.sp[k].inv_W);
+                        lo = std::min(lo, g);
+                        hi = std::max(hi, g);
+                    }
+                h[k] = (int)std::lround(0.5 * (lo + hi));
+                R[k] = std::max(hi - h[k], h[k] - lo) + 0.5;   // margin for the grid
+                ok = std::isfinite(lo) && std::isfinite(hi) && R[k] <= 60.0;
+            }
+            if (ok) {
+                vfloat = true;
+                prog.T_lo = iv[0];
+                prog.T_hi = iv[1];
+                break;
+            }
+        }
+        if (!vfloat) std::fill(h.begin(), h.end(), 0);
+    }
+    // Species table of the generated kernel: the Gibbs-layer weights with
+    // log2(1/W_k) added to the bias, so that 2^g'_k = 2^{g_k} / W_k and
+    // a_k = C_k 2^{g_k} = rho_hat max(Y_k, 0) 2^{g'_k} needs no 1/W_k.
+    // Then v_k = 2^{-g_k} = 2^{-(g'_k - h_k)} 2^{-(h_k + log2 W_k)}, whose
+    // constant factor joins the reaction's Arrhenius bias.
+    prog.sp.resize(16 * (size_t)ns);
+    std::vector<double> lw(ns);
+    for (int k = 0; k < ns; ++k) {
+        std::memcpy(&prog.sp[16 * k], &m.sp[k], sizeof(SpeciesRec));
+        lw[k] = -std::log2(m.sp[k].inv_W);   // log2 W_k
+        prog.sp[16 * k + 8] -= lw[k];         // lo bias
+        prog.sp[16 * k + 15] -= lw[k];        // hi bias
+    }
+    const std::vector<std::vector<int>> rs = reaction_species(m);
+    const std::vector<int> order = live_order(m, rs);
+    std::vector<int> first(ns, -1), last(ns, -1);
+    for (int p = 0; p < nr; ++p)
+        for (int k : rs[order[p]]) {
+            if (first[k] < 0) first[k] = p;
+            last[k] = p;
+        }
+    // per-reaction constants of the generated kernel: log2 A (with the
+    // reactants' shifts and molecular weights), beta, -E/R log2 e
+    // (in the order of the generated code, so that consecutive reactions'
+    // constants are adjacent)
+    prog.rx.resize(3 * (size_t)nr);
+    for (int p = 0; p < nr; ++p) {
+        const int j = order[p];
+        double shift = 0.0;
+        for (int i = 0; i < m.aux[j].nf; ++i) shift += h[m.aux[j].sp[i]] + lw[m.aux[j].sp[i]];
+        prog.rx[3 * p + 0] = m.rx[j].log2A - shift;
+        prog.rx[3 * p + 1] = m.rx[j].beta;
+        prog.rx[3 * p + 2] = m.rx[j].negEoR2;
+    }
+
+
+    Text o;
+    o("// generated by libannkin for a mechanism of %d species and %d reactions (%s path)\n",
+      ns, nr, f64 ? "FP64" : "FP32");
+    o("typedef long long i64;\ntypedef unsigned long long u64;\n");
+    const std::vector<double> c = exp2_taylor(12);
+    if (f64) {
+        // X * 2^t, degree-12 polynomial for 2^f
+        o("__device__ __forceinline__ double qrate(double X, double t) {\n");
+        o("  const double n = __builtin_rint(t), f = t - n;\n");
+        o("  double p = %s;\n", lit(c[12]).c_str());
+        for (int k = 11; k >= 0; --k) o("  p = __builtin_fma(p, f, %s);\n", lit(c[k]).c_str());
+        o("  return __builtin_ldexp(X * p, (int)n);\n}\n");
+    } else {
+        o("__device__ __forceinline__ float qrate(double X, double t) {\n");
+        o("  const double n = __builtin_rint(t);\n");
+        o("  const float p = __builtin_amdgcn_exp2f((float)(t - n));\n");
+        o("  return (float)__builtin_ldexp(X, (int)n) * p;\n}\n");
+    }
+
+    // omega_k of this lane's cell.  The row offset passes through an empty
+    // volatile asm at the store, so that the compiler forms it there rather
+    // than keeping every row's address in scalar registers from the start.
+    o("__device__ __forceinline__ void store(%s *__restrict__ Ob, i64 ldO, int k, unsigned lane, "
+      "%s x) {\n  i64 off = (i64)k * ldO;\n  asm volatile(\"\" : \"+s\"(off));\n"
+      "  (Ob + off)[lane] = x;\n}\n", IO, IO);
+    // the cell body: Tb, Pb, Yb, Ob point at the tile's first cell
+    o("__device__ __forceinline__ void body(const %s *__restrict__ Tb, const %s *__restrict__ Pb,"
+      " const %s *__restrict__ Yb, i64 ldY, %s *__restrict__ Ob, i64 ldO, unsigned lane,"
+      " const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n",
+      IO, IO, IO, IO);
+    o("  const double T = (double)Tb[lane], P = (double)Pb[lane];\n");
+    for (int k = 0; k < ns; ++k) o("  const %s y%d = (Yb + (i64)%d * ldY)[lane];\n", IO, k, k);
+    o("  const double LNT = log(T), IT = 1.0 / T, T2 = T * T, T3 = T2 * T, T4 = T3 * T;\n");
+    o("  const double L2T = LNT * %s;\n", lit(kLog2e).c_str());
+    // mixture sum (Y <= 0 counts as 0); a non-finite mass fraction makes
+    // chk non-finite
+    o("  %s chk = 0;\n  double sg = 0;\n", IO);
+    for (int k = 0; k < ns; ++k)
+        o("  chk += y%d;\n  sg += __builtin_fmax((double)y%d, 0.0) * SP[%d];\n", k, k, 16 * k);
+    o("  const bool bad = !(T > 0.0) || !(P > 0.0) || !__builtin_isfinite(T) || "
+      "!__builtin_isfinite(P) || !__builtin_isfinite(chk) || !(sg > 0.0) || "
+      "!__builtin_isfinite(sg)");
+    if (vfloat) o(" || !(T >= %s) || !(T <= %s)", lit(prog.T_lo).c_str(), lit(prog.T_hi).c_str());
+    o(";\n");
+    o("  const double rh = P / (%s * T * sg);\n", lit(kRu).c_str());
+    std::map<double, int> tmid;
+    for (int k = 0; k < ns; ++k)
+        if (!tmid.count(m.sp[k].T_mid)) {
+            const int id = (int)tmid.size();
+            tmid[m.sp[k].T_mid] = id;
+            o("  const bool hi%d = T >= %s;\n", id, lit(m.sp[k].T_mid).c_str());
+        }
+    o("  const %s nan = __builtin_nan(\"\");\n", IO);
+
+    const int pdeg = f64 ? 12 : 10;   // 2^f to below one ulp / 3e-13
+    auto open_species = [&](int k) {
+        const int b = 16 * k;
+        auto poly = [&](int off) {
+            char buf[512];
+            snprintf(buf, sizeof buf,
+                     "__builtin_fma(spp[%d], IT, __builtin_fma(spp[%d], T4, "
+                     "__builtin_fma(spp[%d], T3, __builtin_fma(spp[%d], T2, "
+                     "__builtin_fma(spp[%d], T, __builtin_fma(spp[%d], LNT, "
+                     "spp[%d]))))))",
+                     b + off + 5, b + off + 4, b + off + 3, b + off + 2, b + off + 1, b + off,
+                     b + off + 6);
+            return std::string(buf);
+        };
+        o("  double a%d; %s v%d; %s w%d = 0;\n  {\n", k, (f64 || !vfloat) ? "double" : "float", k,
+          AC, k);
+        // both ranges are evaluated and one is selected per lane; the empty
+        // asm keeps the compiler from turning the select of the two
+        // polynomials into a select of their coefficient addresses (which
+        // would make the table reads per-lane vector loads) or into a branch
+        o("    double glo = %s, ghi = %s;\n", poly(2).c_str(), poly(9).c_str());
+        o("    asm(\"\" : \"+v\"(glo), \"+v\"(ghi));\n");
+        o("    const double g = hi%d ? ghi : glo;\n", tmid[m.sp[k].T_mid]);
+        // 2^g and 2^-g from the even and odd parts of one Taylor polynomial
+        o("    const double n = __builtin_rint(g), f = g - n, f2 = f * f;\n");
+        const int top_even = pdeg - (pdeg & 1), top_odd = (pdeg & 1) ? pdeg : pdeg - 1;
+        o("    double E = %s;\n", lit(c[top_even]).c_str());
+        for (int q = top_even - 2; q >= 0; q -= 2)
+            o("    E = __builtin_fma(E, f2, %s);\n", lit(c[q]).c_str());
+        o("    double O = %s;\n", lit(c[top_odd]).c_str());
+        for (int q = top_odd - 2; q >= 1; q -= 2)
+            o("    O = __builtin_fma(O, f2, %s);\n", lit(c[q]).c_str());
+        o("    O *= f;\n    const int ni = (int)n;\n");
+        // y passes through an empty asm so that the compiler does not keep
+        // the mixture sum's converted copy of it live until here
+        o("    %s yy = y%d;\n    asm(\"\" : \"+v\"(yy));\n", IO, k);
+        o("    a%d = rh * __builtin_fmax((double)yy, 0.0) * __builtin_ldexp(E + O, ni);\n", k);
+        if (f64 || !vfloat) o("    v%d = __builtin_ldexp(E - O, -ni);\n", k);
+        else o("    v%d = (float)__builtin_ldexp(E - O, %d - ni);\n", k, h[k]);
+        o("  }\n");
+    };
+
+    // species in no reaction: omega = 0
+    for (int k = 0; k < ns; ++k)
+        if (first[k] < 0) o("  store(Ob, ldO, %d, lane, bad ? nan : (%s)0);\n", k, IO);
+
+    // The reactions are emitted in groups of kGroup, separated by scheduling
+    // fences.  The group's table reads go through pointers that an empty asm
+    // derives from the previous group's last rate, so that they cannot move
+    // ahead of it (left alone, the compiler reads every reaction's and
+    // species' constants at the kernel entry and spills them).
+    const int ngroups = (nr + kGroup - 1) / kGroup;
+    auto load_group = [&](int g) {
+        for (int p = g * kGroup; p < std::min(nr, (g + 1) * kGroup); ++p)
+            o("  const double kA%d = rxp[%d], kB%d = rxp[%d], kE%d = rxp[%d];\n", p, 3 * p, p,
+              3 * p + 1, p, 3 * p + 2);
+    };
+    const bool ahead = std::getenv("AK_JIT_PREFETCH") && std::atoi(std::getenv("AK_JIT_PREFETCH"));
+    o("  const double *rxp = RX, *spp = SP;\n");
+    if (ahead) load_group(0);
+    for (int p = 0; p < nr; ++p) {
+        const int j = order[p];
+        const RxnAux &x = m.aux[j];
+        const int nf = x.nf, np = x.nr;
+        const int g = p / kGroup;
+        if (p % kGroup == 0) {
+            if (p > 0)
+                o("  asm volatile(\"\" : \"+s\"(rxp), \"+s\"(spp) : \"v\"(q%d));\n", p - 1);
+            if (!ahead) load_group(g);
+            else if (g + 1 < ngroups) load_group(g + 1);
+        }
+        for (int k : rs[j])
+            if (first[k] == p) open_species(k);
+        // prefactor 2^t prod_r v: in the FP32 path the float v's are
+        // multiplied in float while the product stays in range, the partial
+        // products in double
+        std::string Vr;
+        if (f64 || !vfloat) {
+            for (int i = 0; i < nf; ++i) Vr += (i ? "*v" : "v") + std::to_string(x.sp[i]);
+        } else {
+            double acc = 0.0;
+            std::string grp;
+            for (int i = 0; i < nf; ++i) {
+                const int k = x.sp[i];
+                if (!grp.empty() && acc + R[k] > 120.0) {
+                    Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
+                    grp.clear();
+                    acc = 0.0;
+                }
+                grp += (grp.empty() ? "v" : "*v") + std::to_string(k);
+                acc += R[k];
+            }
+            Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
+        }
+        std::string Ar, Ap;
+        for (int i = 0; i < nf; ++i) Ar += (i ? "*a" : "a") + std::to_string(x.sp[i]);
+        for (int i = 0; i < np; ++i) Ap += (i ? "*a" : "a") + std::to_string(x.sp[nf + i]);
+        o("  %s q%d;\n  {\n    const double t = __builtin_fma(kB%d, L2T, kE%d * IT) + kA%d;\n",
+          AC, p, p, p, p);
+        if (x.rev)
+            o("    q%d = qrate((%s) * ((%s) - (%s)), t);\n", p, Vr.c_str(), Ar.c_str(),
+              Ap.c_str());
+        else
+            o("    q%d = qrate((%s) * (%s), t);\n", p, Vr.c_str(), Ar.c_str());
+        o("    const %s q = q%d;\n", AC, p);
+        // net coefficient of each species in this reaction (Eq. 2)
+        for (int k : rs[j]) {
+            int nu = 0;
+            for (int i = 0; i < nf + np; ++i)
+                if (x.sp[i] == k) nu += i < nf ? -1 : 1;
+            if (nu == 1) o("    w%d += q;\n", k);
+            else if (nu == -1) o("    w%d -= q;\n", k);
+            else if (nu != 0)
+                o("    w%d = %s((%s)%d, q, w%d);\n", k, f64 ? "__builtin_fma" : "__builtin_fmaf",
+                  AC, nu, k);
+        }
+        o("  }\n");
+        for (int k : rs[j])
+            if (last[k] == p) o("  store(Ob, ldO, %d, lane, bad ? nan : (%s)w%d);\n", k, IO, k);
+        if ((p + 1) % kGroup == 0 || p + 1 == nr) o("  __builtin_amdgcn_sched_barrier(0);\n");
+    }
+    o("  if (bad) atomicAdd(err, 1ull);\n}\n");
+
+    o("struct BD { const void *T, *P, *Y; void *om; i64 ldY, ldO, n, block_begin; };\n");
+    o("extern \"C\" __global__ __launch_bounds__(64) void ak_src(const %s *__restrict__ T, "
+      "const %s *__restrict__ P, const %s *__restrict__ Y, i64 ldY, i64 n, %s *__restrict__ om, "
+      "i64 ldO, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n",
+      IO, IO, IO, IO);
+    o("  const i64 c0 = (i64)blockIdx.x * 64;\n  const unsigned lane = threadIdx.x;\n");
+    o("  if (c0 + lane >= n) return;\n");
+    o("  body(T + c0, P + c0, Y + c0, ldY, om + c0, ldO, lane, SP, RX, err);\n}\n");
+    o("extern \"C\" __global__ __launch_bounds__(64) void ak_src_batch(const BD *__restrict__ d, "
+      "int nreq, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n");
+    o("  const i64 b = blockIdx.x;\n  int lo = 0, hi = nreq - 1;\n");
+    o("  while (lo < hi) { const int mid = (lo + hi + 1) >> 1; "
+      "if (d[mid].block_begin <= b) lo = mid; else hi = mid - 1; }\n");
+    o("  const BD r = d[lo];\n  const i64 c0 = (b - r.block_begin) * 64;\n");
+    o("  const unsigned lane = threadIdx.x;\n  if (c0 + lane >= r.n) return;\n");
+    o("  body((const %s *)r.T + c0, (const %s *)r.P + c0, (const %s *)r.Y + c0, r.ldY, "
+      "(%s *)r.om + c0, r.ldO, lane, SP, RX, err);\n}\n",
+      IO, IO, IO, IO);
+    prog.src = std::move(o.s);
+    return prog;
+}
+
+// ---------------------------------------------------------------------------
+// compilation
+
+namespace {
+
+std::mutex g_cache_mu;
+std::map<std::string, std::vector<char>> g_cache;   // source text -> code object
+
+const char *const kOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17",
+                             "-Xclang",              "-target-feature",
+                             "-Xclang",              "-packed-fp32-ops"};
+
+uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull)
+{
+    for (unsigned char ch : s) {
+        h ^= ch;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// optional on-disk cache of code objects (AK_JIT_CACHE_DIR, else
+// $HOME/.cache/annkin; "off" disables it)
+std::string cache_path(const std::string &src)
+{
+    const char *dir = std::getenv("AK_JIT_CACHE_DIR");
+    std::string d;
+    if (dir && *dir) {
+        if (std::strcmp(dir, "off") == 0) return "";
+        d = dir;
+    } else {
+        const char *home = std::getenv("HOME");
+        if (!home || !*home) return "";
+        d = std::string(home) + "/.cache/annkin";
+    }
+    std::string key = src;
+    for (const char *opt : kOpts) key += opt;
+    int ver_major = 0, ver_minor = 0;
+    hiprtcVersion(&ver_major, &ver_minor);
+    key += std::to_string(ver_major) + "." + std::to_string(ver_minor);
+    char name[64];
+    snprintf(name, sizeof name, "/jit-%016llx.co", (unsigned long long)fnv1a(key));
+    return d + name;
+}
+
+bool read_file(const std::string &p, std::vector<char> &out)
+{
+    FILE *f = std::fopen(p.c_str(), "rb");
+    if (!f) return false;
+    std::fseek(f, 0, SEEK_END);
+    const long n = std::ftell(f);
+    std::fseek(f, 0, SEEK_SET);
+    bool ok = n > 0;
+    if (ok) {
+        out.resize(n);
+        ok = std::fread(out.data(), 1, n, f) == (size_t)n;
+    }
+    std::fclose(f);
+    return ok;
+}
+
+void write_file(const std::string &p, const std::vector<char> &data)
+{
+    const size_t slash = p.rfind('/');
+    if (slash != std::string::npos) {
+        // create the directory chain (ignore failures: the cache is optional)
+        std::string dir = p.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') {
+                std::string sub = dir.substr(0, i);
+                (void)mkdir(sub.c_str(), 0755);
+            }
+    }
+    char tmp_suffix[32];
+    snprintf(tmp_suffix, sizeof tmp_suffix, ".tmp%d", (int)getpid());
+    const std::string tmp = p + tmp_suffix;
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    const bool ok = std::fwrite(data.data(), 1, data.size(), f) == data.size();
+    std::fclose(f);
+    if (ok) std::rename(tmp.c_str(), p.c_str());
+    else std::remove(tmp.c_str());
+}
+
+}  // namespace
+
+int jit_compile(const std::string &src, std::vector<char> &code, std::string &log)
+{
+    {
+        std::lock_guard<std::mutex> l(g_cache_mu);
+        auto it = g_cache.find(src);
+        if (it != g_cache.end()) {
+            code = it->second;
+            return AK_OK;
+        }
+    }
+    const std::string path = cache_path(src);
+    if (!path.empty() && read_file(path, code)) {
+        std::lock_guard<std::mutex> l(g_cache_mu);
+        g_cache[src] = code;
+        return AK_OK;
+    }
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "annkin_mechanism.hip", 0, nullptr, nullptr) !=
+        HIPRTC_SUCCESS) {
+        log = "hiprtcCreateProgram failed";
+        return AK_EDEVICE;
+    }
+    const hiprtcResult r =
+        hiprtcCompileProgram(prog, (int)(sizeof kOpts / sizeof kOpts[0]), kOpts);
+    size_t ls = 0;
+    if (hiprtcGetProgramLogSize(prog, &ls) == HIPRTC_SUCCESS && ls > 1) {
+        std::vector<char> b(ls + 1, 0);
+        if (hiprtcGetProgramLog(prog, b.data()) == HIPRTC_SUCCESS) log.assign(b.data());
+    }
+    if (r != HIPRTC_SUCCESS) {
+        hiprtcDestroyProgram(&prog);
+        if (log.empty()) log = hiprtcGetErrorString(r);
+        return AK_EDEVICE;
+    }
+    size_t cs = 0;
+    if (hiprtcGetCodeSize(prog, &cs) != HIPRTC_SUCCESS || cs == 0) {
+        hiprtcDestroyProgram(&prog);
+        log = "hiprtc produced no code";
+        return AK_EDEVICE;
+    }
+    code.resize(cs);
+    const hiprtcResult g = hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    if (g != HIPRTC_SUCCESS) {
+        log = "hiprtcGetCode failed";
+        return AK_EDEVICE;
+    }
+    if (!path.empty()) write_file(path, code);
+    std::lock_guard<std::mutex> l(g_cache_mu);
+    g_cache[src] = code;
+    return AK_OK;
+}
+
+int jit_load(const std::vector<char> &code, JitKernels &out)
+{
+    hipError_t e = hipModuleLoadData(&out.mod, code.data());
+    if (e != hipSuccess) return hip_error(e, "loading the mechanism's kernels");
+    if ((e = hipModuleGetFunction(&out.src, out.mod, "ak_src")) != hipSuccess ||
+        (e = hipModuleGetFunction(&out.batch, out.mod, "ak_src_batch")) != hipSuccess) {
+        (void)hipModuleUnload(out.mod);
+        out.mod = nullptr;
+        return hip_error(e, "finding the mechanism's kernels");
+    }
+    out.block = 64;
+    return AK_OK;
+}
+
+void jit_unload(JitKernels &k)
+{
+    if (k.mod) (void)hipModuleUnload(k.mod);
+    k.mod = nullptr;
+    k.src = k.batch = nullptr;
+}
+
+hipError_t jit_launch(const JitKernels &k, const void *T, const void *P, const void *Y,
+                      int64_t ldY, int64_t n, void *om, int64_t ldO, unsigned long long *err,
+                      hipStream_t st)
+{
+    const int64_t blocks = (n + k.block - 1) / k.block;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const double *SP = k.sp, *RX = k.rx;
+    void *args[] = {(void *)&T, (void *)&P,  (void *)&Y,  (void *)&ldY, (void *)&n,
+                    (void *)&om, (void *)&ldO, (void *)&SP, (void *)&RX, (void *)&err};
+    return hipModuleLaunchKernel(k.src, (unsigned)blocks, 1, 1, k.block, 1, 1, 0, st, args,
+                                 nullptr);
+}
+
+hipError_t jit_batch_launch(const JitKernels &k, const JitBatchDesc *d_desc, int nreq,
+                            int64_t blocks, unsigned long long *err, hipStream_t st)
+{
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const double *SP = k.sp, *RX = k.rx;
+    void *args[] = {(void *)&d_desc, (void *)&nreq, (void *)&SP, (void *)&RX, (void *)&err};
+    return hipModuleLaunchKernel(k.batch, (unsigned)blocks, 1, 1, k.block, 1, 1, 0, st, args,
+                                 nullptr);
+}
+
+}  // namespace ak

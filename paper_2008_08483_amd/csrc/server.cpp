@@ -41,13 +41,6 @@ struct GpuExec {
     int max_req = 64;
     std::vector<Slot> slots;
     std::mutex mu;
-    std::string last_error;          // the last failure (guarded by mu)
-
-    std::string error_text()
-    {
-        std::lock_guard<std::mutex> l(mu);
-        return last_error;
-    }
 
     int init(int dev, size_t arena_bytes, int inflight, int max_requests)
     {
@@ -183,21 +176,22 @@ struct GpuExec {
         return s;
     }
 
-    int wait(void *token, size_t i)
+    // Wait for request i of a batch; on failure *err says why (the text is
+    // copied into the request, which outlives the server).
+    int wait(void *token, size_t i, std::string *err)
     {
-        if (!token) return AK_EDEVICE;
+        if (!token) {
+            *err = "no stream slot for the batch";
+            return AK_EDEVICE;
+        }
         Slot *s = (Slot *)token;
         DeviceGuard g(device);
         hipError_t e = hipEventSynchronize(s->ev[i]);
         if (e != hipSuccess) {
-            std::lock_guard<std::mutex> l(mu);
-            last_error = std::string("event wait: ") + hipGetErrorString(e);
+            *err = std::string("event wait: ") + hipGetErrorString(e);
             return AK_EDEVICE;
         }
-        if (s->rc) {
-            std::lock_guard<std::mutex> l(mu);
-            last_error = s->what;
-        }
+        if (s->rc) *err = s->what;
         return s->rc;
     }
 
@@ -304,9 +298,14 @@ int ak_request_wait(ak_request *q, double timeout_s)
     const int rc = Scheduler<GpuExec>::wait(&q->r, timeout_s);
     if (rc == -5) return set_error(AK_ETIMEDOUT, "ak_request_wait: timed out");
     if (rc == -6) return set_error(AK_ECANCELED, "ak_request_wait: request was cancelled");
-    if (rc)
-        return set_error(rc, "ak_request_wait: request failed (%s)",
-                         q->srv->exec.error_text().c_str());
+    if (rc) {
+        std::string why;
+        {
+            std::lock_guard<std::mutex> l(q->r.mu);
+            why = q->r.error;
+        }
+        return set_error(rc, "ak_request_wait: request failed (%s)", why.c_str());
+    }
     return AK_OK;
 }
 

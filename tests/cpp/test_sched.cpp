@@ -64,9 +64,12 @@ struct MockExec {
     }
     // request i of a batch; the batch counts as outstanding until its last
     // request has been waited for
-    int wait(void *p, size_t i)
+    int wait(void *p, size_t i, std::string *err)
     {
-        if (!p) return -2;
+        if (!p) {
+            *err = "no slot";
+            return -2;
+        }
         Tok *t = (Tok *)p;
         std::unique_lock<std::mutex> l(mu);
         if (autoc) {
@@ -77,6 +80,7 @@ struct MockExec {
             cv.wait(l, [t] { return t->open; });
         }
         if (i + 1 == t->ids.size()) --outstanding;
+        if (t->rc) *err = "mock batch failure";
         return t->rc;
     }
     void release(void *p)
@@ -269,6 +273,31 @@ static void test_cancel_timeout_failure()
     CHECK(Scheduler<MockExec>::wait(d.get(), 5.0) == 0);
     auto st = s.stats();
     CHECK(st.failed == 1 && st.cancelled == 1 && st.completed == 1);
+    // the failure's text travels with the request
+    std::lock_guard<std::mutex> l(a->mu);
+    CHECK(a->error == "mock batch failure");
+}
+
+// A failed request's error stays readable after its scheduler and executor
+// are gone (the text is copied into the request at completion).
+static void test_error_outlives_server()
+{
+    auto a = req(1, 256);
+    {
+        auto ex = std::make_unique<MockExec>();
+        ex->fail_batch = 0;
+        ex->autoc = true;
+        SchedConfig c;
+        c.arena_bytes = 1 << 20;
+        auto s = std::make_unique<Scheduler<MockExec>>(c, ex.get());
+        CHECK(s->submit(a.get()) == 0);
+        CHECK(Scheduler<MockExec>::wait(a.get(), 5.0) == -2);
+        s->shutdown();
+        s.reset();
+        ex.reset();
+    }
+    std::lock_guard<std::mutex> l(a->mu);
+    CHECK(a->state == kFailed && a->error == "mock batch failure");
 }
 
 static void test_shutdown()
@@ -330,6 +359,7 @@ static void test_stress()
 
 int main()
 {
+    test_error_outlives_server();
     test_arena();
     test_continuous_batching();
     test_admission_by_memory_fifo();

@@ -50,3 +50,35 @@ def test_argument_errors_without_gpu(lib):
     assert lib.ak_free_mechanism(None) == 0
     assert lib.ak_mechanism_n_species(None) == -1
     assert lib.ak_version().startswith(b"annkin")
+
+
+def test_server_submit_rejects_mismatched_buffers():
+    """Server.submit checks dtypes, shapes and contiguity of every host buffer
+    before anything reaches the library (no GPU needed)."""
+    import numpy as np
+    import pytest
+    from paper_2008_08483_amd import annkin
+
+    class _M:
+        n_species = 3
+        handle = None
+
+    srv = object.__new__(annkin.Server)   # never created: submit must raise first
+    n = 8
+    Y = np.zeros((3, n), np.float64)
+    T = np.ones(n)
+    P = np.ones(n)
+    out = np.zeros((3, n))
+    bad = [
+        (T.astype(np.float32), P, Y, out, TypeError),          # T dtype
+        (T, P.astype(np.float32), Y, out, TypeError),          # P dtype
+        (T, P, Y, out.astype(np.float32), TypeError),          # out dtype
+        (T[:4], P, Y, out, ValueError),                        # T length
+        (np.ones(2 * n)[::2], P, Y, out, ValueError),          # T not contiguous
+        (T, P, Y, np.zeros((3, 2 * n))[:, ::2], ValueError),   # out cell stride
+        (T, P, np.zeros((2, n)), out, ValueError),             # Y species count
+        (T.astype(np.int32), P.astype(np.int32), Y.astype(np.int32), out, TypeError),
+    ]
+    for t, p, y, o, exc in bad:
+        with pytest.raises(exc):
+            srv.submit(_M(), t, p, y, o)

@@ -22,19 +22,32 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in msg["error"]
 
 
-def test_method_slots_of_one_reaction():
-    # A + A <=> B: per species ln C (4), C from Y (3), Gibbs layer (7), mu (1);
-    # per cell ln T and 1/T (8), T^2..T^4 and ln C0 (4); the reaction: Arrhenius
-    # (2), ln k_r (1), q_f - q_r (1), nu'.lnC (1 nonzero), nu.Gt (2), nu''.lnC
-    # (1), two exponentials (8), production (2)
+def test_method_counts_of_one_reaction():
+    # A + A <=> B (2 species, 1 reaction), by the formulas of the method:
+    # transcendentals 2 NR + NS + 3 = 7; FP64 7 NS + 3 NR = 17; FP32-class
+    # Arrhenius 3 + nu'.lnC 1 nonzero + rate 1 + production 2 nonzeros = 7;
+    # slots 4 * 7 + 7 + 17 = 52
     nu_f = np.array([[2, 0]], np.int8)
     nu_r = np.array([[0, 1]], np.int8)
-    assert roofline.method_slots(nu_f, nu_r) == 2 * 15 + 12 + 18
+    assert roofline.method_counts(nu_f, nu_r) == (7, 7, 17)
+    assert roofline.method_slots(nu_f, nu_r) == 52.0
 
 
-def test_method_slots_of_the_benchmark_mechanism():
+def test_roofline_of_the_benchmark_mechanism():
+    # 53 species / 325 reactions x 2^20 cells: 706 transcendentals, 2,868
+    # FP32-class and 1,346 FP64 operations per cell -> 4 * 706 + 2868 + 1346
+    # = 7,038 slots, 187.7 us at 39.32 T slots/s; with the microbenchmarked
+    # rates 706/21 + 2868/82 + 1346/46 = 97.9 CU-clocks per cell, 167.0 us
     src = synth.make_mechanism(53, 325)
-    assert roofline.method_slots(src.nu_f, src.nu_r) == 8292.0
+    assert roofline.method_slots(src.nu_f, src.nu_r) == 7038.0
+    n = 1 << 20
+    assert abs(roofline.t_valu(src.nu_f, src.nu_r, n) - 7038 * n / 39.3216e12) < 1e-12
+    clocks = 706 / 21 + 2868 / 82 + 1346 / 46
+    assert abs(roofline.t_valu(src.nu_f, src.nu_r, n, "measured") - clocks * n / (256 * 2.4e9)) \
+        < 1e-12
+    r = roofline.roofline(src.nu_f, src.nu_r, n, 4, 0.7e-3)
+    assert abs(r["frac"] - 187.68e-6 / 0.7e-3) < 1e-3
+    assert r["t_hbm_s"] < r["t_valu_slots_s"]
 
 
 def test_compulsory_bytes_match_the_traffic_record():
