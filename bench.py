@@ -394,7 +394,8 @@ def main():
             "unit": "T VALU lane-slots/s",
             "frac": achieved / roofline.PEAK_VALU_SLOTS,
             "traffic": traffic,
-            "kernel": "ak::source_kernel<float>",
+            "kernel": ("ak_src (compiled for the mechanism)" if mech.compiled(torch.float32)
+                       else "ak::source_kernel<float>"),
             "slots_per_cell": slots,
             "hbm_GBps": roofline.hbm_bytes(ns, 4) * n / k_avg_s / 1e9,
             "hbm_frac": roofline.hbm_bytes(ns, 4) * n / k_avg_s / roofline.PEAK_HBM,

@@ -206,9 +206,9 @@ def _stream_ptr(stream):
 
 def _prec(dtype):
     torch = _torch()
-    if dtype == torch.float32:
+    if dtype == torch.float32 or dtype is np.float32 or dtype == np.dtype(np.float32):
         return AK_FP32
-    if dtype == torch.float64:
+    if dtype == torch.float64 or dtype is np.float64 or dtype == np.dtype(np.float64):
         return AK_FP64
     raise TypeError(f"unsupported dtype {dtype}: use float32 or float64")
 

@@ -23,6 +23,9 @@ struct ak_mechanism {
 namespace ak {
 
 int set_error(int code, const char *fmt, ...);
+// Let a kernel use the device's whole LDS as dynamic shared memory (set once
+// per kernel and device, on the current device).
+hipError_t allow_dynamic_lds(const void *fn);
 int hip_error(hipError_t e, const char *what);
 
 // Makes `dev` current for the lifetime of the guard, restoring the caller's

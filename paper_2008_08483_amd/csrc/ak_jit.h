@@ -31,7 +31,8 @@ struct JitKernels {
     hipModule_t mod = nullptr;
     hipFunction_t src = nullptr;
     hipFunction_t batch = nullptr;
-    int block = 64;          // threads per workgroup of both kernels
+    int block = 64;          // cells per workgroup of both kernels
+    int threads = 64;        // threads per workgroup
 };
 
 // One request of a fused launch of generated kernels (device table).
@@ -42,10 +43,16 @@ struct JitBatchDesc {
     int64_t block_begin;     // first workgroup of this request
 };
 
-// Whether the register-resident form suits a mechanism of this size: the
-// whole per-cell state (a, v and the omega accumulators) must fit the
-// register file of one lane.
+// Waves per 64-cell tile of the tiled form, and the largest mechanism for
+// which the whole per-cell state (a, v and the omega accumulators) is kept in
+// the registers of one lane instead.
+constexpr int kTileWaves = 4;
+constexpr int kLaneFormMaxSpecies = 16;
+
+// Whether a mechanism of this size gets compiled kernels: two tiles of the
+// tiled form must fit a CU's LDS.
 bool jit_suitable(int ns, bool f64);
+size_t tile_lds_bytes(int ns, bool f64, int waves);
 
 // Generated kernels of one mechanism and precision: the HIP source text of
 // both kernels and the constant tables they read (per species the Gibbs
@@ -55,11 +62,22 @@ bool jit_suitable(int ns, bool f64);
 // as bad (T_lo = T_hi = 0: no restriction).
 struct JitProgram {
     std::string src;
+    int threads = 64;         // threads per workgroup (one workgroup: 64 cells)
     std::vector<double> sp;   // 16 doubles per species (SpeciesRec layout)
     std::vector<double> rx;
     double T_lo = 0.0, T_hi = 0.0;
 };
 JitProgram jit_program(const JitMech &m, bool f64);
+
+// The same kernels for larger mechanisms, one 64-cell tile per workgroup of
+// `waves` waves: the per-species factors of the tile in LDS, each wave
+// sweeping a fixed subset of the reactions with its own rate accumulators,
+// which the waves then add up in a fixed order.
+JitProgram jit_program_tile(const JitMech &m, bool f64, int waves);
+
+// The form that suits the mechanism (lane-per-cell for small ones, tiled
+// otherwise).
+JitProgram jit_generate(const JitMech &m, bool f64);
 
 // Compile the text for gfx950 with hiprtc; returns 0 or an AK_E* code (the
 // compiler log goes to `log`).  Results are cached in the process by text.

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -48,6 +49,35 @@ DeviceGuard::~DeviceGuard()
 {
     int cur = -1;
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
+
+hipError_t allow_dynamic_lds(const void *fn)
+{
+    // Raised once per (kernel, device) to the device's whole LDS, never
+    // lowered, so that concurrent launches of one kernel with different LDS
+    // sizes cannot race on this process-wide attribute.
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, bool> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> l(mu);
+    if (done.count({fn, dev})) return hipSuccess;
+    int lds_max = 0;
+    if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                   dev)) != hipSuccess)
+        return e;
+    lds_max = std::min(lds_max, 160 * 1024);
+    // the kernel's static LDS comes out of the same budget
+    hipFuncAttributes fa;
+    if ((e = hipFuncGetAttributes(&fa, fn)) != hipSuccess) return e;
+    const int dyn = lds_max - (int)fa.sharedSizeBytes;
+    if (dyn <= 0) return hipErrorInvalidValue;
+    if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, dyn)) !=
+        hipSuccess)
+        return e;
+    done[{fn, dev}] = true;
+    return hipSuccess;
 }
 
 // Gibbs-layer weights on (ln T, T, T^2, T^3, T^4, 1/T, 1) for one NASA-7
@@ -243,7 +273,7 @@ int ak_jit_source(const ak_mechanism_desc *d, ak_precision prec, char *buf, size
     Prepared p;
     int rc = prepare(d, p);
     if (rc) return rc;
-    const std::string src = jit_program(jit_view(p), prec == AK_FP64).src;
+    const std::string src = jit_generate(jit_view(p), prec == AK_FP64).src;
     *needed = src.size() + 1;
     if (buf && cap > 0) {
         const size_t n = std::min(cap - 1, src.size());
@@ -295,7 +325,7 @@ int ak_load_mechanism_ex(const ak_mechanism_desc *d, int device, int kernels, ak
     for (int f = 0; f < 2; ++f) {
         const bool f64 = f == AK_FP64;   // index = ak_precision
         if (kernels != AK_KERNEL_AUTO || !jit_suitable(ns, f64)) continue;
-        prog[f] = jit_program(jit_view(p), f64);
+        prog[f] = jit_generate(jit_view(p), f64);
         std::string log;
         rc = jit_compile(prog[f].src, code[f], log);
         if (rc) return set_error(rc, "ak_load_mechanism: compiling the mechanism's kernels "
@@ -357,6 +387,7 @@ int ak_load_mechanism_ex(const ak_mechanism_desc *d, int device, int kernels, ak
     for (int f = 0; f < 2; ++f) {
         if (!use_jit[f]) continue;
         rc = jit_load(code[f], m->jit[f]);
+        m->jit[f].threads = prog[f].threads;
         m->jit[f].sp = (const double *)(dev + o_jsp[f]);
         m->jit[f].rx = (const double *)(dev + o_jrx[f]);
         m->jit[f].T_lo = prog[f].T_lo;

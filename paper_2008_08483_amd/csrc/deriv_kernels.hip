@@ -17,6 +17,7 @@
 #include <stdint.h>
 
 #include "ak_device.h"
+#include "ak_internal.h"
 #include "ak_math.h"
 
 namespace ak {
@@ -541,8 +542,7 @@ static hipError_t jacobian_launch_t(const MechView &m, const void *T, const void
     if (n > 0x7fffffff) return hipErrorInvalidValue;
     const size_t lds = jacobian_lds_per_cell(m.ns);
     auto fn = jacobian_kernel<IO>;
-    hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = allow_dynamic_lds((const void *)fn);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3((unsigned)n), dim3(kJacThreads), lds, st, m, (const IO *)T,
                        (const IO *)P, (const IO *)Y, ldY, n, (IO *)J, ldJ);
@@ -572,8 +572,7 @@ static hipError_t vjp_launch_t(const MechView &m, int tile, const void *T, const
 {
     const size_t lds = (size_t)m.ns * tile * kVjpEntry;
     auto fn = vjp_kernel<IO, KV>;
-    hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = allow_dynamic_lds((const void *)fn);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * kVjpWaves), lds, st, m, tile,
                        (const IO *)T, (const IO *)P, (const IO *)Y, ldY, n, (const IO *)G, ldG,

@@ -91,12 +91,16 @@ std::vector<double> exp2_taylor(int deg)
 
 bool jit_suitable(int ns, bool f64)
 {
-    // registers per species: a (double), v (float in the FP32 path, double
-    // in the FP64 path) and the accumulator (float / double); a lane has 512
-    // (256 of them usable directly by the vector ALU), some of which the
-    // rest of the kernel needs
-    const int per = f64 ? 6 : 4;
-    return ns * per <= 320;
+    // the tiled form keeps a (double) and v (float or double) of each
+    // species and cell of a 64-cell tile in LDS and needs two tiles per CU;
+    // the accumulators (one per species) stay within the register cap
+    return tile_lds_bytes(ns, f64, kTileWaves) <= 80 * 1024;
+}
+
+size_t tile_lds_bytes(int ns, bool f64, int waves)
+{
+    const size_t v = f64 ? 8 : 4;   // FP32 path: v as float where its range allows
+    return (size_t)64 * ns * (8 + v) + (size_t)64 * waves * (8 + (f64 ? 8 : 4));
 }
 
 namespace {
@@ -159,28 +163,34 @@ std::vector<int> live_order(const JitMech &m, const std::vector<std::vector<int>
 
 }  // namespace
 
-// reactions per group of table reads (see below)
-static int kGroup = 2;
+namespace {
 
-JitProgram jit_program(const JitMech &m, bool f64)
+// What both generators share: the FP32 path's per-species shifts of v and
+// the species table.
+struct Common {
+    std::vector<int> h;        // integer shift of log2 v per species (FP32 path)
+    std::vector<double> R;     // max |g_k - h_k| over the temperature interval
+    std::vector<double> lw;    // log2 W_k
+    bool vfloat = false;       // v stored as float
+};
+
+Common common_setup(const JitMech &m, bool f64, JitProgram &prog)
 {
-    if (const char *g = std::getenv("AK_JIT_GROUP")) kGroup = std::max(1, std::atoi(g));
-    const int ns = m.ns, nr = m.nr;
-    const char *IO = f64 ? "double" : "float";
-    const char *AC = f64 ? "double" : "float";   // omega accumulator type
-    JitProgram prog;
-    prog.T_lo = 0.0;
-    prog.T_hi = 0.0;
-
+    const int ns = m.ns;
+    Common cm;
+    std::vector<int> &h = cm.h;
+    std::vector<double> &R = cm.R;
+    std::vector<double> &lw = cm.lw;
+    bool &vfloat = cm.vfloat;
+    h.assign(ns, 0);
+    R.assign(ns, 0.0);
+    lw.assign(ns, 0.0);
     // FP32 path: v'_k = 2^-(g'_k - h_k) stored as float, with h_k an integer
     // shift that centres it over a temperature interval [T_lo, T_hi] on which
     // |g_k - h_k| <= 60 for every species (so that a product of two stays
     // well inside float range); the shifts of a reaction's reactants are
     // folded into its log2 A.  Cells outside the interval are reported as
     // bad.  If no interval containing 300-3000 K qualifies, v stays double.
-    std::vector<int> h(ns, 0);
-    std::vector<double> R(ns, 0.0);     // max |g_k - h_k| on the interval
-    bool vfloat = false;
     if (!f64) {
         const double cand[2][2] = {{200.0, 6000.0}, {300.0, 3000.0}};
         for (const auto &iv : cand) {
@@ -219,13 +229,35 @@ JitProgram jit_program(const JitMech &m, bool f64)
     // Then v_k = 2^{-g_k} = 2^{-(g'_k - h_k)} 2^{-(h_k + log2 W_k)}, whose
     // constant factor joins the reaction's Arrhenius bias.
     prog.sp.resize(16 * (size_t)ns);
-    std::vector<double> lw(ns);
     for (int k = 0; k < ns; ++k) {
         std::memcpy(&prog.sp[16 * k], &m.sp[k], sizeof(SpeciesRec));
         lw[k] = -std::log2(m.sp[k].inv_W);   // log2 W_k
         prog.sp[16 * k + 8] -= lw[k];         // lo bias
         prog.sp[16 * k + 15] -= lw[k];        // hi bias
     }
+    return cm;
+}
+
+}  // namespace
+
+// reactions per group of table reads (see below)
+static int kGroup = 2;
+
+JitProgram jit_program(const JitMech &m, bool f64)
+{
+    if (const char *g = std::getenv("AK_JIT_GROUP")) kGroup = std::max(1, std::atoi(g));
+    const int ns = m.ns, nr = m.nr;
+    const char *IO = f64 ? "double" : "float";
+    const char *AC = f64 ? "double" : "float";   // omega accumulator type
+    JitProgram prog;
+    prog.T_lo = 0.0;
+    prog.T_hi = 0.0;
+
+    const Common cm = common_setup(m, f64, prog);
+    const std::vector<int> &h = cm.h;
+    const std::vector<double> &R = cm.R;
+    const std::vector<double> &lw = cm.lw;
+    const bool vfloat = cm.vfloat;
     const std::vector<std::vector<int>> rs = reaction_species(m);
     const std::vector<int> order = live_order(m, rs);
     std::vector<int> first(ns, -1), last(ns, -1);
@@ -249,6 +281,12 @@ JitProgram jit_program(const JitMech &m, bool f64)
     }
 
 
+    const char *VT = (f64 || !vfloat) ? "double" : "float";
+    const bool vlds = std::getenv("AK_JIT_VLDS") && std::atoi(std::getenv("AK_JIT_VLDS"));
+    const bool yreload = std::getenv("AK_JIT_YRELOAD") && std::atoi(std::getenv("AK_JIT_YRELOAD"));
+    auto vname = [&](int k) {
+        return vlds ? "vsh[" + std::to_string(k) + " * 64 + lane]" : "v" + std::to_string(k);
+    };
     Text o;
     o("// generated by libannkin for a mechanism of %d species and %d reactions (%s path)\n",
       ns, nr, f64 ? "FP64" : "FP32");
@@ -277,8 +315,8 @@ JitProgram jit_program(const JitMech &m, bool f64)
     // the cell body: Tb, Pb, Yb, Ob point at the tile's first cell
     o("__device__ __forceinline__ void body(const %s *__restrict__ Tb, const %s *__restrict__ Pb,"
       " const %s *__restrict__ Yb, i64 ldY, %s *__restrict__ Ob, i64 ldO, unsigned lane,"
-      " const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n",
-      IO, IO, IO, IO);
+      " const double *__restrict__ SP, const double *__restrict__ RX, u64 *err%s) {\n",
+      IO, IO, IO, IO, vlds ? (std::string(", ") + VT + " *vsh").c_str() : "");
     o("  const double T = (double)Tb[lane], P = (double)Pb[lane];\n");
     for (int k = 0; k < ns; ++k) o("  const %s y%d = (Yb + (i64)%d * ldY)[lane];\n", IO, k, k);
     o("  const double LNT = log(T), IT = 1.0 / T, T2 = T * T, T3 = T2 * T, T4 = T3 * T;\n");
@@ -317,8 +355,8 @@ JitProgram jit_program(const JitMech &m, bool f64)
                      b + off + 6);
             return std::string(buf);
         };
-        o("  double a%d; %s v%d; %s w%d = 0;\n  {\n", k, (f64 || !vfloat) ? "double" : "float", k,
-          AC, k);
+        if (vlds) o("  double a%d; %s w%d = 0;\n  {\n", k, AC, k);
+        else o("  double a%d; %s v%d; %s w%d = 0;\n  {\n", k, VT, k, AC, k);
         // both ranges are evaluated and one is selected per lane; the empty
         // asm keeps the compiler from turning the select of the two
         // polynomials into a select of their coefficient addresses (which
@@ -338,10 +376,11 @@ JitProgram jit_program(const JitMech &m, bool f64)
         o("    O *= f;\n    const int ni = (int)n;\n");
         // y passes through an empty asm so that the compiler does not keep
         // the mixture sum's converted copy of it live until here
-        o("    %s yy = y%d;\n    asm(\"\" : \"+v\"(yy));\n", IO, k);
+        if (yreload) o("    %s yy = (ypp + (i64)%d * ldY)[lane];\n", IO, k);
+        else o("    %s yy = y%d;\n    asm(\"\" : \"+v\"(yy));\n", IO, k);
         o("    a%d = rh * __builtin_fmax((double)yy, 0.0) * __builtin_ldexp(E + O, ni);\n", k);
-        if (f64 || !vfloat) o("    v%d = __builtin_ldexp(E - O, -ni);\n", k);
-        else o("    v%d = (float)__builtin_ldexp(E - O, %d - ni);\n", k, h[k]);
+        if (f64 || !vfloat) o("    %s = __builtin_ldexp(E - O, -ni);\n", vname(k).c_str());
+        else o("    %s = (float)__builtin_ldexp(E - O, %d - ni);\n", vname(k).c_str(), h[k]);
         o("  }\n");
     };
 
@@ -362,6 +401,7 @@ JitProgram jit_program(const JitMech &m, bool f64)
     };
     const bool ahead = std::getenv("AK_JIT_PREFETCH") && std::atoi(std::getenv("AK_JIT_PREFETCH"));
     o("  const double *rxp = RX, *spp = SP;\n");
+    if (yreload) o("  const %s *ypp = Yb;\n", IO);
     if (ahead) load_group(0);
     for (int p = 0; p < nr; ++p) {
         const int j = order[p];
@@ -370,7 +410,8 @@ JitProgram jit_program(const JitMech &m, bool f64)
         const int g = p / kGroup;
         if (p % kGroup == 0) {
             if (p > 0)
-                o("  asm volatile(\"\" : \"+s\"(rxp), \"+s\"(spp) : \"v\"(q%d));\n", p - 1);
+                o("  asm volatile(\"\" : \"+s\"(rxp), \"+s\"(spp)%s : \"v\"(q%d));\n",
+                  yreload ? ", \"+s\"(ypp)" : "", p - 1);
             if (!ahead) load_group(g);
             else if (g + 1 < ngroups) load_group(g + 1);
         }
@@ -381,7 +422,7 @@ JitProgram jit_program(const JitMech &m, bool f64)
         // products in double
         std::string Vr;
         if (f64 || !vfloat) {
-            for (int i = 0; i < nf; ++i) Vr += (i ? "*v" : "v") + std::to_string(x.sp[i]);
+            for (int i = 0; i < nf; ++i) Vr += (i ? "*" : "") + vname(x.sp[i]);
         } else {
             double acc = 0.0;
             std::string grp;
@@ -392,7 +433,7 @@ JitProgram jit_program(const JitMech &m, bool f64)
                     grp.clear();
                     acc = 0.0;
                 }
-                grp += (grp.empty() ? "v" : "*v") + std::to_string(k);
+                grp += (grp.empty() ? "" : "*") + vname(k);
                 acc += R[k];
             }
             Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
@@ -400,7 +441,7 @@ JitProgram jit_program(const JitMech &m, bool f64)
         std::string Ar, Ap;
         for (int i = 0; i < nf; ++i) Ar += (i ? "*a" : "a") + std::to_string(x.sp[i]);
         for (int i = 0; i < np; ++i) Ap += (i ? "*a" : "a") + std::to_string(x.sp[nf + i]);
-        o("  %s q%d;\n  {\n    const double t = __builtin_fma(kB%d, L2T, kE%d * IT) + kA%d;\n",
+        o("  %s q%d;\n  {\n    const double t = __builtin_fma(kB%d, L2T, __builtin_fma(kE%d, IT, kA%d));\n",
           AC, p, p, p, p);
         if (x.rev)
             o("    q%d = qrate((%s) * ((%s) - (%s)), t);\n", p, Vr.c_str(), Ar.c_str(),
@@ -427,25 +468,374 @@ JitProgram jit_program(const JitMech &m, bool f64)
     o("  if (bad) atomicAdd(err, 1ull);\n}\n");
 
     o("struct BD { const void *T, *P, *Y; void *om; i64 ldY, ldO, n, block_begin; };\n");
-    o("extern \"C\" __global__ __launch_bounds__(64) void ak_src(const %s *__restrict__ T, "
+    int wpe = 1;
+    if (const char *w = std::getenv("AK_JIT_WPE")) wpe = std::max(1, std::atoi(w));
+    o("#define AK_LB __launch_bounds__(64, %d)\n", wpe);
+    o("extern \"C\" __global__ AK_LB void ak_src(const %s *__restrict__ T, "
       "const %s *__restrict__ P, const %s *__restrict__ Y, i64 ldY, i64 n, %s *__restrict__ om, "
       "i64 ldO, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n",
       IO, IO, IO, IO);
     o("  const i64 c0 = (i64)blockIdx.x * 64;\n  const unsigned lane = threadIdx.x;\n");
     o("  if (c0 + lane >= n) return;\n");
-    o("  body(T + c0, P + c0, Y + c0, ldY, om + c0, ldO, lane, SP, RX, err);\n}\n");
-    o("extern \"C\" __global__ __launch_bounds__(64) void ak_src_batch(const BD *__restrict__ d, "
+    if (vlds) o("  __shared__ %s vsh[%d * 64];\n", VT, ns);
+    o("  body(T + c0, P + c0, Y + c0, ldY, om + c0, ldO, lane, SP, RX, err%s);\n}\n",
+      vlds ? ", vsh" : "");
+    o("extern \"C\" __global__ AK_LB void ak_src_batch(const BD *__restrict__ d, "
       "int nreq, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n");
     o("  const i64 b = blockIdx.x;\n  int lo = 0, hi = nreq - 1;\n");
     o("  while (lo < hi) { const int mid = (lo + hi + 1) >> 1; "
       "if (d[mid].block_begin <= b) lo = mid; else hi = mid - 1; }\n");
     o("  const BD r = d[lo];\n  const i64 c0 = (b - r.block_begin) * 64;\n");
     o("  const unsigned lane = threadIdx.x;\n  if (c0 + lane >= r.n) return;\n");
+    if (vlds) o("  __shared__ %s vsh[%d * 64];\n", VT, ns);
     o("  body((const %s *)r.T + c0, (const %s *)r.P + c0, (const %s *)r.Y + c0, r.ldY, "
-      "(%s *)r.om + c0, r.ldO, lane, SP, RX, err);\n}\n",
+      "(%s *)r.om + c0, r.ldO, lane, SP, RX, err%s);\n}\n",
+      IO, IO, IO, IO, vlds ? ", vsh" : "");
+    prog.src = std::move(o.s);
+    return prog;
+}
+
+// ---------------------------------------------------------------------------
+// tiled form
+
+namespace {
+
+// Reactions split over the waves of a tile: each reaction goes to one of the
+// waves whose estimated work is within a small slack of the least loaded,
+// preferring the wave that already touches most of its species (fewer
+// accumulators to reduce afterwards); then each wave's list is ordered so
+// that consecutive reactions share species.
+std::vector<std::vector<int>> split_reactions(const JitMech &m,
+                                              const std::vector<std::vector<int>> &rs, int W)
+{
+    const int nr = m.nr;
+    std::vector<double> cost(nr);
+    double total = 0.0;
+    for (int j = 0; j < nr; ++j) {
+        cost[j] = 14.0 + 2.0 * (m.aux[j].nf + m.aux[j].nr) + 2.0 * rs[j].size();
+        total += cost[j];
+    }
+    std::vector<double> load(W, 0.0);
+    std::vector<std::vector<char>> touch(W, std::vector<char>(m.ns, 0));
+    std::vector<std::vector<int>> part(W);
+    const double slack = 2.0 * total / nr;
+    for (int j = 0; j < nr; ++j) {
+        const double lmin = *std::min_element(load.begin(), load.end());
+        int best = -1, bov = -1;
+        for (int w = 0; w < W; ++w) {
+            if (load[w] > lmin + slack) continue;
+            int ov = 0;
+            for (int k : rs[j]) ov += touch[w][k];
+            if (ov > bov || (ov == bov && load[w] < load[best])) {
+                best = w;
+                bov = ov;
+            }
+        }
+        part[best].push_back(j);
+        load[best] += cost[j];
+        for (int k : rs[j]) touch[best][k] = 1;
+    }
+    // chain within each wave: next = the remaining reaction sharing most
+    // species with the previous one (ties: list order)
+    for (auto &pl : part) {
+        std::vector<int> out;
+        std::vector<char> used(pl.size(), 0);
+        int prev = -1;
+        for (size_t step = 0; step < pl.size(); ++step) {
+            int bi = -1, bs = -1;
+            for (size_t i = 0; i < pl.size(); ++i) {
+                if (used[i]) continue;
+                int sh = 0;
+                if (prev >= 0)
+                    for (int k : rs[pl[i]])
+                        sh += std::find(rs[prev].begin(), rs[prev].end(), k) != rs[prev].end();
+                if (sh > bs) {
+                    bs = sh;
+                    bi = (int)i;
+                }
+            }
+            used[bi] = 1;
+            prev = pl[bi];
+            out.push_back(prev);
+        }
+        pl = out;
+    }
+    return part;
+}
+
+}  // namespace
+
+JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
+{
+    int group = 4;
+    if (const char *g = std::getenv("AK_JIT_GROUP")) group = std::max(1, std::atoi(g));
+    const bool ahead = !std::getenv("AK_JIT_PREFETCH") || std::atoi(std::getenv("AK_JIT_PREFETCH"));
+    const int ns = m.ns, nr = m.nr;
+    const char *IO = f64 ? "double" : "float";
+    const char *AC = f64 ? "double" : "float";   // omega accumulator type
+    JitProgram prog;
+    prog.threads = 64 * W;
+    const Common cm = common_setup(m, f64, prog);
+    const std::vector<int> &h = cm.h;
+    const std::vector<double> &R = cm.R;
+    const std::vector<double> &lw = cm.lw;
+    const bool vfloat = cm.vfloat;
+    const char *VT = (f64 || !vfloat) ? "double" : "float";
+
+    const std::vector<std::vector<int>> rs = reaction_species(m);
+    const std::vector<std::vector<int>> part = split_reactions(m, rs, W);
+    // species owned by each wave (loads, the species layer, the stores)
+    std::vector<std::vector<int>> own(W);
+    for (int k = 0; k < ns; ++k) own[k % W].push_back(k);
+    const int maxown = (ns + W - 1) / W;
+    // the first wave (in the reduction order 0..W-1) that touches species k
+    std::vector<int> first_w(ns, -1);
+    for (int w = 0; w < W; ++w)
+        for (int j : part[w])
+            for (int k : rs[j])
+                if (first_w[k] < 0 || first_w[k] > w) first_w[k] = w;
+    // per-reaction constants in the order of the generated code
+    std::vector<int> rxoff(W + 1, 0);
+    prog.rx.clear();
+    for (int w = 0; w < W; ++w) {
+        rxoff[w] = (int)prog.rx.size() / 3;
+        for (int j : part[w]) {
+            double shift = 0.0;
+            for (int i = 0; i < m.aux[j].nf; ++i)
+                shift += h[m.aux[j].sp[i]] + lw[m.aux[j].sp[i]];
+            prog.rx.push_back(m.rx[j].log2A - shift);
+            prog.rx.push_back(m.rx[j].beta);
+            prog.rx.push_back(m.rx[j].negEoR2);
+        }
+    }
+    rxoff[W] = nr;
+
+    Text o;
+    o("// generated by libannkin for a mechanism of %d species and %d reactions (%s path, "
+      "%d waves per 64-cell tile)\n", ns, nr, f64 ? "FP64" : "FP32", W);
+    o("typedef long long i64;\ntypedef unsigned long long u64;\n");
+    const std::vector<double> c = exp2_taylor(12);
+    if (f64) {
+        o("__device__ __forceinline__ double qrate(double X, double t) {\n");
+        o("  const double n = __builtin_rint(t), f = t - n;\n");
+        o("  double p = %s;\n", lit(c[12]).c_str());
+        for (int k = 11; k >= 0; --k) o("  p = __builtin_fma(p, f, %s);\n", lit(c[k]).c_str());
+        o("  return __builtin_ldexp(X * p, (int)n);\n}\n");
+    } else {
+        o("__device__ __forceinline__ float qrate(double X, double t) {\n");
+        o("  const double n = __builtin_rint(t);\n");
+        o("  const float p = __builtin_amdgcn_exp2f((float)(t - n));\n");
+        o("  return (float)__builtin_ldexp(X, (int)n) * p;\n}\n");
+    }
+    // LDS of a tile: a (double) and v per species and cell; after the sweep
+    // the a area holds the accumulated rates
+    o("__device__ __forceinline__ void tile(i64 c0, i64 n, const %s *__restrict__ Tg, "
+      "const %s *__restrict__ Pg, const %s *__restrict__ Yg, i64 ldY, %s *__restrict__ Og, "
+      "i64 ldO, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err, "
+      "double *LA, %s *LV, double *LS, %s *LC) {\n", IO, IO, IO, IO, VT, IO);
+    o("  const unsigned lane = threadIdx.x & 63u;\n");
+    o("  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));\n");
+    o("  const bool live = c0 + (i64)lane < n;\n");
+    o("  const i64 ci = live ? c0 + (i64)lane : n - 1;\n");
+    o("  const double T = (double)Tg[ci], P = (double)Pg[ci];\n");
+    o("  const double LNT = log(T), IT = 1.0 / T, T2 = T * T, T3 = T2 * T, T4 = T3 * T;\n");
+    o("  const double L2T = LNT * %s;\n", lit(kLog2e).c_str());
+    // phase 1: each wave loads its own species, partial mixture sums
+    o("  %s ys[%d];\n  double sgp = 0;\n  %s chk = 0;\n", IO, maxown, IO);
+    for (int w = 0; w < W; ++w) {
+        o("  %sif (wave == %d) {\n", w ? "else " : "", w);
+        for (size_t i = 0; i < own[w].size(); ++i)
+            o("    ys[%d] = (Yg + (i64)%d * ldY)[ci];\n", (int)i, own[w][i]);
+        for (size_t i = 0; i < own[w].size(); ++i)
+            o("    chk += ys[%d];\n    sgp += __builtin_fmax((double)ys[%d], 0.0) * SP[%d];\n",
+              (int)i, (int)i, 16 * own[w][i]);
+        o("  }\n");
+    }
+    o("  LS[threadIdx.x] = sgp;\n  LC[threadIdx.x] = chk;\n  __syncthreads();\n");
+    o("  double sg = LS[lane];\n  %s chkt = LC[lane];\n", IO);
+    for (int w = 1; w < W; ++w) o("  sg += LS[%d + lane];\n  chkt += LC[%d + lane];\n", 64 * w, 64 * w);
+    o("  const bool bad = !(T > 0.0) || !(P > 0.0) || !__builtin_isfinite(T) || "
+      "!__builtin_isfinite(P) || !__builtin_isfinite(chkt) || !(sg > 0.0) || "
+      "!__builtin_isfinite(sg)");
+    if (vfloat) o(" || !(T >= %s) || !(T <= %s)", lit(prog.T_lo).c_str(), lit(prog.T_hi).c_str());
+    o(";\n");
+    o("  const double rh = P / (%s * T * sg);\n", lit(kRu).c_str());
+    std::map<double, int> tmid;
+    for (int k = 0; k < ns; ++k)
+        if (!tmid.count(m.sp[k].T_mid)) {
+            const int id = (int)tmid.size();
+            tmid[m.sp[k].T_mid] = id;
+            o("  const bool hi%d = T >= %s;\n", id, lit(m.sp[k].T_mid).c_str());
+        }
+    // phase 2: the species layer of each wave's own species into LDS
+    const int pdeg = f64 ? 12 : 10;
+    const int top_even = pdeg - (pdeg & 1), top_odd = (pdeg & 1) ? pdeg : pdeg - 1;
+    for (int w = 0; w < W; ++w) {
+        o("  %sif (wave == %d) {\n", w ? "else " : "", w);
+        for (size_t i = 0; i < own[w].size(); ++i) {
+            const int k = own[w][i], b = 16 * k;
+            auto poly = [&](int off) {
+                char buf[512];
+                snprintf(buf, sizeof buf,
+                         "__builtin_fma(SP[%d], IT, __builtin_fma(SP[%d], T4, "
+                         "__builtin_fma(SP[%d], T3, __builtin_fma(SP[%d], T2, "
+                         "__builtin_fma(SP[%d], T, __builtin_fma(SP[%d], LNT, SP[%d]))))))",
+                         b + off + 5, b + off + 4, b + off + 3, b + off + 2, b + off + 1,
+                         b + off, b + off + 6);
+                return std::string(buf);
+            };
+            o("    {\n      double glo = %s, ghi = %s;\n", poly(2).c_str(), poly(9).c_str());
+            o("      asm(\"\" : \"+v\"(glo), \"+v\"(ghi));\n");
+            o("      const double g = hi%d ? ghi : glo;\n", tmid[m.sp[k].T_mid]);
+            o("      const double nn = __builtin_rint(g), f = g - nn, f2 = f * f;\n");
+            o("      double E = %s;\n", lit(c[top_even]).c_str());
+            for (int q = top_even - 2; q >= 0; q -= 2)
+                o("      E = __builtin_fma(E, f2, %s);\n", lit(c[q]).c_str());
+            o("      double O = %s;\n", lit(c[top_odd]).c_str());
+            for (int q = top_odd - 2; q >= 1; q -= 2)
+                o("      O = __builtin_fma(O, f2, %s);\n", lit(c[q]).c_str());
+            o("      O *= f;\n      const int ni = (int)nn;\n");
+            o("      LA[%d + lane] = rh * __builtin_fmax((double)ys[%d], 0.0) * "
+              "__builtin_ldexp(E + O, ni);\n", 64 * k, (int)i);
+            if (f64 || !vfloat) o("      LV[%d + lane] = __builtin_ldexp(E - O, -ni);\n", 64 * k);
+            else o("      LV[%d + lane] = (float)__builtin_ldexp(E - O, %d - ni);\n", 64 * k, h[k]);
+            o("    }\n");
+        }
+        o("  }\n");
+    }
+    o("  __syncthreads();\n");
+    // phase 3: each wave sweeps its reactions, rates accumulated in registers
+    for (int k = 0; k < ns; ++k) o("  %s w%d = 0;\n", AC, k);
+    for (int w = 0; w < W; ++w) {
+        const std::vector<int> &pl = part[w];
+        o("  %sif (wave == %d) {\n", w ? "else " : "", w);
+        o("    const double *rxp = RX + %d;\n    unsigned li = lane;\n", 3 * rxoff[w]);
+        const int cnt = (int)pl.size();
+        const int ngroups = (cnt + group - 1) / group;
+        auto load_group = [&](int g) {
+            for (int p = g * group; p < std::min(cnt, (g + 1) * group); ++p)
+                o("    const double kA%d = rxp[%d], kB%d = rxp[%d], kE%d = rxp[%d];\n", p, 3 * p, p,
+                  3 * p + 1, p, 3 * p + 2);
+        };
+        if (ahead) load_group(0);
+        for (int p = 0; p < cnt; ++p) {
+            const int j = pl[p];
+            const RxnAux &x = m.aux[j];
+            const int nf = x.nf, np = x.nr;
+            if (p % group == 0) {
+                if (p > 0)
+                    o("    asm volatile(\"\" : \"+s\"(rxp), \"+v\"(li) : \"v\"(q%d));\n", p - 1);
+                if (!ahead) load_group(p / group);
+                else if (p / group + 1 < ngroups) load_group(p / group + 1);
+            }
+            auto A = [&](int k) { return "LA[" + std::to_string(64 * k) + " + li]"; };
+            auto V = [&](int k) { return "LV[" + std::to_string(64 * k) + " + li]"; };
+            std::string Vr;
+            if (f64 || !vfloat) {
+                for (int i = 0; i < nf; ++i) Vr += (i ? "*" : "") + V(x.sp[i]);
+            } else {
+                double acc = 0.0;
+                std::string grp;
+                for (int i = 0; i < nf; ++i) {
+                    const int k = x.sp[i];
+                    if (!grp.empty() && acc + R[k] > 120.0) {
+                        Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
+                        grp.clear();
+                        acc = 0.0;
+                    }
+                    grp += (grp.empty() ? "" : "*") + V(k);
+                    acc += R[k];
+                }
+                Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
+            }
+            std::string Ar, Ap;
+            for (int i = 0; i < nf; ++i) Ar += (i ? "*" : "") + A(x.sp[i]);
+            for (int i = 0; i < np; ++i) Ap += (i ? "*" : "") + A(x.sp[nf + i]);
+            o("    %s q%d;\n    {\n      const double t = __builtin_fma(kB%d, L2T, "
+              "__builtin_fma(kE%d, IT, kA%d));\n", AC, p, p, p, p);
+            if (x.rev)
+                o("      q%d = qrate((%s) * ((%s) - (%s)), t);\n", p, Vr.c_str(), Ar.c_str(),
+                  Ap.c_str());
+            else
+                o("      q%d = qrate((%s) * (%s), t);\n", p, Vr.c_str(), Ar.c_str());
+            o("      const %s q = q%d;\n", AC, p);
+            for (int k : rs[j]) {
+                int nu = 0;
+                for (int i = 0; i < nf + np; ++i)
+                    if (x.sp[i] == k) nu += i < nf ? -1 : 1;
+                if (nu == 1) o("      w%d += q;\n", k);
+                else if (nu == -1) o("      w%d -= q;\n", k);
+                else if (nu != 0)
+                    o("      w%d = %s((%s)%d, q, w%d);\n", k,
+                      f64 ? "__builtin_fma" : "__builtin_fmaf", AC, nu, k);
+            }
+            o("    }\n");
+            if ((p + 1) % group == 0 || p + 1 == cnt) o("    __builtin_amdgcn_sched_barrier(0);\n");
+        }
+        o("  }\n");
+    }
+    o("  __syncthreads();\n");
+    // phase 4: the waves' rates added in wave order into the a area
+    o("  %s *LW = (%s *)LA;\n", AC, AC);
+    for (int w = 0; w < W; ++w) {
+        o("  if (wave == %d) {\n", w);
+        std::vector<char> t(ns, 0);
+        for (int j : part[w])
+            for (int k : rs[j]) t[k] = 1;
+        for (int k = 0; k < ns; ++k)
+            if (t[k]) o("    LW[%d + lane] %s w%d;\n", 64 * k, first_w[k] == w ? "=" : "+=", k);
+        o("  }\n  __syncthreads();\n");
+    }
+    // phase 5: each wave stores its own species
+    o("  if (live) {\n");
+    for (int w = 0; w < W; ++w) {
+        o("    %sif (wave == %d) {\n", w ? "else " : "", w);
+        for (int k : own[w])
+            o("      Og[(i64)%d * ldO + c0 + lane] = bad ? (%s)__builtin_nan(\"\") : (%s)%s;\n", k,
+              IO, IO, first_w[k] >= 0 ? ("LW[" + std::to_string(64 * k) + " + lane]").c_str()
+                                      : "0");
+        o("    }\n");
+    }
+    o("    if (wave == 0 && bad) atomicAdd(err, 1ull);\n  }\n}\n");
+
+    const int wpe = f64 ? 2 : 3;
+    o("struct BD { const void *T, *P, *Y; void *om; i64 ldY, ldO, n, block_begin; };\n");
+    o("#define AK_TILE_LDS __shared__ double LA[%d]; __shared__ %s LV[%d]; "
+      "__shared__ double LS[%d]; __shared__ %s LC[%d];\n", 64 * ns, VT, 64 * ns, 64 * W, IO,
+      64 * W);
+    o("extern \"C\" __global__ __launch_bounds__(%d) __attribute__((amdgpu_waves_per_eu(%d))) "
+      "void ak_src(const %s *__restrict__ T, const %s *__restrict__ P, "
+      "const %s *__restrict__ Y, i64 ldY, i64 n, %s *__restrict__ om, i64 ldO, "
+      "const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n",
+      64 * W, wpe, IO, IO, IO, IO);
+    o("  AK_TILE_LDS\n  tile((i64)blockIdx.x * 64, n, T, P, Y, ldY, om, ldO, SP, RX, err, "
+      "LA, LV, LS, LC);\n}\n");
+    o("extern \"C\" __global__ __launch_bounds__(%d) __attribute__((amdgpu_waves_per_eu(%d))) "
+      "void ak_src_batch(const BD *__restrict__ d, int nreq, const double *__restrict__ SP, "
+      "const double *__restrict__ RX, u64 *err) {\n", 64 * W, wpe);
+    o("  AK_TILE_LDS\n  const i64 b = blockIdx.x;\n  int lo = 0, hi = nreq - 1;\n");
+    o("  while (lo < hi) { const int mid = (lo + hi + 1) >> 1; "
+      "if (d[mid].block_begin <= b) lo = mid; else hi = mid - 1; }\n");
+    o("  const BD r = d[lo];\n");
+    o("  tile((b - r.block_begin) * 64, r.n, (const %s *)r.T, (const %s *)r.P, "
+      "(const %s *)r.Y, r.ldY, (%s *)r.om, r.ldO, SP, RX, err, LA, LV, LS, LC);\n}\n",
       IO, IO, IO, IO);
     prog.src = std::move(o.s);
     return prog;
+}
+
+JitProgram jit_generate(const JitMech &m, bool f64)
+{
+    // small mechanisms: the whole per-cell state in registers; larger ones:
+    // the tiled form
+    const char *mode = std::getenv("AK_JIT_MODE");
+    bool lane = m.ns <= kLaneFormMaxSpecies;
+    if (mode && std::strcmp(mode, "lane") == 0) lane = true;
+    if (mode && std::strcmp(mode, "tile") == 0) lane = false;
+    if (lane) return jit_program(m, f64);
+    int waves = kTileWaves;
+    if (const char *w = std::getenv("AK_JIT_WAVES")) waves = std::max(1, std::min(16, std::atoi(w)));
+    return jit_program_tile(m, f64, waves);
 }
 
 // ---------------------------------------------------------------------------
@@ -598,6 +988,7 @@ int jit_load(const std::vector<char> &code, JitKernels &out)
         return hip_error(e, "finding the mechanism's kernels");
     }
     out.block = 64;
+    out.threads = 64;
     return AK_OK;
 }
 
@@ -618,7 +1009,7 @@ hipError_t jit_launch(const JitKernels &k, const void *T, const void *P, const v
     const double *SP = k.sp, *RX = k.rx;
     void *args[] = {(void *)&T, (void *)&P,  (void *)&Y,  (void *)&ldY, (void *)&n,
                     (void *)&om, (void *)&ldO, (void *)&SP, (void *)&RX, (void *)&err};
-    return hipModuleLaunchKernel(k.src, (unsigned)blocks, 1, 1, k.block, 1, 1, 0, st, args,
+    return hipModuleLaunchKernel(k.src, (unsigned)blocks, 1, 1, k.threads, 1, 1, 0, st, args,
                                  nullptr);
 }
 
@@ -629,7 +1020,7 @@ hipError_t jit_batch_launch(const JitKernels &k, const JitBatchDesc *d_desc, int
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     const double *SP = k.sp, *RX = k.rx;
     void *args[] = {(void *)&d_desc, (void *)&nreq, (void *)&SP, (void *)&RX, (void *)&err};
-    return hipModuleLaunchKernel(k.batch, (unsigned)blocks, 1, 1, k.block, 1, 1, 0, st, args,
+    return hipModuleLaunchKernel(k.batch, (unsigned)blocks, 1, 1, k.threads, 1, 1, 0, st, args,
                                  nullptr);
 }
 

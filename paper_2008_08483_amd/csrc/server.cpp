@@ -31,6 +31,8 @@ struct GpuExec {
         std::vector<hipEvent_t> ev;      // per request of the batch: its copy-out done
         BatchDesc *d_desc[2] = {nullptr, nullptr};
         BatchDesc *h_desc[2] = {nullptr, nullptr};
+        JitBatchDesc *d_jdesc = nullptr;   // requests of mechanism-compiled kernels
+        JitBatchDesc *h_jdesc = nullptr;
         int nlaunch = 0;
         int rc = 0;
         bool busy = false;
@@ -68,6 +70,12 @@ struct GpuExec {
                     return set_error(AK_ENOMEM, "ak_server_create: descriptor tables: %s",
                                      hipGetErrorString(e));
             }
+            if ((e = hipMalloc((void **)&s.d_jdesc, sizeof(JitBatchDesc) * max_req)) !=
+                    hipSuccess ||
+                (e = hipHostMalloc((void **)&s.h_jdesc, sizeof(JitBatchDesc) * max_req,
+                                   hipHostMallocDefault)) != hipSuccess)
+                return set_error(AK_ENOMEM, "ak_server_create: descriptor tables: %s",
+                                 hipGetErrorString(e));
         }
         return AK_OK;
     }
@@ -81,6 +89,8 @@ struct GpuExec {
                 if (s.d_desc[p]) (void)hipFree(s.d_desc[p]);
                 if (s.h_desc[p]) (void)hipHostFree(s.h_desc[p]);
             }
+            if (s.d_jdesc) (void)hipFree(s.d_jdesc);
+            if (s.h_jdesc) (void)hipHostFree(s.h_jdesc);
             for (hipEvent_t ev : s.ev)
                 if (ev) (void)hipEventDestroy(ev);
             if (s.st) (void)hipStreamDestroy(s.st);
@@ -128,6 +138,55 @@ struct GpuExec {
             ok(hipMemcpy2DAsync(dY, es * r->n, r->Y, es * r->ldY, es * r->n, r->ns,
                                 hipMemcpyHostToDevice, s->st));
         }
+        // Requests whose mechanism has compiled kernels for their precision:
+        // one launch per (mechanism, precision), with the same kernel that
+        // ak_eval_source runs, so that a request's result does not depend on
+        // its batch.  All other requests: one fused launch of the table-driven
+        // kernel per precision.
+        std::vector<std::pair<const JitKernels *, std::vector<const Request *>>> groups;
+        for (const Request *r : reqs) {
+            const JitKernels *jk = &((const ak_mechanism *)r->mech)->jit[r->prec];
+            if (!jk->src) continue;
+            size_t gi = 0;
+            while (gi < groups.size() && groups[gi].first != jk) ++gi;
+            if (gi == groups.size()) groups.push_back({jk, {}});
+            groups[gi].second.push_back(r);
+        }
+        if (!groups.empty()) {
+            // descriptor table: the groups one after another, block offsets
+            // counted within each group
+            std::vector<int> first(groups.size() + 1, 0);
+            std::vector<int64_t> gblocks(groups.size(), 0);
+            int nj = 0;
+            for (size_t gi = 0; gi < groups.size(); ++gi) {
+                first[gi] = nj;
+                const int block = groups[gi].first->block;
+                for (const Request *r : groups[gi].second) {
+                    const size_t es = elem_size(r->prec);
+                    unsigned char *b = arena + r->arena_off;
+                    JitBatchDesc &d = s->h_jdesc[nj++];
+                    d.T = b;
+                    d.P = b + Arena::round(es * r->n);
+                    d.Y = b + 2 * Arena::round(es * r->n);
+                    d.om = b + 2 * Arena::round(es * r->n) + Arena::round(es * r->n * r->ns);
+                    d.ldY = d.ldO = d.n = r->n;
+                    d.block_begin = gblocks[gi];
+                    gblocks[gi] += (r->n + block - 1) / block;
+                }
+            }
+            first[groups.size()] = nj;
+            step = "descriptor table";
+            ok(hipMemcpyAsync(s->d_jdesc, s->h_jdesc, sizeof(JitBatchDesc) * nj,
+                              hipMemcpyHostToDevice, s->st));
+            step = "compiled-kernel launch";
+            for (size_t gi = 0; gi < groups.size(); ++gi) {
+                const ak_mechanism *m = (const ak_mechanism *)groups[gi].second[0]->mech;
+                ok(jit_batch_launch(*groups[gi].first, s->d_jdesc + first[gi],
+                                    first[gi + 1] - first[gi], gblocks[gi], m->view.err,
+                                    s->st));
+                s->nlaunch++;
+            }
+        }
         for (int p = 0; p < 2; ++p) {
             const int prec = p == 0 ? AK_FP32 : AK_FP64;
             int nd = 0;
@@ -137,6 +196,7 @@ struct GpuExec {
             for (Request *r : reqs) {
                 if (r->prec != prec) continue;
                 const ak_mechanism *m = (const ak_mechanism *)r->mech;
+                if (m->jit[r->prec].src) continue;
                 const size_t es = elem_size(r->prec);
                 unsigned char *b = arena + r->arena_off;
                 BatchDesc &d = s->h_desc[p][nd++];

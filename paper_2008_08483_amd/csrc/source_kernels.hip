@@ -20,6 +20,7 @@
 #include <stdint.h>
 
 #include "ak_device.h"
+#include "ak_internal.h"
 #include "ak_math.h"
 
 #ifndef AK_SOURCE_WAVES
@@ -424,8 +425,7 @@ static hipError_t launch_source(const MechView &m, const void *T, const void *P,
 {
     const size_t lds = (size_t)m.ns * species_stride(m.tile);
     auto fn = source_kernel<IO, F64, WAVES, KMAX>;
-    hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = allow_dynamic_lds((const void *)fn);
     if (e != hipSuccess) return e;
     const int64_t blocks = (n + m.tile - 1) / m.tile;
     if (blocks <= 0) return hipSuccess;
@@ -465,8 +465,7 @@ static hipError_t launch_batch(const BatchDesc *d_desc, int nreq, int64_t blocks
                                hipStream_t st)
 {
     auto fn = source_batch_kernel<IO, F64, AK_SOURCE_WAVES, KMAX>;
-    hipError_t e = hipFuncSetAttribute((const void *)fn,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = allow_dynamic_lds((const void *)fn);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * AK_SOURCE_WAVES), lds, st, d_desc,
                        nreq);
