@@ -400,7 +400,10 @@ JitProgram jit_program(const JitMech &m, bool f64)
               3 * p + 1, p, 3 * p + 2);
     };
     const bool ahead = std::getenv("AK_JIT_PREFETCH") && std::atoi(std::getenv("AK_JIT_PREFETCH"));
-    o("  const double *rxp = RX, *spp = SP;\n");
+    o("  const __attribute__((address_space(4))) double *rxp = "
+      "(const __attribute__((address_space(4))) double *)RX;\n"
+      "  const __attribute__((address_space(4))) double *spp = "
+      "(const __attribute__((address_space(4))) double *)SP;\n");
     if (yreload) o("  const %s *ypp = Yb;\n", IO);
     if (ahead) load_group(0);
     for (int p = 0; p < nr; ++p) {
@@ -441,7 +444,7 @@ JitProgram jit_program(const JitMech &m, bool f64)
         std::string Ar, Ap;
         for (int i = 0; i < nf; ++i) Ar += (i ? "*a" : "a") + std::to_string(x.sp[i]);
         for (int i = 0; i < np; ++i) Ap += (i ? "*a" : "a") + std::to_string(x.sp[nf + i]);
-        o("  %s q%d;\n  {\n    const double t = __builtin_fma(kB%d, L2T, __builtin_fma(kE%d, IT, kA%d));\n",
+        o("  %s q%d;\n  {\n    const double t = __builtin_fma(kB%d, L2T, kE%d * IT) + kA%d;\n",
           AC, p, p, p, p);
         if (x.rev)
             o("    q%d = qrate((%s) * ((%s) - (%s)), t);\n", p, Vr.c_str(), Ar.c_str(),
@@ -570,6 +573,13 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
     int group = 4;
     if (const char *g = std::getenv("AK_JIT_GROUP")) group = std::max(1, std::atoi(g));
     const bool ahead = !std::getenv("AK_JIT_PREFETCH") || std::atoi(std::getenv("AK_JIT_PREFETCH"));
+    auto knob = [](const char *name, int def) {
+        const char *v = std::getenv(name);
+        return v ? std::atoi(v) : def;
+    };
+    const bool lsalias = knob("AK_JIT_LSALIAS", 1) != 0;
+    const bool tree = knob("AK_JIT_TREE", 1) != 0;
+    const int wpe = f64 ? knob("AK_JIT_WPE64", 3) : knob("AK_JIT_WPE", 4);
     const int ns = m.ns, nr = m.nr;
     const char *IO = f64 ? "double" : "float";
     const char *AC = f64 ? "double" : "float";   // omega accumulator type
@@ -660,6 +670,7 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
     if (vfloat) o(" || !(T >= %s) || !(T <= %s)", lit(prog.T_lo).c_str(), lit(prog.T_hi).c_str());
     o(";\n");
     o("  const double rh = P / (%s * T * sg);\n", lit(kRu).c_str());
+    if (lsalias) o("  __syncthreads();\n");
     std::map<double, int> tmid;
     for (int k = 0; k < ns; ++k)
         if (!tmid.count(m.sp[k].T_mid)) {
@@ -668,7 +679,9 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
             o("  const bool hi%d = T >= %s;\n", id, lit(m.sp[k].T_mid).c_str());
         }
     // phase 2: the species layer of each wave's own species into LDS
-    const int pdeg = f64 ? 12 : 10;
+    // 2^f, |f| <= 1/2: degree 12 (below one ulp) in the FP64 path; degree 8
+    // (relative error below 3e-10) in the FP32 path
+    const int pdeg = f64 ? 12 : knob("AK_JIT_EXPDEG", 8);
     const int top_even = pdeg - (pdeg & 1), top_odd = (pdeg & 1) ? pdeg : pdeg - 1;
     for (int w = 0; w < W; ++w) {
         o("  %sif (wave == %d) {\n", w ? "else " : "", w);
@@ -709,9 +722,14 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
     for (int w = 0; w < W; ++w) {
         const std::vector<int> &pl = part[w];
         o("  %sif (wave == %d) {\n", w ? "else " : "", w);
-        o("    const double *rxp = RX + %d;\n    unsigned li = lane;\n", 3 * rxoff[w]);
+        // the constants are read through a constant-address-space pointer, so
+        // that the loads stay scalar after the pointer passes the asm fences
+        o("    const __attribute__((address_space(4))) double *rxp = "
+          "(const __attribute__((address_space(4))) double *)(RX + %d);\n"
+          "    unsigned li = lane;\n", 3 * rxoff[w]);
         const int cnt = (int)pl.size();
         const int ngroups = (cnt + group - 1) / group;
+        std::vector<char> seen(ns, 0);
         auto load_group = [&](int g) {
             for (int p = g * group; p < std::min(cnt, (g + 1) * group); ++p)
                 o("    const double kA%d = rxp[%d], kB%d = rxp[%d], kE%d = rxp[%d];\n", p, 3 * p, p,
@@ -751,8 +769,9 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
             std::string Ar, Ap;
             for (int i = 0; i < nf; ++i) Ar += (i ? "*" : "") + A(x.sp[i]);
             for (int i = 0; i < np; ++i) Ap += (i ? "*" : "") + A(x.sp[nf + i]);
-            o("    %s q%d;\n    {\n      const double t = __builtin_fma(kB%d, L2T, "
-              "__builtin_fma(kE%d, IT, kA%d));\n", AC, p, p, p, p);
+            // one scalar operand per instruction (the constants sit in SGPRs)
+            o("    %s q%d;\n    {\n      const double t = __builtin_fma(kB%d, L2T, kE%d * IT) "
+              "+ kA%d;\n", AC, p, p, p, p);
             if (x.rev)
                 o("      q%d = qrate((%s) * ((%s) - (%s)), t);\n", p, Vr.c_str(), Ar.c_str(),
                   Ap.c_str());
@@ -763,9 +782,16 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
                 int nu = 0;
                 for (int i = 0; i < nf + np; ++i)
                     if (x.sp[i] == k) nu += i < nf ? -1 : 1;
-                if (nu == 1) o("      w%d += q;\n", k);
+                if (nu == 0) continue;
+                if (!seen[k]) {
+                    // first term of this wave's sum for species k
+                    if (nu == 1) o("      w%d = q;\n", k);
+                    else if (nu == -1) o("      w%d = -q;\n", k);
+                    else o("      w%d = (%s)%d * q;\n", k, AC, nu);
+                    seen[k] = 1;
+                } else if (nu == 1) o("      w%d += q;\n", k);
                 else if (nu == -1) o("      w%d -= q;\n", k);
-                else if (nu != 0)
+                else
                     o("      w%d = %s((%s)%d, q, w%d);\n", k,
                       f64 ? "__builtin_fma" : "__builtin_fmaf", AC, nu, k);
             }
@@ -777,32 +803,80 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
     o("  __syncthreads();\n");
     // phase 4: the waves' rates added in wave order into the a area
     o("  %s *LW = (%s *)LA;\n", AC, AC);
-    for (int w = 0; w < W; ++w) {
-        o("  if (wave == %d) {\n", w);
-        std::vector<char> t(ns, 0);
+    std::vector<std::vector<char>> tw(W, std::vector<char>(ns, 0));
+    for (int w = 0; w < W; ++w)
         for (int j : part[w])
-            for (int k : rs[j]) t[k] = 1;
+            for (int k : rs[j]) tw[w][k] = 1;
+    // fixed summation order per species: ((w0 + w1) + (w2 + w3)) for the tree,
+    // (((w0 + w1) + w2) + w3) for the chain; untouched terms are left out
+    std::vector<std::string> omega_expr(ns);
+    if (tree && W == 4) {
+        // two buffers: B0 (waves 0 + 1) at the start of the a area, B1 (waves
+        // 2 + 3) after it in the FP32 path (floats take half of it) and in
+        // the v area in the FP64 path (v is double there)
+        const std::string lw1 = f64 ? "(double *)LV" : "LW + " + std::to_string(64 * ns);
+        o("  %s *LW1 = %s;\n", AC, lw1.c_str());
+        auto B = [&](int b, int k) {
+            return std::string(b ? "LW1[" : "LW[") + std::to_string(64 * k) + " + lane]";
+        };
+        for (int half = 0; half < 2; ++half) {
+            o("  if (wave == %d) {\n", 2 * half);
+            for (int k = 0; k < ns; ++k)
+                if (tw[2 * half][k]) o("    %s = w%d;\n", B(half, k).c_str(), k);
+            o("  }\n");
+        }
+        o("  __syncthreads();\n");
+        for (int half = 0; half < 2; ++half) {
+            o("  if (wave == %d) {\n", 2 * half + 1);
+            for (int k = 0; k < ns; ++k)
+                if (tw[2 * half + 1][k])
+                    o("    %s %s w%d;\n", B(half, k).c_str(), tw[2 * half][k] ? "+=" : "=", k);
+            o("  }\n");
+        }
+        o("  __syncthreads();\n");
+        for (int k = 0; k < ns; ++k) {
+            const bool h0 = tw[0][k] || tw[1][k], h1 = tw[2][k] || tw[3][k];
+            if (h0 && h1) omega_expr[k] = "(" + B(0, k) + " + " + B(1, k) + ")";
+            else if (h0) omega_expr[k] = B(0, k);
+            else if (h1) omega_expr[k] = B(1, k);
+            else omega_expr[k] = "0";
+        }
+    } else {
+        for (int w = 0; w < W; ++w) {
+            o("  if (wave == %d) {\n", w);
+            for (int k = 0; k < ns; ++k)
+                if (tw[w][k])
+                    o("    LW[%d + lane] %s w%d;\n", 64 * k, first_w[k] == w ? "=" : "+=", k);
+            o("  }\n  __syncthreads();\n");
+        }
         for (int k = 0; k < ns; ++k)
-            if (t[k]) o("    LW[%d + lane] %s w%d;\n", 64 * k, first_w[k] == w ? "=" : "+=", k);
-        o("  }\n  __syncthreads();\n");
+            omega_expr[k] = first_w[k] >= 0 ? "LW[" + std::to_string(64 * k) + " + lane]" : "0";
     }
     // phase 5: each wave stores its own species
     o("  if (live) {\n");
     for (int w = 0; w < W; ++w) {
         o("    %sif (wave == %d) {\n", w ? "else " : "", w);
         for (int k : own[w])
-            o("      Og[(i64)%d * ldO + c0 + lane] = bad ? (%s)__builtin_nan(\"\") : (%s)%s;\n", k,
-              IO, IO, first_w[k] >= 0 ? ("LW[" + std::to_string(64 * k) + " + lane]").c_str()
-                                      : "0");
+            o("      Og[(i64)%d * ldO + c0 + lane] = bad ? (%s)__builtin_nan(\"\") : (%s)(%s);\n",
+              k, IO, IO, omega_expr[k].c_str());
         o("    }\n");
     }
     o("    if (wave == 0 && bad) atomicAdd(err, 1ull);\n  }\n}\n");
 
-    const int wpe = f64 ? 2 : 3;
     o("struct BD { const void *T, *P, *Y; void *om; i64 ldY, ldO, n, block_begin; };\n");
-    o("#define AK_TILE_LDS __shared__ double LA[%d]; __shared__ %s LV[%d]; "
-      "__shared__ double LS[%d]; __shared__ %s LC[%d];\n", 64 * ns, VT, 64 * ns, 64 * W, IO,
-      64 * W);
+    if (lsalias) {
+        // the mixture-sum partials live in the v area until the species layer
+        // writes it (a barrier separates the two)
+        const size_t vbytes = (size_t)64 * ns * (f64 || !vfloat ? 8 : 4);
+        const size_t need = (size_t)64 * W * 8 + (size_t)64 * W * (f64 ? 8 : 4);
+        o("#define AK_TILE_LDS __shared__ double LA[%d]; __shared__ double LVD[%d]; "
+          "%s *LV = (%s *)LVD; double *LS = LVD; %s *LC = (%s *)(LVD + %d);\n", 64 * ns,
+          (int)((std::max(vbytes, need) + 7) / 8), VT, VT, IO, IO, 64 * W);
+    } else {
+        o("#define AK_TILE_LDS __shared__ double LA[%d]; __shared__ %s LV[%d]; "
+          "__shared__ double LS[%d]; __shared__ %s LC[%d];\n", 64 * ns, VT, 64 * ns, 64 * W, IO,
+          64 * W);
+    }
     o("extern \"C\" __global__ __launch_bounds__(%d) __attribute__((amdgpu_waves_per_eu(%d))) "
       "void ak_src(const %s *__restrict__ T, const %s *__restrict__ P, "
       "const %s *__restrict__ Y, i64 ldY, i64 n, %s *__restrict__ om, i64 ldO, "
@@ -834,7 +908,8 @@ JitProgram jit_generate(const JitMech &m, bool f64)
     if (mode && std::strcmp(mode, "tile") == 0) lane = false;
     if (lane) return jit_program(m, f64);
     int waves = kTileWaves;
-    if (const char *w = std::getenv("AK_JIT_WAVES")) waves = std::max(1, std::min(16, std::atoi(w)));
+    if (const char *w = std::getenv(f64 ? "AK_JIT_WAVES64" : "AK_JIT_WAVES"))
+        waves = std::max(1, std::min(16, std::atoi(w)));
     return jit_program_tile(m, f64, waves);
 }
 
