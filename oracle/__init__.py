@@ -52,6 +52,9 @@ class _Mech(C.Structure):
         ("ln_A", C.c_void_p), ("beta", C.c_void_p), ("Ea", C.c_void_p),
         ("nasa_low", C.c_void_p), ("nasa_high", C.c_void_p), ("T_mid", C.c_void_p),
         ("reversible", C.c_void_p),
+        ("rtype", C.c_void_p), ("eff", C.c_void_p),
+        ("low_ln_A", C.c_void_p), ("low_beta", C.c_void_p), ("low_Ea", C.c_void_p),
+        ("troe", C.c_void_p),
     ]
 
 
@@ -107,10 +110,24 @@ class OracleMechanism:
             "reversible": np.ascontiguousarray(mech.reversible, dtype=np.uint8),
         }
         assert self._keep["nu_f"].shape == (self.nr, self.ns)
+        # pressure-dependent reactions (optional attributes; None = absent)
+        opt = {"rtype": (np.uint8, (self.nr,)), "eff": (np.float64, (self.nr, self.ns)),
+               "low_ln_A": (np.float64, (self.nr,)), "low_beta": (np.float64, (self.nr,)),
+               "low_Ea": (np.float64, (self.nr,)), "troe": (np.float64, (self.nr, 4))}
+        for name, (dt, shape) in opt.items():
+            v = getattr(mech, name, None)
+            if v is not None:
+                v = np.ascontiguousarray(v, dtype=dt)
+                assert v.shape == shape, (name, v.shape)
+            self._keep[name] = v
         k = self._keep
-        self._c = _Mech(self.ns, self.nr, *(k[n].ctypes.data for n in (
+
+        def ptr(n):
+            return None if k[n] is None else k[n].ctypes.data
+
+        self._c = _Mech(self.ns, self.nr, *(ptr(n) for n in (
             "W", "nu_f", "nu_r", "ln_A", "beta", "Ea", "nasa_low", "nasa_high", "T_mid",
-            "reversible")))
+            "reversible", "rtype", "eff", "low_ln_A", "low_beta", "low_Ea", "troe")))
 
     @property
     def ptr(self):
@@ -212,6 +229,8 @@ def jacobian(mech, T, P, Y, precision: str = "f64", scales: bool = False, n_thre
     rc = getattr(_lib_handle(), f"ora_jacobian_scaled_{precision}")(
         m.ptr, n, T.ctypes.data, P.ctypes.data, Y.ctypes.data, n, J.ctypes.data,
         Ja.ctypes.data if scales else None, nv * nv, int(n_threads))
+    if rc == -2:
+        raise NotImplementedError("oracle Jacobian of third-body and falloff reactions")
     if rc:
         raise RuntimeError("oracle jacobian failed")
     return (J, Ja) if scales else J

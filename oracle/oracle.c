@@ -16,6 +16,7 @@
 #define LOG log
 #define POW pow
 #define FABS fabs
+#define LOG10 log10
 #include "oracle_impl.h"
 #undef REAL
 #undef SFX
@@ -23,6 +24,7 @@
 #undef LOG
 #undef POW
 #undef FABS
+#undef LOG10
 
 #define REAL long double
 #define SFX(x) x##_ld
@@ -30,4 +32,5 @@
 #define LOG logl
 #define POW powl
 #define FABS fabsl
+#define LOG10 log10l
 #include "oracle_impl.h"

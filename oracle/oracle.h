@@ -26,7 +26,15 @@
  *   W[ns] kg/kmol; nu_f, nu_r [nr][ns] (entry [j][k] = nu'_kj, nu''_kj);
  *   ln_A[nr] natural log of A in cgs units (cm^3/mol)^(order-1)/s;
  *   beta[nr]; Ea[nr] cal/mol; nasa_low, nasa_high [ns][7] a1..a7;
- *   T_mid[ns] K; reversible[nr] (NULL = all reversible). */
+ *   T_mid[ns] K; reversible[nr] (NULL = all reversible);
+ * pressure-dependent reactions (Sec. 2.4), all NULL for none:
+ *   rtype[nr] 0 elementary, 1 third body (+M), 2 falloff (Lindemann),
+ *     3 falloff (Troe); eff[nr][ns] third-body efficiencies (NULL = all 1);
+ *   for types 2 and 3 the arrays ln_A, beta, Ea give the high-pressure limit
+ *   and low_ln_A, low_beta, low_Ea the low-pressure limit k0 (A in cgs units
+ *   of one order more); troe[nr][4] = alpha, T3, T1, T2 (the usual T-triple-
+ *   star, T-star, T-double-star; T2 = 0: the third term is absent).  Third-body reactions carry A in cgs units of
+ *   order sum nu' + 1. */
 typedef struct {
     int ns, nr;
     const double *W;
@@ -34,7 +42,16 @@ typedef struct {
     const double *ln_A, *beta, *Ea;
     const double *nasa_low, *nasa_high, *T_mid;
     const uint8_t *reversible;
+    const uint8_t *rtype;
+    const double *eff;
+    const double *low_ln_A, *low_beta, *low_Ea;
+    const double *troe;
 } ora_mech;
+
+#define ORA_ELEMENTARY 0
+#define ORA_THIRD_BODY 1
+#define ORA_LINDEMANN 2
+#define ORA_TROE 3
 
 #define ORA_DECL(R, S)                                                                        \
     int ora_thermo_##S(const ora_mech *m, double T, R *h_RT, R *s_R, R *cp_R);                \

@@ -29,15 +29,54 @@ static void SFX(thermo1)(const ora_mech *m, int k, REAL T, REAL *h_RT, REAL *s_R
     if (dcp_R) *dcp_R = a2 + 2 * a3 * T + 3 * a4 * T2 + 4 * a5 * T3;
 }
 
-/* Arrhenius forward rate constant in SI-kmol units (Eq. 5).  The mechanism
- * carries A in cgs units, (cm^3/mol)^(n-1)/s, and Ea in cal/mol. */
-static REAL SFX(kf1)(const ora_mech *m, int j, REAL T)
+/* Arrhenius rate constant A T^beta exp(-E/(R T)) in SI-kmol units (Eq. 5),
+ * from A in cgs units of the given order, (cm^3/mol)^(order-1)/s, and E in
+ * cal/mol. */
+static REAL SFX(arrhenius)(double ln_A, double beta, double Ea, int order, REAL T)
+{
+    REAL A_si = EXP((REAL)ln_A) * POW((REAL)1e-3L, (REAL)(order - 1));
+    REAL E_R = (REAL)Ea * (REAL)ORA_CAL / (REAL)ORA_RU_MOL;
+    return A_si * POW(T, (REAL)beta) * EXP(-E_R / T);
+}
+
+static int SFX(rtype1)(const ora_mech *m, int j) { return m->rtype ? m->rtype[j] : 0; }
+
+/* Forward rate constant of reaction j (Eq. 5), with the pressure dependence
+ * of Sec. 2.4 for third-body and falloff reactions:
+ *   third body:  k_f = k [M], [M] = sum_k eff_kj C_k (the paper's M = C E);
+ *   falloff:     k_f = k_inf Pr/(1 + Pr) F, Pr = k_0 [M] / k_inf, with F = 1
+ *                (Lindemann) or the Troe broadening
+ *                log10 F = log10 Fc / (1 + ((log10 Pr + c)/(n - 0.14 (log10 Pr + c)))^2),
+ *                c = -0.4 - 0.67 log10 Fc, n = 0.75 - 1.27 log10 Fc,
+ *                Fc = (1 - alpha) exp(-T/T3) + alpha exp(-T/T1) + exp(-T2/T)
+ *                (Gilbert, Luther & Troe 1983; T3, T1, T2 are the usual T***,
+ *                T* and T**). */
+static REAL SFX(kf1)(const ora_mech *m, int j, REAL T, const REAL *C)
 {
     int order = 0;
     for (int k = 0; k < m->ns; ++k) order += m->nu_f[j * m->ns + k];
-    REAL A_si = EXP((REAL)m->ln_A[j]) * POW((REAL)1e-3L, (REAL)(order - 1));
-    REAL E_R = (REAL)m->Ea[j] * (REAL)ORA_CAL / (REAL)ORA_RU_MOL;
-    return A_si * POW(T, (REAL)m->beta[j]) * EXP(-E_R / T);
+    const int type = SFX(rtype1)(m, j);
+    if (type == ORA_ELEMENTARY)
+        return SFX(arrhenius)(m->ln_A[j], m->beta[j], m->Ea[j], order, T);
+    REAL M = 0;
+    for (int k = 0; k < m->ns; ++k) M += (m->eff ? (REAL)m->eff[j * m->ns + k] : 1) * C[k];
+    if (type == ORA_THIRD_BODY)
+        return SFX(arrhenius)(m->ln_A[j], m->beta[j], m->Ea[j], order + 1, T) * M;
+    REAL kinf = SFX(arrhenius)(m->ln_A[j], m->beta[j], m->Ea[j], order, T);
+    REAL k0 = SFX(arrhenius)(m->low_ln_A[j], m->low_beta[j], m->low_Ea[j], order + 1, T);
+    REAL Pr = k0 * M / kinf;
+    REAL F = 1;
+    if (type == ORA_TROE && Pr > 0) {
+        const double *tp = &m->troe[4 * j];
+        REAL Fc = (1 - (REAL)tp[0]) * EXP(-T / (REAL)tp[1]) + (REAL)tp[0] * EXP(-T / (REAL)tp[2]);
+        if (tp[3] != 0) Fc += EXP(-(REAL)tp[3] / T);
+        REAL lFc = LOG10(Fc);
+        REAL c = (REAL)-0.4L - (REAL)0.67L * lFc, nn = (REAL)0.75L - (REAL)1.27L * lFc;
+        REAL x = LOG10(Pr) + c;
+        REAL f1 = x / (nn - (REAL)0.14L * x);
+        F = POW((REAL)10, lFc / (1 + f1 * f1));
+    }
+    return kinf * (Pr / (1 + Pr)) * F;
 }
 
 /* Concentrations from the ideal-gas state: C_k = P/(Ru T) * (Y_k/W_k)/sum_l(Y_l/W_l),
@@ -72,7 +111,7 @@ static void SFX(reaction1)(const ora_mech *m, int j, REAL T, const REAL *C,
 {
     const int ns = m->ns;
     const int8_t *nf = &m->nu_f[j * ns], *nr = &m->nu_r[j * ns];
-    REAL k_f = SFX(kf1)(m, j, T);
+    REAL k_f = SFX(kf1)(m, j, T, C);
     REAL dn = 0, dS = 0, dH = 0;
     for (int k = 0; k < ns; ++k) {
         int nu = nr[k] - nf[k];
@@ -239,6 +278,9 @@ int SFX(ora_jacobian_scaled)(const ora_mech *m, int64_t n, const double *T, cons
 {
     const int ns = m->ns, nr = m->nr, nv = ns + 1;
     int err = 0;
+    /* the derivatives of [M] and of the falloff form are not implemented */
+    for (int j = 0; j < nr; ++j)
+        if (SFX(rtype1)(m, j) != ORA_ELEMENTARY) return -2;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #pragma omp parallel

@@ -61,6 +61,13 @@ class Mechanism:
     T_mid: np.ndarray        # [NS] float64, K
     reversible: np.ndarray   # [NR] uint8
     species: list = field(default_factory=list)
+    # pressure-dependent reactions (Sec. 2.4); None = all elementary
+    rtype: np.ndarray | None = None      # [NR] uint8: 0 elementary, 1 third body, 2 Lindemann, 3 Troe
+    eff: np.ndarray | None = None        # [NR, NS] third-body efficiencies
+    low_ln_A: np.ndarray | None = None   # [NR] low-pressure limit (falloff), cgs of order + 1
+    low_beta: np.ndarray | None = None
+    low_Ea: np.ndarray | None = None
+    troe: np.ndarray | None = None       # [NR, 4] alpha, T***, T*, T** (0: absent)
 
     @property
     def n_species(self) -> int:
@@ -233,6 +240,57 @@ def _try_reactions(ns, nr, comp, rng):
     if not np.all((nu_f + nu_r).sum(axis=0) > 0):
         return None
     return nu_f, nu_r
+
+
+def with_pressure_dependence(mech: Mechanism, frac: float = 0.2, seed: int = 11,
+                             types=(0.5, 0.2, 0.3)) -> Mechanism:
+    """A copy of ``mech`` in which a fraction ``frac`` of the reactions are
+    pressure dependent (Sec. 2.4): third-body (+M), Lindemann falloff or Troe
+    falloff, in the proportions ``types``.  Reactions with one molecule on
+    one side and two on the other (dissociation / recombination, the usual
+    form of such reactions) are taken first.  Efficiencies are 1 except for
+    about one species in five (0, 0.5, 2 or 5).  A third-body reaction's
+    ln A, one order more, gets U[5, 10] added (termolecular constants are
+    larger in cgs units); for falloff the drawn
+    parameters are the high-pressure limit and the low-pressure limit gets
+    ln A0 = ln A + U[8, 14] (one order more, so that the reduced pressure
+    k0 [M] / k_inf spans the falloff region at 1-20 atm), beta0 = beta +
+    U[-1, 0], E0 = E U[0.5, 1]; Troe: alpha ~ U[0.1, 0.9], T3 ~ U[50, 500] K,
+    T1 ~ U[1000, 5000] K, T2 ~ U[2000, 8000] K for half of them (else
+    absent)."""
+    rng = np.random.default_rng(seed)
+    nr, ns = mech.nu_f.shape
+    nf = mech.nu_f.sum(axis=1)
+    nb = mech.nu_r.sum(axis=1)
+    pref = np.nonzero(((nf == 1) & (nb == 2)) | ((nf == 2) & (nb == 1)))[0]
+    rest = np.setdiff1d(np.arange(nr), pref)
+    cand = np.concatenate([rng.permutation(pref), rng.permutation(rest)])
+    chosen = np.sort(cand[:int(round(frac * nr))])
+    rtype = np.zeros(nr, np.uint8)
+    kinds = rng.choice(3, size=chosen.size, p=np.asarray(types) / np.sum(types)) + 1
+    rtype[chosen] = kinds
+    eff = np.ones((nr, ns))
+    for j in chosen:
+        special = rng.random(ns) < 0.2
+        eff[j, special] = rng.choice([0.0, 0.5, 2.0, 5.0], size=int(special.sum()))
+    low_ln_A = mech.ln_A + rng.uniform(8.0, 14.0, nr)
+    low_beta = mech.beta + rng.uniform(-1.0, 0.0, nr)
+    low_Ea = mech.Ea * rng.uniform(0.5, 1.0, nr)
+    troe = np.zeros((nr, 4))
+    troe[:, 0] = rng.uniform(0.1, 0.9, nr)
+    troe[:, 1] = rng.uniform(50.0, 500.0, nr)
+    troe[:, 2] = rng.uniform(1000.0, 5000.0, nr)
+    troe[:, 3] = np.where(rng.random(nr) < 0.5, rng.uniform(2000.0, 8000.0, nr), 0.0)
+    fall = rtype >= 2
+    ln_A = np.where(rtype == 1, mech.ln_A + rng.uniform(5.0, 10.0, nr), mech.ln_A)
+    return Mechanism(
+        name=mech.name + f"_pdep{int(round(100 * frac))}", W=mech.W, atoms=mech.atoms,
+        nu_f=mech.nu_f, nu_r=mech.nu_r, ln_A=ln_A, beta=mech.beta, Ea=mech.Ea,
+        nasa_low=mech.nasa_low, nasa_high=mech.nasa_high, T_mid=mech.T_mid,
+        reversible=mech.reversible, species=list(mech.species), rtype=rtype,
+        eff=np.where(rtype[:, None] > 0, eff, 1.0),
+        low_ln_A=np.where(fall, low_ln_A, 0.0), low_beta=np.where(fall, low_beta, 0.0),
+        low_Ea=np.where(fall, low_Ea, 0.0), troe=np.where((rtype == 3)[:, None], troe, 0.0))
 
 
 # ----------------------------------------------------------------------------
