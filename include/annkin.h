@@ -58,13 +58,16 @@ typedef struct ak_mechanism ak_mechanism; /* opaque; owns its device tables */
 
 /*
  * Mechanism as a CHEMKIN-style file carries it (Sec. 2, Eq. 1; Eq. 5;
- * Eq. 10).  All pointers are HOST arrays owned by the caller and copied
- * during ak_load_mechanism; row-major.
+ * Eq. 10; Sec. 2.4 for the pressure-dependent reactions).  All pointers are
+ * HOST arrays owned by the caller and copied during ak_load_mechanism;
+ * row-major.
  *   W          [NS]      molecular weights, kg/kmol (> 0)
  *   nu_f, nu_r [NR][NS]  reactant / product stoichiometric coefficients
  *                        nu'_kj, nu''_kj at [j*NS + k] (>= 0)
  *   ln_A       [NR]      ln of the pre-exponential factor in cgs units,
- *                        (cm^3/mol)^(order-1)/s, order = sum_k nu'_kj
+ *                        (cm^3/mol)^(order-1)/s, order = sum_k nu'_kj (one
+ *                        more for a third-body reaction); for a falloff
+ *                        reaction the high-pressure limit
  *   beta       [NR]      temperature exponent
  *   Ea         [NR]      activation energy, cal/mol
  *   nasa_low, nasa_high [NS][7]  NASA-7 coefficients a1..a7 below / at and
@@ -72,12 +75,38 @@ typedef struct ak_mechanism ak_mechanism; /* opaque; owns its device tables */
  *   T_mid      [NS]      range switch temperature, K
  *   reversible [NR]      1 = reversible, 0 = irreversible (the indicator of
  *                        Sec. 2.4); NULL means all reversible
+ *   rtype      [NR]      AK_RXN_* (Sec. 2.4); NULL means all elementary
+ *   efficiency [NR][NS]  third-body efficiencies eff_kj of the third-body
+ *                        concentration [M]_j = sum_k eff_kj C_k (the paper's
+ *                        M = C E); read for rows with rtype != 0; NULL means
+ *                        all 1.  Finite and >= 0.
+ *   low_ln_A, low_beta, low_Ea [NR]  low-pressure limit k_0 of falloff
+ *                        reactions (A in cgs units of order sum nu' + 1);
+ *                        read for rows with rtype AK_RXN_LINDEMANN or
+ *                        AK_RXN_TROE (may be NULL if there are none)
+ *   troe       [NR][4]   Troe parameters alpha, T3, T1, T2 (the usual T***,
+ *                        T*, T**; T3, T1 > 0; T2 = 0 leaves the exp(-T2/T)
+ *                        term out); read for AK_RXN_TROE rows
+ * Falloff rate constants are k = k_inf Pr/(1 + Pr) F with
+ * Pr = k_0 [M] / k_inf and F = 1 (Lindemann) or the Troe broadening
+ * log10 F = log10 Fc / (1 + ((log10 Pr + c)/(n - 0.14 (log10 Pr + c)))^2),
+ * c = -0.4 - 0.67 log10 Fc, n = 0.75 - 1.27 log10 Fc,
+ * Fc = (1 - alpha) exp(-T/T3) + alpha exp(-T/T1) + exp(-T2/T).
+ * Third-body and falloff reactions are evaluated by the compiled kernels
+ * only: a mechanism with them needs AK_KERNEL_AUTO and a size the compiled
+ * kernels take, and ak_eval_jacobian / ak_eval_vjp return AK_EUNSUPPORTED
+ * for it.
  * Limits: NS >= 1 and NR >= 1 (else AK_EINVAL); NS <= 256, at most 4
  * reactant and 4 product molecules per reaction counting multiplicity
  * (sum of nu' <= 4, sum of nu'' <= 4), and a 16-cell LDS tile of
  * 24 * NS bytes per cell must fit the device (NS <= 426 on gfx950);
  * otherwise AK_EUNSUPPORTED.
  */
+#define AK_RXN_ELEMENTARY 0
+#define AK_RXN_THIRD_BODY 1 /* k [M] */
+#define AK_RXN_LINDEMANN 2  /* falloff, F = 1 */
+#define AK_RXN_TROE 3       /* falloff, Troe broadening */
+
 typedef struct {
     int32_t n_species;
     int32_t n_reactions;
@@ -91,6 +120,12 @@ typedef struct {
     const double *nasa_high;
     const double *T_mid;
     const uint8_t *reversible;
+    const uint8_t *rtype;
+    const double *efficiency;
+    const double *low_ln_A;
+    const double *low_beta;
+    const double *low_Ea;
+    const double *troe;
 } ak_mechanism_desc;
 
 /* Thread-local message describing the last error on this thread. */
@@ -138,6 +173,18 @@ int ak_mechanism_compiled(const ak_mechanism *mech, ak_precision prec);
  */
 int ak_jit_source(const ak_mechanism_desc *desc, ak_precision prec, char *buf, size_t cap,
                   size_t *needed);
+
+/*
+ * Diagnostic, no device needed: the constant tables the generated kernels
+ * of ak_jit_source read (per species 16 doubles: 1/W, T_mid, the low- and
+ * high-range Gibbs-layer weights; per reaction the Arrhenius layer and, for
+ * falloff reactions, the low-pressure and Troe constants, in the order of
+ * the generated code).  Copies at most cap_sp / cap_rx doubles into sp / rx
+ * (either may be NULL with cap 0) and the full counts into *n_sp / *n_rx.
+ * Errors: as ak_jit_source.
+ */
+int ak_jit_tables(const ak_mechanism_desc *desc, ak_precision prec, double *sp, size_t cap_sp,
+                  double *rx, size_t cap_rx, size_t *n_sp, size_t *n_rx);
 
 /* Free a mechanism.  The caller must ensure no enqueued work still uses it
  * (synchronise the streams first).  NULL is a no-op. */

@@ -40,7 +40,9 @@ class MechanismDesc(C.Structure):
         ("W", C.c_void_p), ("nu_f", C.c_void_p), ("nu_r", C.c_void_p),
         ("ln_A", C.c_void_p), ("beta", C.c_void_p), ("Ea", C.c_void_p),
         ("nasa_low", C.c_void_p), ("nasa_high", C.c_void_p), ("T_mid", C.c_void_p),
-        ("reversible", C.c_void_p),
+        ("reversible", C.c_void_p), ("rtype", C.c_void_p), ("efficiency", C.c_void_p),
+        ("low_ln_A", C.c_void_p), ("low_beta", C.c_void_p), ("low_Ea", C.c_void_p),
+        ("troe", C.c_void_p),
     ]
 
 
@@ -75,6 +77,9 @@ def lib():
                                            C.POINTER(C.c_void_p)]
         h.ak_mechanism_compiled.argtypes = [C.c_void_p, C.c_int]
         h.ak_jit_source.argtypes = [C.POINTER(MechanismDesc), C.c_int, C.c_char_p, C.c_size_t,
+                                    C.POINTER(C.c_size_t)]
+        h.ak_jit_tables.argtypes = [C.POINTER(MechanismDesc), C.c_int, C.c_void_p, C.c_size_t,
+                                    C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t),
                                     C.POINTER(C.c_size_t)]
         h.ak_free_mechanism.argtypes = [C.c_void_p]
         h.ak_mechanism_n_species.argtypes = [C.c_void_p]
@@ -117,7 +122,10 @@ _KERNELS = {"auto": AK_KERNEL_AUTO, "table": AK_KERNEL_TABLE}
 
 
 def _desc(src):
-    """(MechanismDesc, arrays it points into) for a mechanism-like object."""
+    """(MechanismDesc, arrays it points into) for a mechanism-like object.
+    Pressure-dependent reactions (Sec. 2.4) come from the optional
+    attributes rtype, eff, low_ln_A, low_beta, low_Ea and troe."""
+    nr, ns = int(src.nu_f.shape[0]), int(src.W.shape[0])
     keep = {
         "W": np.ascontiguousarray(src.W, np.float64),
         "nu_f": np.ascontiguousarray(src.nu_f, np.int8),
@@ -130,9 +138,24 @@ def _desc(src):
         "T_mid": np.ascontiguousarray(src.T_mid, np.float64),
         "reversible": np.ascontiguousarray(src.reversible, np.uint8),
     }
-    d = MechanismDesc(int(src.W.shape[0]), int(src.nu_f.shape[0]), *(keep[k].ctypes.data for k in (
+    opt = {"rtype": ("rtype", np.uint8, (nr,)), "efficiency": ("eff", np.float64, (nr, ns)),
+           "low_ln_A": ("low_ln_A", np.float64, (nr,)),
+           "low_beta": ("low_beta", np.float64, (nr,)),
+           "low_Ea": ("low_Ea", np.float64, (nr,)), "troe": ("troe", np.float64, (nr, 4))}
+    for name, (attr, dt, shape) in opt.items():
+        v = getattr(src, attr, None)
+        if v is not None:
+            v = np.ascontiguousarray(v, dt)
+            if v.shape != shape:
+                raise ValueError(f"{attr} must have shape {shape}")
+        keep[name] = v
+
+    def ptr(k):
+        return None if keep[k] is None else keep[k].ctypes.data
+
+    d = MechanismDesc(ns, nr, *(ptr(k) for k in (
         "W", "nu_f", "nu_r", "ln_A", "beta", "Ea", "nasa_low", "nasa_high", "T_mid",
-        "reversible")))
+        "reversible", "rtype", "efficiency", "low_ln_A", "low_beta", "low_Ea", "troe")))
     return d, keep
 
 
@@ -145,6 +168,21 @@ def jit_source(src, precision: str = "fp32") -> str:
     buf = C.create_string_buffer(need.value)
     _check(lib().ak_jit_source(C.byref(d), prec, buf, need.value, C.byref(need)))
     return buf.value.decode()
+
+
+def jit_tables(src, precision: str = "fp32"):
+    """(species table, reaction table) the generated kernels read (no GPU
+    needed; a diagnostic beside jit_source)."""
+    d, keep = _desc(src)
+    prec = {"fp32": AK_FP32, "fp64": AK_FP64}[precision]
+    nsp, nrx = C.c_size_t(), C.c_size_t()
+    _check(lib().ak_jit_tables(C.byref(d), prec, None, 0, None, 0, C.byref(nsp), C.byref(nrx)))
+    sp = np.zeros(nsp.value)
+    rx = np.zeros(nrx.value)
+    _check(lib().ak_jit_tables(C.byref(d), prec, sp.ctypes.data_as(C.c_void_p), sp.size,
+                               rx.ctypes.data_as(C.c_void_p), rx.size, C.byref(nsp),
+                               C.byref(nrx)))
+    return sp, rx
 
 
 class Mechanism:

@@ -18,6 +18,7 @@ struct ak_mechanism {
     std::vector<ak::RxnRec> host_rxn;   // shape-sorted order
     std::vector<int> rxn_order;         // file index of each sorted reaction
     ak::JitKernels jit[2];              // mechanism-compiled kernels per precision (FP64, FP32)
+    bool pdep = false;                  // third-body or falloff reactions (compiled kernels only)
 };
 
 namespace ak {

@@ -11,6 +11,18 @@
 
 namespace ak {
 
+// Pressure dependence of one reaction (Sec. 2.4), host side.  A
+// third-body reaction's RxnRec::log2A already counts the extra order; for
+// a falloff reaction RxnRec holds the high-pressure limit.
+struct PdepRec {
+    int type = 0;             // AK_RXN_* of annkin.h
+    int profile = -1;         // efficiency profile (third-body concentration)
+    double log2A0 = 0.0;      // low-pressure limit: log2 A (SI, order + 1)
+    double beta0 = 0.0;
+    double negE0oR2 = 0.0;    // -(E0/R) log2(e), K
+    double alpha = 0.0, T3 = 0.0, T1 = 0.0, T2 = 0.0;   // Troe
+};
+
 // What the generator needs of a prepared mechanism (host copies, sorted
 // reaction order).
 struct JitMech {
@@ -18,6 +30,9 @@ struct JitMech {
     const SpeciesRec *sp = nullptr;   // [ns]
     const RxnRec *rx = nullptr;       // [nr]
     const RxnAux *aux = nullptr;      // [nr]
+    const PdepRec *pd = nullptr;      // [nr], or null when all are elementary
+    // distinct efficiency vectors [ns] of the pressure-dependent reactions
+    const std::vector<std::vector<double>> *profiles = nullptr;
 };
 
 // Generated kernels of one mechanism for one precision.
@@ -48,6 +63,9 @@ struct JitBatchDesc {
 // the registers of one lane instead.
 constexpr int kTileWaves = 4;
 constexpr int kLaneFormMaxSpecies = 16;
+// largest mechanisms with compiled kernels (two tiles per CU of 160 KB LDS)
+constexpr int kJitMaxSpeciesFP32 = 102;
+constexpr int kJitMaxSpeciesFP64 = 76;
 
 // Whether a mechanism of this size gets compiled kernels: two tiles of the
 // tiled form must fit a CU's LDS.

@@ -129,6 +129,9 @@ struct Prepared {
     std::vector<ThermoRec> th;
     std::vector<int> order;         // file index of each sorted reaction
     MechView view;                  // runs and sweep ranges filled in
+    bool pdep = false;              // any third-body or falloff reaction
+    std::vector<PdepRec> pd;        // [nr] sorted order (empty without pdep)
+    std::vector<std::vector<double>> profiles;
 };
 
 static int prepare(const ak_mechanism_desc *d, Prepared &p)
@@ -156,6 +159,58 @@ static int prepare(const ak_mechanism_desc *d, Prepared &p)
         gibbs_weights(&d->nasa_low[7 * k], p.sp[k].lo);
         gibbs_weights(&d->nasa_high[7 * k], p.sp[k].hi);
     }
+    // pressure-dependent reactions (Sec. 2.4)
+    std::vector<PdepRec> pd(nr);
+    if (d->rtype) {
+        for (int j = 0; j < nr; ++j) {
+            const int t = d->rtype[j];
+            if (t > AK_RXN_TROE)
+                return set_error(AK_EINVAL, "reaction %d: unknown reaction type %d", j, t);
+            if (t == AK_RXN_ELEMENTARY) continue;
+            p.pdep = true;
+            PdepRec &r = pd[j];
+            r.type = t;
+            std::vector<double> e(ns, 1.0);
+            if (d->efficiency)
+                for (int k = 0; k < ns; ++k) {
+                    e[k] = d->efficiency[(size_t)j * ns + k];
+                    if (!std::isfinite(e[k]) || e[k] < 0.0)
+                        return set_error(AK_EINVAL, "reaction %d: bad efficiency of species %d",
+                                         j, k);
+                }
+            size_t q = 0;
+            while (q < p.profiles.size() && p.profiles[q] != e) ++q;
+            if (q == p.profiles.size()) p.profiles.push_back(e);
+            r.profile = (int)q;
+            if (t == AK_RXN_LINDEMANN || t == AK_RXN_TROE) {
+                if (!d->low_ln_A || !d->low_beta || !d->low_Ea)
+                    return set_error(AK_EINVAL, "reaction %d: falloff without low-pressure "
+                                                "parameters", j);
+                if (!std::isfinite(d->low_ln_A[j]) || !std::isfinite(d->low_beta[j]) ||
+                    !std::isfinite(d->low_Ea[j]))
+                    return set_error(AK_EINVAL, "reaction %d: non-finite low-pressure "
+                                                "parameter", j);
+                int order = 0;
+                for (int k = 0; k < ns; ++k) order += d->nu_f[(size_t)j * ns + k];
+                // k_0 carries one order more than the reaction
+                r.log2A0 = (d->low_ln_A[j] + order * std::log(1e-3)) * kLog2e;
+                r.beta0 = d->low_beta[j];
+                r.negE0oR2 = -(d->low_Ea[j] * kCal / kRuMol) * kLog2e;
+            }
+            if (t == AK_RXN_TROE) {
+                if (!d->troe) return set_error(AK_EINVAL, "reaction %d: Troe without parameters", j);
+                const double *tp = &d->troe[4 * (size_t)j];
+                if (!std::isfinite(tp[0]) || !(tp[1] > 0.0) || !(tp[2] > 0.0) ||
+                    !std::isfinite(tp[1]) || !std::isfinite(tp[2]) || !std::isfinite(tp[3]) ||
+                    tp[3] < 0.0)
+                    return set_error(AK_EINVAL, "reaction %d: bad Troe parameters", j);
+                r.alpha = tp[0];
+                r.T3 = tp[1];
+                r.T1 = tp[2];
+                r.T2 = tp[3];
+            }
+        }
+    }
     std::vector<RxnRec> rx(nr);
     std::vector<RxnAux> aux(nr);
     std::vector<int> shape(nr);
@@ -179,8 +234,10 @@ static int prepare(const ak_mechanism_desc *d, Prepared &p)
             return set_error(AK_EUNSUPPORTED, "reaction %d: empty reactant or product side", j);
         for (int t = 0; t < nf; ++t) r.sp[t] = (uint8_t)reac[t];
         for (int t = 0; t < np; ++t) r.sp[nf + t] = (uint8_t)prod[t];
-        // Arrhenius parameters: A from (cm^3/mol)^(order-1)/s to (m^3/kmol)^(order-1)/s
-        r.log2A = (d->ln_A[j] + (order - 1) * std::log(1e-3)) * kLog2e;
+        // Arrhenius parameters: A from (cm^3/mol)^(order-1)/s to (m^3/kmol)^(order-1)/s;
+        // a third-body reaction's A counts [M] as one order more
+        const int aorder = order + (pd[j].type == AK_RXN_THIRD_BODY ? 1 : 0);
+        r.log2A = (d->ln_A[j] + (aorder - 1) * std::log(1e-3)) * kLog2e;
         r.beta = d->beta[j];
         r.negEoR2 = -(d->Ea[j] * kCal / kRuMol) * kLog2e;
         const bool rev = d->reversible == nullptr || d->reversible[j];
@@ -204,6 +261,10 @@ static int prepare(const ak_mechanism_desc *d, Prepared &p)
     p.rx.resize(nr);
     p.aux.resize(nr);
     p.th.resize(ns);
+    if (p.pdep) {
+        p.pd.resize(nr);
+        for (int i = 0; i < nr; ++i) p.pd[i] = pd[p.order[i]];
+    }
     for (int k = 0; k < ns; ++k)
         for (int c = 0; c < 7; ++c) {
             p.th[k].lo[c] = d->nasa_low[7 * k + c];
@@ -257,6 +318,8 @@ static JitMech jit_view(const Prepared &p)
     j.sp = p.sp.data();
     j.rx = p.rx.data();
     j.aux = p.aux.data();
+    j.pd = p.pdep ? p.pd.data() : nullptr;
+    j.profiles = &p.profiles;
     return j;
 }
 
@@ -280,6 +343,23 @@ int ak_jit_source(const ak_mechanism_desc *d, ak_precision prec, char *buf, size
         std::memcpy(buf, src.data(), n);
         buf[n] = 0;
     }
+    return AK_OK;
+}
+
+int ak_jit_tables(const ak_mechanism_desc *d, ak_precision prec, double *sp, size_t cap_sp,
+                  double *rx, size_t cap_rx, size_t *n_sp, size_t *n_rx)
+{
+    if (!d || !n_sp || !n_rx) return set_error(AK_EINVAL, "ak_jit_tables: null argument");
+    if (prec != AK_FP32 && prec != AK_FP64)
+        return set_error(AK_EINVAL, "ak_jit_tables: bad precision %d", (int)prec);
+    Prepared p;
+    int rc = prepare(d, p);
+    if (rc) return rc;
+    const JitProgram prog = jit_generate(jit_view(p), prec == AK_FP64);
+    *n_sp = prog.sp.size();
+    *n_rx = prog.rx.size();
+    if (sp) std::memcpy(sp, prog.sp.data(), sizeof(double) * std::min(cap_sp, prog.sp.size()));
+    if (rx) std::memcpy(rx, prog.rx.data(), sizeof(double) * std::min(cap_rx, prog.rx.size()));
     return AK_OK;
 }
 
@@ -332,6 +412,11 @@ int ak_load_mechanism_ex(const ak_mechanism_desc *d, int device, int kernels, ak
                                      "failed: %s", log.c_str());
         use_jit[f] = true;
     }
+    if (p.pdep && !use_jit[0] && !use_jit[1])
+        return set_error(AK_EUNSUPPORTED,
+                         "ak_load_mechanism: third-body and falloff reactions need the compiled "
+                         "kernels (AK_KERNEL_AUTO and a mechanism of at most %d species)",
+                         kJitMaxSpeciesFP32);
 
     ak_mechanism *m = new (std::nothrow) ak_mechanism();
     if (!m) return set_error(AK_ENOMEM, "ak_load_mechanism: out of host memory");
@@ -349,7 +434,9 @@ int ak_load_mechanism_ex(const ak_mechanism_desc *d, int device, int kernels, ak
     const size_t o_err = o_aux + ((sizeof(RxnAux) * nr + 255) & ~(size_t)255);
     // tables of the compiled kernels, per precision: species, reactions
     const size_t jsp_bytes = (sizeof(double) * 16 * ns + 255) & ~(size_t)255;
-    const size_t jrx_bytes = (sizeof(double) * 3 * nr + 255) & ~(size_t)255;
+    // (falloff reactions carry more constants than the 3 of the others)
+    const size_t jrx_bytes =
+        (sizeof(double) * std::max(prog[0].rx.size(), prog[1].rx.size()) + 255) & ~(size_t)255;
     size_t o_jsp[2], o_jrx[2];
     o_jsp[0] = o_err + 256;
     o_jrx[0] = o_jsp[0] + jsp_bytes;
@@ -360,7 +447,7 @@ int ak_load_mechanism_ex(const ak_mechanism_desc *d, int device, int kernels, ak
     for (int f = 0; f < 2; ++f)
         if (use_jit[f]) {
             std::memcpy(&host[o_jsp[f]], prog[f].sp.data(), sizeof(double) * 16 * ns);
-            std::memcpy(&host[o_jrx[f]], prog[f].rx.data(), sizeof(double) * 3 * nr);
+            std::memcpy(&host[o_jrx[f]], prog[f].rx.data(), sizeof(double) * prog[f].rx.size());
         }
     std::memcpy(&host[o_sp], p.sp.data(), sizeof(SpeciesRec) * ns);
     std::memcpy(&host[o_rx], p.rx.data(), sizeof(RxnRec) * nr);
@@ -399,6 +486,7 @@ int ak_load_mechanism_ex(const ak_mechanism_desc *d, int device, int kernels, ak
             return rc;
         }
     }
+    m->pdep = p.pdep;
     m->host_species = std::move(p.sp);
     m->host_rxn = std::move(p.rx);
     m->rxn_order = std::move(p.order);
@@ -442,6 +530,10 @@ int ak_eval_source(const ak_mechanism *m, ak_precision prec, const void *T, cons
     DeviceGuard g(m->device);
     if (!g.ok) return set_error(AK_EDEVICE, "ak_eval_source: cannot select device %d", m->device);
     const JitKernels &jk = m->jit[prec];   // indexed by ak_precision
+    if (!jk.src && m->pdep)
+        return set_error(AK_EUNSUPPORTED, "ak_eval_source: third-body and falloff reactions "
+                                          "need the compiled kernel, which this mechanism has "
+                                          "not for %s", prec == AK_FP64 ? "AK_FP64" : "AK_FP32");
     hipError_t e = jk.src ? jit_launch(jk, T, P, Y, ldY, n, omega, ldO, m->view.err,
                                        (hipStream_t)stream)
                           : source_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, omega, ldO,
@@ -476,6 +568,9 @@ int ak_eval_jacobian(const ak_mechanism *m, ak_precision prec, const void *T, co
     if (ldJ < nv * nv)
         return set_error(AK_EINVAL, "ak_eval_jacobian: ldJ=%lld < (NS+1)^2=%lld", (long long)ldJ,
                          (long long)(nv * nv));
+    if (m->pdep)
+        return set_error(AK_EUNSUPPORTED, "ak_eval_jacobian: third-body and falloff reactions "
+                                          "are not differentiated");
     if (jacobian_lds_bytes(m->ns) > (size_t)m->lds_max)
         return set_error(AK_EUNSUPPORTED, "ak_eval_jacobian: %d species exceed the LDS", m->ns);
     DeviceGuard g(m->device);
@@ -497,6 +592,9 @@ int ak_eval_vjp(const ak_mechanism *m, ak_precision prec, const void *T, const v
     if (ldG < n || ldGY < n)
         return set_error(AK_EINVAL, "ak_eval_vjp: ldG=%lld ldGY=%lld < n_cells=%lld",
                          (long long)ldG, (long long)ldGY, (long long)n);
+    if (m->pdep)
+        return set_error(AK_EUNSUPPORTED, "ak_eval_vjp: third-body and falloff reactions are "
+                                          "not differentiated");
     if (m->vjp_tile < 16)
         return set_error(AK_EUNSUPPORTED, "ak_eval_vjp: %d species exceed the LDS", m->ns);
     DeviceGuard g(m->device);

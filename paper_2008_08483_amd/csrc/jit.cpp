@@ -29,6 +29,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -240,23 +241,183 @@ Common common_setup(const JitMech &m, bool f64, JitProgram &prog)
 
 }  // namespace
 
-// reactions per group of table reads (see below)
-static int kGroup = 2;
+namespace {
+
+// ---------------------------------------------------------------------------
+// pieces shared by both generated forms
+
+bool is_falloff(const JitMech &m, int j)
+{
+    return m.pd && (m.pd[j].type == AK_RXN_LINDEMANN || m.pd[j].type == AK_RXN_TROE);
+}
+bool is_pdep(const JitMech &m, int j) { return m.pd && m.pd[j].type != AK_RXN_ELEMENTARY; }
+
+// log2 of the constant factor between the stored v'_k and v_k = 2^-g_k:
+// v_k = v'_k 2^-(h_k + log2 W_k); a reaction's log2 A absorbs the factors of
+// its reactants
+double reactant_shift(const JitMech &m, const Common &cm, int j)
+{
+    double s = 0.0;
+    for (int i = 0; i < m.aux[j].nf; ++i) s += cm.h[m.aux[j].sp[i]] + cm.lw[m.aux[j].sp[i]];
+    return s;
+}
+
+// Constants of reaction j in the generated kernels' table: log2 A (shifted),
+// beta, -E/R log2 e; for falloff 8 more: log2 A0, beta0, -E0/R log2 e (low-
+// pressure limit), the shift, Troe alpha, log2(e)/T3, log2(e)/T1,
+// T2 log2(e).
+void push_rx(std::vector<double> &rx, const JitMech &m, const Common &cm, int j)
+{
+    const double sh = reactant_shift(m, cm, j);
+    rx.push_back(m.rx[j].log2A - sh);
+    rx.push_back(m.rx[j].beta);
+    rx.push_back(m.rx[j].negEoR2);
+    if (is_falloff(m, j)) {
+        const PdepRec &d = m.pd[j];
+        rx.push_back(d.log2A0);
+        rx.push_back(d.beta0);
+        rx.push_back(d.negE0oR2);
+        rx.push_back(sh);
+        rx.push_back(d.alpha);
+        rx.push_back(d.type == AK_RXN_TROE ? kLog2e / d.T3 : 0.0);
+        rx.push_back(d.type == AK_RXN_TROE ? kLog2e / d.T1 : 0.0);
+        rx.push_back(d.T2 * kLog2e);
+    }
+}
+int rx_size(const JitMech &m, int j) { return is_falloff(m, j) ? 11 : 3; }
+
+// scalar loads of reaction p's constants from rxp[off..]
+void emit_loads(Text &o, const char *ind, const JitMech &m, int p, int j, int off)
+{
+    o("%sconst double kA%d = rxp[%d], kB%d = rxp[%d], kE%d = rxp[%d];\n", ind, p, off, p,
+      off + 1, p, off + 2);
+    if (is_falloff(m, j))
+        o("%sconst double kA0%d = rxp[%d], kB0%d = rxp[%d], kE0%d = rxp[%d], kS%d = rxp[%d], "
+          "kal%d = rxp[%d], ki3%d = rxp[%d], ki1%d = rxp[%d], kt2%d = rxp[%d];\n",
+          ind, p, off + 3, p, off + 4, p, off + 5, p, off + 6, p, off + 7, p, off + 8, p,
+          off + 9, p, off + 10);
+}
+
+// Third-body concentration of efficiency profile q (Sec. 2.4, [M] = C E):
+// Ctot + sum over species with efficiency != 1 of (eff - 1) C_k, where
+// C(k) spells C_k and Ctot = P / (Ru T) is in scope.  Declares M<q> and,
+// with `log`, lM<q> = log2 [M].
+void emit_profile(Text &o, const char *ind, const JitMech &m, int q, bool log, bool f64,
+                  const std::function<std::string(int)> &C)
+{
+    const std::vector<double> &e = (*m.profiles)[q];
+    o("%sdouble M%d = Ctot;\n", ind, q);
+    for (int k = 0; k < m.ns; ++k)
+        if (e[k] != 1.0) o("%sM%d = __builtin_fma(%s, %s, M%d);\n", ind, q, lit(e[k] - 1.0).c_str(),
+                           C(k).c_str(), q);
+    if (log && f64) o("%sconst double lM%d = log2(M%d);\n", ind, q, q);
+    else if (log) o("%sconst double lM%d = (double)__builtin_amdgcn_logf((float)M%d);\n", ind, q, q);
+}
+
+// Names of the third-body concentration of reaction j's profile: M<q>,
+// lM<q> (in scope from emit_profile), or, with `local`, the names that
+// emit_rate declares inside the reaction's block.
+
+// The rate of progress of reaction j at position p of the generated code:
+// declares q<p> (accumulator type) from
+//     q = 2^t prod_r v (prod_r a - rev prod_p a) [x [M] | x Pr/(1+Pr) F]
+// (Eq. 4 re-associated with ln K_c = -sum_k nu_kj Gt_k, Eq. 11; the
+// pressure dependence of Sec. 2.4).  A(k) and V(k) spell a_k and v_k; the
+// reaction's constants (emit_loads) and the M / lM of its profile are in
+// scope.
+void emit_rate(Text &o, const char *ind, const JitMech &m, const Common &cm, bool f64, int p,
+               int j, const std::function<std::string(int)> &A,
+               const std::function<std::string(int)> &V,
+               const std::function<std::string(int)> *C = nullptr)
+{
+    const RxnAux &x = m.aux[j];
+    const int nf = x.nf, np = x.nr;
+    const char *AC = f64 ? "double" : "float";
+    std::string Vr;
+    if (f64 || !cm.vfloat) {
+        for (int i = 0; i < nf; ++i) Vr += (i ? "*" : "") + V(x.sp[i]);
+    } else {
+        // float v's are multiplied in float while the product stays in
+        // range, the partial products in double
+        double acc = 0.0;
+        std::string grp;
+        for (int i = 0; i < nf; ++i) {
+            const int k = x.sp[i];
+            if (!grp.empty() && acc + cm.R[k] > 120.0) {
+                Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
+                grp.clear();
+                acc = 0.0;
+            }
+            grp += (grp.empty() ? "" : "*") + V(k);
+            acc += cm.R[k];
+        }
+        Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
+    }
+    std::string Ar, Ap;
+    for (int i = 0; i < nf; ++i) Ar += (i ? "*" : "") + A(x.sp[i]);
+    for (int i = 0; i < np; ++i) Ap += (i ? "*" : "") + A(x.sp[nf + i]);
+    // one scalar operand per instruction (the constants sit in SGPRs)
+    o("%s%s q%d;\n%s{\n", ind, AC, p, ind);
+    o("%s  const double t = __builtin_fma(kB%d, L2T, kE%d * IT) + kA%d;\n", ind, p, p, p);
+    if (x.rev) o("%s  double X = (%s) * ((%s) - (%s));\n", ind, Vr.c_str(), Ar.c_str(), Ap.c_str());
+    else o("%s  double X = (%s) * (%s);\n", ind, Vr.c_str(), Ar.c_str());
+    if (is_pdep(m, j)) {
+        const PdepRec &d = m.pd[j];
+        // with C given, the reaction's own third-body concentration is formed
+        // here (short register live ranges), else the profile's is in scope
+        if (C) {
+            const std::string in = std::string(ind) + "  ";
+            emit_profile(o, in.c_str(), m, d.profile, is_falloff(m, j), f64, *C);
+        }
+        if (d.type == AK_RXN_THIRD_BODY) {
+            o("%s  X *= M%d;\n", ind, d.profile);
+        } else {
+            // log2 Pr = log2 k0 - log2 k_inf + log2 [M] (the Arrhenius layer
+            // also evaluates the low-pressure limit); the falloff function is
+            // a per-reaction epilogue outside the matrix form (Sec. 2.4)
+            o("%s  const double lp = (__builtin_fma(kB0%d, L2T, kE0%d * IT) + kA0%d) - t - kS%d + "
+              "lM%d;\n", ind, p, p, p, p, d.profile);
+            const char *FT = f64 ? "double" : "float";
+            // FP32 path: the hardware exp2 / log2 (about 1 ulp; the
+            // arguments stay in the normal range); FP64 path: the library's
+            const char *EX = f64 ? "exp2" : "__builtin_amdgcn_exp2f";
+            const char *LG = f64 ? "log2" : "__builtin_amdgcn_logf";
+            o("%s  %s r = (%s)1 / ((%s)1 + %s((%s)-lp));\n", ind, FT, FT, FT, EX, FT);
+            if (d.type == AK_RXN_TROE) {
+                o("%s  %s Fc = ((%s)1 - (%s)kal%d) * %s((%s)(-T * ki3%d)) + (%s)kal%d * "
+                  "%s((%s)(-T * ki1%d))%s;\n", ind, FT, FT, FT, p, EX, FT, p, FT, p, EX, FT, p,
+                  d.T2 != 0.0 ? (std::string(" + ") + EX + "((" + FT + ")(-kt2" +
+                                 std::to_string(p) + " * IT))").c_str() : "");
+                // log10 Fc, c, n, then F (Troe's broadening)
+                o("%s  const %s lFc = %s(Fc) * (%s)%s;\n", ind, FT, LG, FT,
+                  lit(std::log10(2.0)).c_str());
+                o("%s  const %s xc = (%s)lp * (%s)%s + ((%s)-0.4 - (%s)0.67 * lFc);\n", ind, FT,
+                  FT, FT, lit(std::log10(2.0)).c_str(), FT, FT);
+                o("%s  const %s f1 = xc / (((%s)0.75 - (%s)1.27 * lFc) - (%s)0.14 * xc);\n", ind,
+                  FT, FT, FT, FT);
+                o("%s  r *= %s(lFc / ((%s)1 + f1 * f1) * (%s)%s);\n", ind, EX, FT, FT,
+                  lit(std::log2(10.0)).c_str());
+            }
+            o("%s  X *= (double)r;\n", ind);
+        }
+    }
+    o("%s  q%d = qrate(X, t);\n", ind, p);
+}
+
+}  // namespace
 
 JitProgram jit_program(const JitMech &m, bool f64)
 {
-    if (const char *g = std::getenv("AK_JIT_GROUP")) kGroup = std::max(1, std::atoi(g));
+    // reactions per scheduling group
+    int group = 8;
+    if (const char *g = std::getenv("AK_JIT_GROUP")) group = std::max(1, std::atoi(g));
     const int ns = m.ns, nr = m.nr;
     const char *IO = f64 ? "double" : "float";
     const char *AC = f64 ? "double" : "float";   // omega accumulator type
     JitProgram prog;
-    prog.T_lo = 0.0;
-    prog.T_hi = 0.0;
-
+    prog.threads = 64;
     const Common cm = common_setup(m, f64, prog);
     const std::vector<int> &h = cm.h;
-    const std::vector<double> &R = cm.R;
-    const std::vector<double> &lw = cm.lw;
     const bool vfloat = cm.vfloat;
     const std::vector<std::vector<int>> rs = reaction_species(m);
     const std::vector<int> order = live_order(m, rs);
@@ -266,30 +427,19 @@ JitProgram jit_program(const JitMech &m, bool f64)
             if (first[k] < 0) first[k] = p;
             last[k] = p;
         }
-    // per-reaction constants of the generated kernel: log2 A (with the
-    // reactants' shifts and molecular weights), beta, -E/R log2 e
-    // (in the order of the generated code, so that consecutive reactions'
-    // constants are adjacent)
-    prog.rx.resize(3 * (size_t)nr);
+    // per-reaction constants in the order of the generated code, so that
+    // consecutive reactions' constants are adjacent
+    std::vector<int> off(nr + 1, 0);
+    prog.rx.clear();
     for (int p = 0; p < nr; ++p) {
-        const int j = order[p];
-        double shift = 0.0;
-        for (int i = 0; i < m.aux[j].nf; ++i) shift += h[m.aux[j].sp[i]] + lw[m.aux[j].sp[i]];
-        prog.rx[3 * p + 0] = m.rx[j].log2A - shift;
-        prog.rx[3 * p + 1] = m.rx[j].beta;
-        prog.rx[3 * p + 2] = m.rx[j].negEoR2;
+        off[p] = (int)prog.rx.size();
+        push_rx(prog.rx, m, cm, order[p]);
     }
-
-
     const char *VT = (f64 || !vfloat) ? "double" : "float";
-    const bool vlds = std::getenv("AK_JIT_VLDS") && std::atoi(std::getenv("AK_JIT_VLDS"));
-    const bool yreload = std::getenv("AK_JIT_YRELOAD") && std::atoi(std::getenv("AK_JIT_YRELOAD"));
-    auto vname = [&](int k) {
-        return vlds ? "vsh[" + std::to_string(k) + " * 64 + lane]" : "v" + std::to_string(k);
-    };
+
     Text o;
-    o("// generated by libannkin for a mechanism of %d species and %d reactions (%s path)\n",
-      ns, nr, f64 ? "FP64" : "FP32");
+    o("// generated by libannkin for a mechanism of %d species and %d reactions (%s path, "
+      "one lane per cell)\n", ns, nr, f64 ? "FP64" : "FP32");
     o("typedef long long i64;\ntypedef unsigned long long u64;\n");
     const std::vector<double> c = exp2_taylor(12);
     if (f64) {
@@ -305,7 +455,6 @@ JitProgram jit_program(const JitMech &m, bool f64)
         o("  const float p = __builtin_amdgcn_exp2f((float)(t - n));\n");
         o("  return (float)__builtin_ldexp(X, (int)n) * p;\n}\n");
     }
-
     // omega_k of this lane's cell.  The row offset passes through an empty
     // volatile asm at the store, so that the compiler forms it there rather
     // than keeping every row's address in scalar registers from the start.
@@ -315,8 +464,8 @@ JitProgram jit_program(const JitMech &m, bool f64)
     // the cell body: Tb, Pb, Yb, Ob point at the tile's first cell
     o("__device__ __forceinline__ void body(const %s *__restrict__ Tb, const %s *__restrict__ Pb,"
       " const %s *__restrict__ Yb, i64 ldY, %s *__restrict__ Ob, i64 ldO, unsigned lane,"
-      " const double *__restrict__ SP, const double *__restrict__ RX, u64 *err%s) {\n",
-      IO, IO, IO, IO, vlds ? (std::string(", ") + VT + " *vsh").c_str() : "");
+      " const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n",
+      IO, IO, IO, IO);
     o("  const double T = (double)Tb[lane], P = (double)Pb[lane];\n");
     for (int k = 0; k < ns; ++k) o("  const %s y%d = (Yb + (i64)%d * ldY)[lane];\n", IO, k, k);
     o("  const double LNT = log(T), IT = 1.0 / T, T2 = T * T, T3 = T2 * T, T4 = T3 * T;\n");
@@ -340,23 +489,41 @@ JitProgram jit_program(const JitMech &m, bool f64)
             o("  const bool hi%d = T >= %s;\n", id, lit(m.sp[k].T_mid).c_str());
         }
     o("  const %s nan = __builtin_nan(\"\");\n", IO);
+    // third-body concentrations of the efficiency profiles (while every
+    // mass fraction is at hand): C_k = rho_hat max(Y_k, 0) / W_k
+    if (m.pd) {
+        o("  const double Ctot = rh * sg;\n");
+        std::vector<char> used(m.profiles->size(), 0), logd(m.profiles->size(), 0);
+        for (int j = 0; j < nr; ++j)
+            if (is_pdep(m, j)) {
+                used[m.pd[j].profile] = 1;
+                if (is_falloff(m, j)) logd[m.pd[j].profile] = 1;
+            }
+        for (size_t q = 0; q < used.size(); ++q)
+            if (used[q])
+                emit_profile(o, "  ", m, (int)q, logd[q], f64, [&](int k) {
+                    return "(rh * __builtin_fmax((double)y" + std::to_string(k) + ", 0.0) * SP[" +
+                           std::to_string(16 * k) + "])";
+                });
+    }
 
-    const int pdeg = f64 ? 12 : 10;   // 2^f to below one ulp / 3e-13
+    // 2^f, |f| <= 1/2: degree 12 (below one ulp) in the FP64 path; degree 8
+    // (relative error below 3e-10) in the FP32 path
+    const int pdeg = f64 ? 12 : 8;
     auto open_species = [&](int k) {
         const int b = 16 * k;
         auto poly = [&](int off) {
+            // one scalar operand per instruction: the bias is added last
             char buf[512];
             snprintf(buf, sizeof buf,
-                     "__builtin_fma(spp[%d], IT, __builtin_fma(spp[%d], T4, "
-                     "__builtin_fma(spp[%d], T3, __builtin_fma(spp[%d], T2, "
-                     "__builtin_fma(spp[%d], T, __builtin_fma(spp[%d], LNT, "
-                     "spp[%d]))))))",
-                     b + off + 5, b + off + 4, b + off + 3, b + off + 2, b + off + 1, b + off,
+                     "(__builtin_fma(spp[%d], LNT, __builtin_fma(spp[%d], T, "
+                     "__builtin_fma(spp[%d], T2, __builtin_fma(spp[%d], T3, "
+                     "__builtin_fma(spp[%d], T4, spp[%d] * IT))))) + spp[%d])",
+                     b + off, b + off + 1, b + off + 2, b + off + 3, b + off + 4, b + off + 5,
                      b + off + 6);
             return std::string(buf);
         };
-        if (vlds) o("  double a%d; %s w%d = 0;\n  {\n", k, AC, k);
-        else o("  double a%d; %s v%d; %s w%d = 0;\n  {\n", k, VT, k, AC, k);
+        o("  double a%d; %s v%d; %s w%d = 0;\n  {\n", k, VT, k, AC, k);
         // both ranges are evaluated and one is selected per lane; the empty
         // asm keeps the compiler from turning the select of the two
         // polynomials into a select of their coefficient addresses (which
@@ -376,11 +543,10 @@ JitProgram jit_program(const JitMech &m, bool f64)
         o("    O *= f;\n    const int ni = (int)n;\n");
         // y passes through an empty asm so that the compiler does not keep
         // the mixture sum's converted copy of it live until here
-        if (yreload) o("    %s yy = (ypp + (i64)%d * ldY)[lane];\n", IO, k);
-        else o("    %s yy = y%d;\n    asm(\"\" : \"+v\"(yy));\n", IO, k);
+        o("    %s yy = y%d;\n    asm(\"\" : \"+v\"(yy));\n", IO, k);
         o("    a%d = rh * __builtin_fmax((double)yy, 0.0) * __builtin_ldexp(E + O, ni);\n", k);
-        if (f64 || !vfloat) o("    %s = __builtin_ldexp(E - O, -ni);\n", vname(k).c_str());
-        else o("    %s = (float)__builtin_ldexp(E - O, %d - ni);\n", vname(k).c_str(), h[k]);
+        if (f64 || !vfloat) o("    v%d = __builtin_ldexp(E - O, -ni);\n", k);
+        else o("    v%d = (float)__builtin_ldexp(E - O, %d - ni);\n", k, h[k]);
         o("  }\n");
     };
 
@@ -388,69 +554,37 @@ JitProgram jit_program(const JitMech &m, bool f64)
     for (int k = 0; k < ns; ++k)
         if (first[k] < 0) o("  store(Ob, ldO, %d, lane, bad ? nan : (%s)0);\n", k, IO);
 
-    // The reactions are emitted in groups of kGroup, separated by scheduling
-    // fences.  The group's table reads go through pointers that an empty asm
-    // derives from the previous group's last rate, so that they cannot move
-    // ahead of it (left alone, the compiler reads every reaction's and
-    // species' constants at the kernel entry and spills them).
-    const int ngroups = (nr + kGroup - 1) / kGroup;
+    // The reactions are emitted in groups, separated by scheduling fences.
+    // The group's table reads go through a pointer that an empty asm derives
+    // from the previous group's last rate, so that they cannot move ahead of
+    // it (left alone, the compiler reads every reaction's and species'
+    // constants at the kernel entry and spills them); the next group's
+    // constants are read one group ahead.  The pointers are in the constant
+    // address space, so that the reads stay scalar.
+    const int ngroups = (nr + group - 1) / group;
     auto load_group = [&](int g) {
-        for (int p = g * kGroup; p < std::min(nr, (g + 1) * kGroup); ++p)
-            o("  const double kA%d = rxp[%d], kB%d = rxp[%d], kE%d = rxp[%d];\n", p, 3 * p, p,
-              3 * p + 1, p, 3 * p + 2);
+        for (int p = g * group; p < std::min(nr, (g + 1) * group); ++p)
+            emit_loads(o, "  ", m, p, order[p], off[p]);
     };
-    const bool ahead = std::getenv("AK_JIT_PREFETCH") && std::atoi(std::getenv("AK_JIT_PREFETCH"));
     o("  const __attribute__((address_space(4))) double *rxp = "
       "(const __attribute__((address_space(4))) double *)RX;\n"
       "  const __attribute__((address_space(4))) double *spp = "
       "(const __attribute__((address_space(4))) double *)SP;\n");
-    if (yreload) o("  const %s *ypp = Yb;\n", IO);
-    if (ahead) load_group(0);
+    load_group(0);
+    auto A = [](int k) { return "a" + std::to_string(k); };
+    auto V = [](int k) { return "v" + std::to_string(k); };
     for (int p = 0; p < nr; ++p) {
         const int j = order[p];
         const RxnAux &x = m.aux[j];
         const int nf = x.nf, np = x.nr;
-        const int g = p / kGroup;
-        if (p % kGroup == 0) {
-            if (p > 0)
-                o("  asm volatile(\"\" : \"+s\"(rxp), \"+s\"(spp)%s : \"v\"(q%d));\n",
-                  yreload ? ", \"+s\"(ypp)" : "", p - 1);
-            if (!ahead) load_group(g);
-            else if (g + 1 < ngroups) load_group(g + 1);
+        const int g = p / group;
+        if (p % group == 0) {
+            if (p > 0) o("  asm volatile(\"\" : \"+s\"(rxp), \"+s\"(spp) : \"v\"(q%d));\n", p - 1);
+            if (g + 1 < ngroups) load_group(g + 1);
         }
         for (int k : rs[j])
             if (first[k] == p) open_species(k);
-        // prefactor 2^t prod_r v: in the FP32 path the float v's are
-        // multiplied in float while the product stays in range, the partial
-        // products in double
-        std::string Vr;
-        if (f64 || !vfloat) {
-            for (int i = 0; i < nf; ++i) Vr += (i ? "*" : "") + vname(x.sp[i]);
-        } else {
-            double acc = 0.0;
-            std::string grp;
-            for (int i = 0; i < nf; ++i) {
-                const int k = x.sp[i];
-                if (!grp.empty() && acc + R[k] > 120.0) {
-                    Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
-                    grp.clear();
-                    acc = 0.0;
-                }
-                grp += (grp.empty() ? "" : "*") + vname(k);
-                acc += R[k];
-            }
-            Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
-        }
-        std::string Ar, Ap;
-        for (int i = 0; i < nf; ++i) Ar += (i ? "*a" : "a") + std::to_string(x.sp[i]);
-        for (int i = 0; i < np; ++i) Ap += (i ? "*a" : "a") + std::to_string(x.sp[nf + i]);
-        o("  %s q%d;\n  {\n    const double t = __builtin_fma(kB%d, L2T, kE%d * IT) + kA%d;\n",
-          AC, p, p, p, p);
-        if (x.rev)
-            o("    q%d = qrate((%s) * ((%s) - (%s)), t);\n", p, Vr.c_str(), Ar.c_str(),
-              Ap.c_str());
-        else
-            o("    q%d = qrate((%s) * (%s), t);\n", p, Vr.c_str(), Ar.c_str());
+        emit_rate(o, "  ", m, cm, f64, p, j, A, V);
         o("    const %s q = q%d;\n", AC, p);
         // net coefficient of each species in this reaction (Eq. 2)
         for (int k : rs[j]) {
@@ -466,34 +600,28 @@ JitProgram jit_program(const JitMech &m, bool f64)
         o("  }\n");
         for (int k : rs[j])
             if (last[k] == p) o("  store(Ob, ldO, %d, lane, bad ? nan : (%s)w%d);\n", k, IO, k);
-        if ((p + 1) % kGroup == 0 || p + 1 == nr) o("  __builtin_amdgcn_sched_barrier(0);\n");
+        if ((p + 1) % group == 0 || p + 1 == nr) o("  __builtin_amdgcn_sched_barrier(0);\n");
     }
     o("  if (bad) atomicAdd(err, 1ull);\n}\n");
 
     o("struct BD { const void *T, *P, *Y; void *om; i64 ldY, ldO, n, block_begin; };\n");
-    int wpe = 1;
-    if (const char *w = std::getenv("AK_JIT_WPE")) wpe = std::max(1, std::atoi(w));
-    o("#define AK_LB __launch_bounds__(64, %d)\n", wpe);
-    o("extern \"C\" __global__ AK_LB void ak_src(const %s *__restrict__ T, "
+    o("extern \"C\" __global__ __launch_bounds__(64) void ak_src(const %s *__restrict__ T, "
       "const %s *__restrict__ P, const %s *__restrict__ Y, i64 ldY, i64 n, %s *__restrict__ om, "
       "i64 ldO, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n",
       IO, IO, IO, IO);
     o("  const i64 c0 = (i64)blockIdx.x * 64;\n  const unsigned lane = threadIdx.x;\n");
     o("  if (c0 + lane >= n) return;\n");
-    if (vlds) o("  __shared__ %s vsh[%d * 64];\n", VT, ns);
-    o("  body(T + c0, P + c0, Y + c0, ldY, om + c0, ldO, lane, SP, RX, err%s);\n}\n",
-      vlds ? ", vsh" : "");
-    o("extern \"C\" __global__ AK_LB void ak_src_batch(const BD *__restrict__ d, "
+    o("  body(T + c0, P + c0, Y + c0, ldY, om + c0, ldO, lane, SP, RX, err);\n}\n");
+    o("extern \"C\" __global__ __launch_bounds__(64) void ak_src_batch(const BD *__restrict__ d, "
       "int nreq, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n");
     o("  const i64 b = blockIdx.x;\n  int lo = 0, hi = nreq - 1;\n");
     o("  while (lo < hi) { const int mid = (lo + hi + 1) >> 1; "
       "if (d[mid].block_begin <= b) lo = mid; else hi = mid - 1; }\n");
     o("  const BD r = d[lo];\n  const i64 c0 = (b - r.block_begin) * 64;\n");
     o("  const unsigned lane = threadIdx.x;\n  if (c0 + lane >= r.n) return;\n");
-    if (vlds) o("  __shared__ %s vsh[%d * 64];\n", VT, ns);
     o("  body((const %s *)r.T + c0, (const %s *)r.P + c0, (const %s *)r.Y + c0, r.ldY, "
-      "(%s *)r.om + c0, r.ldO, lane, SP, RX, err%s);\n}\n",
-      IO, IO, IO, IO, vlds ? ", vsh" : "");
+      "(%s *)r.om + c0, r.ldO, lane, SP, RX, err);\n}\n",
+      IO, IO, IO, IO);
     prog.src = std::move(o.s);
     return prog;
 }
@@ -580,7 +708,6 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
     };
     const bool lsalias = knob("AK_JIT_LSALIAS", 1) != 0;
     const bool tree = knob("AK_JIT_TREE", 1) != 0;
-    const int wpe = f64 ? knob("AK_JIT_WPE64", 3) : knob("AK_JIT_WPE", 4);
     const int ns = m.ns, nr = m.nr;
     const char *IO = f64 ? "double" : "float";
     const char *AC = f64 ? "double" : "float";   // omega accumulator type
@@ -588,10 +715,17 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
     prog.threads = 64 * W;
     const Common cm = common_setup(m, f64, prog);
     const std::vector<int> &h = cm.h;
-    const std::vector<double> &R = cm.R;
-    const std::vector<double> &lw = cm.lw;
     const bool vfloat = cm.vfloat;
     const char *VT = (f64 || !vfloat) ? "double" : "float";
+    // waves per SIMD the kernel is built for: as many tiles as the LDS holds
+    // (W waves each), within what the registers allow (one accumulator per
+    // species, two registers each in the FP64 path, plus about 48 others)
+    const size_t lds = (size_t)64 * ns * (8 + ((f64 || !vfloat) ? 8 : 4)) +
+                       (lsalias ? 0 : (size_t)64 * W * (8 + (f64 ? 8 : 4)));
+    const int tiles = std::max<int>(1, (int)(163840 / lds));
+    const int wpe_lds = std::max(1, tiles * W / 4);
+    const int wpe_reg = std::max(1, 512 / ((f64 ? 2 : 1) * ns + (m.pd ? 80 : 48)));
+    const int wpe = knob(f64 ? "AK_JIT_WPE64" : "AK_JIT_WPE", std::min(wpe_lds, wpe_reg));
 
     const std::vector<std::vector<int>> rs = reaction_species(m);
     const std::vector<std::vector<int>> part = split_reactions(m, rs, W);
@@ -605,21 +739,19 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
         for (int j : part[w])
             for (int k : rs[j])
                 if (first_w[k] < 0 || first_w[k] > w) first_w[k] = w;
-    // per-reaction constants in the order of the generated code
+    // per-reaction constants in the order of the generated code: each
+    // wave's segment, offsets within it
     std::vector<int> rxoff(W + 1, 0);
+    std::vector<std::vector<int>> off(W);
     prog.rx.clear();
     for (int w = 0; w < W; ++w) {
-        rxoff[w] = (int)prog.rx.size() / 3;
+        rxoff[w] = (int)prog.rx.size();
         for (int j : part[w]) {
-            double shift = 0.0;
-            for (int i = 0; i < m.aux[j].nf; ++i)
-                shift += h[m.aux[j].sp[i]] + lw[m.aux[j].sp[i]];
-            prog.rx.push_back(m.rx[j].log2A - shift);
-            prog.rx.push_back(m.rx[j].beta);
-            prog.rx.push_back(m.rx[j].negEoR2);
+            off[w].push_back((int)prog.rx.size() - rxoff[w]);
+            push_rx(prog.rx, m, cm, j);
         }
     }
-    rxoff[W] = nr;
+    rxoff[W] = (int)prog.rx.size();
 
     Text o;
     o("// generated by libannkin for a mechanism of %d species and %d reactions (%s path, "
@@ -671,6 +803,7 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
     if (vfloat) o(" || !(T >= %s) || !(T <= %s)", lit(prog.T_lo).c_str(), lit(prog.T_hi).c_str());
     o(";\n");
     o("  const double rh = P / (%s * T * sg);\n", lit(kRu).c_str());
+    if (m.pd) o("  const double Ctot = rh * sg;\n");
     if (lsalias) o("  __syncthreads();\n");
     std::map<double, int> tmid;
     for (int k = 0; k < ns; ++k)
@@ -728,14 +861,27 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
         // that the loads stay scalar after the pointer passes the asm fences
         o("    const __attribute__((address_space(4))) double *rxp = "
           "(const __attribute__((address_space(4))) double *)(RX + %d);\n"
-          "    unsigned la8 = lane * 8u, lv8 = lane * (unsigned)sizeof(*LV);\n", 3 * rxoff[w]);
+          "    unsigned la8 = lane * 8u, lv8 = lane * (unsigned)sizeof(*LV);\n", rxoff[w]);
         const int cnt = (int)pl.size();
         const int ngroups = (cnt + group - 1) / group;
         std::vector<char> seen(ns, 0);
+        // byte offsets passed through the group fences, so that each read
+        // is a base register plus an immediate offset
+        auto A = [&](int k) {
+            return "*(const double *)((const char *)LA + la8 + " + std::to_string(512 * k) + ")";
+        };
+        auto V = [&](int k) {
+            return std::string("*(const ") + VT + " *)((const char *)LV + lv8 + " +
+                   std::to_string(64 * k * ((f64 || !vfloat) ? 8 : 4)) + ")";
+        };
+        // concentrations for third-body sums: C_k = a_k v_k 2^-(h_k + log2 W_k)
+        const std::function<std::string(int)> Cf = [&](int k) {
+            return "(" + A(k) + " * (double)" + V(k) + " * " +
+                   lit(std::exp2(-(cm.h[k] + cm.lw[k]))) + ")";
+        };
         auto load_group = [&](int g) {
             for (int p = g * group; p < std::min(cnt, (g + 1) * group); ++p)
-                o("    const double kA%d = rxp[%d], kB%d = rxp[%d], kE%d = rxp[%d];\n", p, 3 * p, p,
-                  3 * p + 1, p, 3 * p + 2);
+                emit_loads(o, "    ", m, p, pl[p], off[w][p]);
         };
         if (ahead) load_group(0);
         for (int p = 0; p < cnt; ++p) {
@@ -749,44 +895,7 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int W)
                 if (!ahead) load_group(p / group);
                 else if (p / group + 1 < ngroups) load_group(p / group + 1);
             }
-            // byte offsets passed through the group fences, so that each read
-            // is a base register plus an immediate offset
-            auto A = [&](int k) {
-                return "*(const double *)((const char *)LA + la8 + " + std::to_string(512 * k) + ")";
-            };
-            auto V = [&](int k) {
-                return std::string("*(const ") + VT + " *)((const char *)LV + lv8 + " +
-                       std::to_string(64 * k * ((f64 || !vfloat) ? 8 : 4)) + ")";
-            };
-            std::string Vr;
-            if (f64 || !vfloat) {
-                for (int i = 0; i < nf; ++i) Vr += (i ? "*" : "") + V(x.sp[i]);
-            } else {
-                double acc = 0.0;
-                std::string grp;
-                for (int i = 0; i < nf; ++i) {
-                    const int k = x.sp[i];
-                    if (!grp.empty() && acc + R[k] > 120.0) {
-                        Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
-                        grp.clear();
-                        acc = 0.0;
-                    }
-                    grp += (grp.empty() ? "" : "*") + V(k);
-                    acc += R[k];
-                }
-                Vr += (Vr.empty() ? "(double)(" : "*(double)(") + grp + ")";
-            }
-            std::string Ar, Ap;
-            for (int i = 0; i < nf; ++i) Ar += (i ? "*" : "") + A(x.sp[i]);
-            for (int i = 0; i < np; ++i) Ap += (i ? "*" : "") + A(x.sp[nf + i]);
-            // one scalar operand per instruction (the constants sit in SGPRs)
-            o("    %s q%d;\n    {\n      const double t = __builtin_fma(kB%d, L2T, kE%d * IT) "
-              "+ kA%d;\n", AC, p, p, p, p);
-            if (x.rev)
-                o("      q%d = qrate((%s) * ((%s) - (%s)), t);\n", p, Vr.c_str(), Ar.c_str(),
-                  Ap.c_str());
-            else
-                o("      q%d = qrate((%s) * (%s), t);\n", p, Vr.c_str(), Ar.c_str());
+            emit_rate(o, "    ", m, cm, f64, p, j, A, V, &Cf);
             o("      const %s q = q%d;\n", AC, p);
             for (int k : rs[j]) {
                 int nu = 0;

@@ -325,6 +325,9 @@ int ak_server_submit(ak_server *s, const ak_mechanism *m, ak_precision prec, con
     if (m->device != s->device)
         return set_error(AK_EINVAL, "ak_server_submit: mechanism on device %d, server on %d",
                          m->device, s->device);
+    if (m->pdep && !m->jit[prec].src)
+        return set_error(AK_EUNSUPPORTED, "ak_server_submit: third-body and falloff reactions "
+                                          "need the compiled kernel for this precision");
     ak_request *q = new (std::nothrow) ak_request();
     if (!q) return set_error(AK_ENOMEM, "ak_server_submit: out of host memory");
     q->srv = s;

@@ -249,7 +249,9 @@ def with_pressure_dependence(mech: Mechanism, frac: float = 0.2, seed: int = 11,
     falloff, in the proportions ``types``.  Reactions with one molecule on
     one side and two on the other (dissociation / recombination, the usual
     form of such reactions) are taken first.  Efficiencies are 1 except for
-    about one species in five (0, 0.5, 2 or 5).  A third-body reaction's
+    those of one of three efficiency profiles drawn for the mechanism, as real
+    mechanisms share a few (each: five species at 0, 0.5, 2 or 5; the first
+    profile is taken by half of the reactions).  A third-body reaction's
     ln A, one order more, gets U[5, 10] added (termolecular constants are
     larger in cgs units); for falloff the drawn
     parameters are the high-pressure limit and the low-pressure limit gets
@@ -269,10 +271,13 @@ def with_pressure_dependence(mech: Mechanism, frac: float = 0.2, seed: int = 11,
     rtype = np.zeros(nr, np.uint8)
     kinds = rng.choice(3, size=chosen.size, p=np.asarray(types) / np.sum(types)) + 1
     rtype[chosen] = kinds
+    profiles = np.ones((3, ns))
+    for q in range(3):
+        special = rng.choice(ns, size=min(5, ns), replace=False)
+        profiles[q, special] = rng.choice([0.0, 0.5, 2.0, 5.0], size=special.size)
     eff = np.ones((nr, ns))
     for j in chosen:
-        special = rng.random(ns) < 0.2
-        eff[j, special] = rng.choice([0.0, 0.5, 2.0, 5.0], size=int(special.sum()))
+        eff[j] = profiles[rng.choice(3, p=[0.5, 0.25, 0.25])]
     low_ln_A = mech.ln_A + rng.uniform(8.0, 14.0, nr)
     low_beta = mech.beta + rng.uniform(-1.0, 0.0, nr)
     low_Ea = mech.Ea * rng.uniform(0.5, 1.0, nr)

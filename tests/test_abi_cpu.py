@@ -82,3 +82,36 @@ def test_server_submit_rejects_mismatched_buffers():
     for t, p, y, o, exc in bad:
         with pytest.raises(exc):
             srv.submit(_M(), t, p, y, o)
+
+
+def test_pressure_dependent_descriptor_checks():
+    """Third-body / falloff fields are validated at load (host only: the
+    source generator runs the same checks without a GPU)."""
+    import numpy as np
+    from paper_2008_08483_amd import annkin, synth
+
+    base = synth.with_pressure_dependence(synth.make_mechanism(9, 21), frac=0.5)
+    text = annkin.jit_source(base, "fp64")
+    assert "Ctot" in text and "lM" in text and "exp2(" in text   # [M] and the falloff epilogue
+    text32 = annkin.jit_source(base, "fp32")
+    assert "__builtin_amdgcn_exp2f" in text32
+
+    def variant(**kw):
+        import copy
+        m = copy.copy(base)
+        for k, v in kw.items():
+            setattr(m, k, v)
+        return m
+
+    bad_type = base.rtype.copy()
+    bad_type[0] = 4
+    neg_eff = base.eff.copy()
+    neg_eff[np.nonzero(base.rtype)[0][0], 0] = -1.0
+    j_troe = int(np.nonzero(base.rtype == 3)[0][0])
+    bad_troe = base.troe.copy()
+    bad_troe[j_troe, 1] = 0.0
+    for m in (variant(rtype=bad_type), variant(eff=neg_eff), variant(troe=bad_troe),
+              variant(low_ln_A=None, low_beta=None, low_Ea=None), variant(troe=None)):
+        with pytest.raises(annkin.AnnkinError) as e:
+            annkin.jit_source(m, "fp32")
+        assert e.value.code == -1, annkin.lib().ak_last_error()

@@ -1,0 +1,135 @@
+"""GPU parity of the pressure-dependent reactions (Sec. 2.4: third-body
+reactions through [M] = sum of efficiency-weighted concentrations, Lindemann
+and Troe falloff as a per-reaction epilogue) against the oracle, through the
+compiled kernels (both forms: one lane per cell for small mechanisms, the
+tiled form for larger ones).
+
+Tolerances as for the elementary mechanisms (tests/metrics.py): FP32 path
+max M1 and M2 (kappa <= 1e4) <= 1e-5 against the double oracle on the exact
+FP32 inputs; FP64 path <= 1e-12 against the extended-precision oracle.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_08483_amd import synth
+from tests.test_gpu_source import _check32, _check64, _equilibrium, _run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ak():
+    from paper_2008_08483_amd import annkin
+    return annkin
+
+
+_MECHS = {}
+
+
+def _mech(ak, ns, nr, frac):
+    key = (ns, nr, frac)
+    if key not in _MECHS:
+        src = synth.with_pressure_dependence(synth.make_mechanism(ns, nr), frac=frac)
+        _MECHS[key] = (src, ak.Mechanism(src))
+    return _MECHS[key]
+
+
+@pytest.mark.parametrize("ns,nr,frac,n", [(9, 21, 0.5, 1024), (53, 325, 0.2, 4099)])
+def test_pdep_parity(torch, ak, ns, nr, frac, n):
+    src, m = _mech(ak, ns, nr, frac)
+    assert set(np.unique(src.rtype)) >= {0, 1, 2, 3}
+    assert m.compiled(np.float32) and m.compiled(np.float64)
+    T, P, Y = synth.make_states(src, n, 77, (800.0, 2800.0), (1.0, 20.0), 0.3)
+    om = _run(torch, ak, m, T, P, Y, torch.float64)
+    _check64(src, T, P, Y, om)
+    T32, P32, Y32 = (a.astype(np.float32) for a in (T, P, Y))
+    om32 = _run(torch, ak, m, T32, P32, Y32, torch.float32)
+    _check32(src, T32, P32, Y32, om32)
+
+
+def test_pdep_across_the_falloff_curve(torch, ak):
+    # pressures from 1 kPa to 100 MPa: reduced pressures from the low- to the
+    # high-pressure limit
+    src, m = _mech(ak, 53, 325, 0.2)
+    rng = np.random.default_rng(4)
+    n = 2048
+    T = rng.uniform(800.0, 2800.0, n)
+    P = 10.0 ** rng.uniform(3.0, 8.0, n)
+    Y = rng.dirichlet(np.full(53, 0.3), n).T.copy()
+    om = _run(torch, ak, m, T, P, Y, torch.float64)
+    _check64(src, T, P, Y, om)
+    T32, P32, Y32 = (a.astype(np.float32) for a in (T, P, Y))
+    om32 = _run(torch, ak, m, T32, P32, Y32, torch.float32)
+    _check32(src, T32, P32, Y32, om32)
+
+
+@pytest.mark.parametrize("delta", [0.0, 1e-3])
+def test_pdep_near_equilibrium(torch, ak, delta):
+    src, m = _mech(ak, 53, 325, 0.2)
+    rng = np.random.default_rng(6)
+    n = 128
+    T = rng.uniform(900.0, 2600.0, n)
+    P = np.zeros(n)
+    Y = np.zeros((53, n))
+    for i in range(n):
+        lam = rng.uniform(-14.0, -9.0, 3)
+        P[i], Y[:, i] = _equilibrium(src, T[i], lam, delta, rng)
+    om = _run(torch, ak, m, T, P, Y, torch.float64)
+    _check64(src, T, P, Y, om)
+    T32, P32, Y32 = (a.astype(np.float32) for a in (T, P, Y))
+    om32 = _run(torch, ak, m, T32, P32, Y32, torch.float32)
+    _check32(src, T32, P32, Y32, om32)
+
+
+def test_pdep_full_size_sampled(torch, ak):
+    # 53/325 with 20 % pressure-dependent reactions at 2^20 cells (the
+    # benchmark's launch), sampled cells against the oracle
+    src, m = _mech(ak, 53, 325, 0.2)
+    _, T, P, Y = synth.workload("c1_full", dtype=np.float32)
+    om = _run(torch, ak, m, T, P, Y, torch.float32)
+    idx = np.random.default_rng(9).choice(T.shape[0], 4096, replace=False)
+    _check32(src, T[idx], P[idx], Y[:, idx], om[:, idx])
+
+
+def test_pdep_unsupported_paths(torch, ak):
+    src, m = _mech(ak, 9, 21, 0.5)
+    with pytest.raises(ak.AnnkinError) as e:
+        ak.Mechanism(src, kernels="table")
+    assert e.value.code == -7
+    T, P, Y = synth.make_states(src, 8, 1)
+    Tt, Pt, Yt = (torch.tensor(a, device="cuda") for a in (T, P, Y))
+    with pytest.raises(ak.AnnkinError) as e:
+        ak.eval_jacobian(m, Tt, Pt, Yt)
+    assert e.value.code == -7
+    with pytest.raises(ak.AnnkinError) as e:
+        ak.eval_vjp(m, Tt, Pt, Yt, torch.zeros_like(Yt))
+    assert e.value.code == -7
+
+
+def test_pdep_served_bitwise_as_alone(torch, ak):
+    src, m = _mech(ak, 53, 325, 0.2)
+    srv = ak.Server(max_inflight=2, batching=True, arena_bytes=64 << 20)
+    reqs, outs = [], []
+    states = [synth.make_states(src, n, 300 + i, dtype=np.float32)
+              for i, n in enumerate((100, 1000, 64, 3000))]
+    for T, P, Y in states:
+        out = torch.zeros(Y.shape, dtype=torch.float32).pin_memory()
+        pins = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory() for a in (T, P, Y)]
+        reqs.append((srv.submit(m, *pins, out), pins))
+        outs.append(out)
+    for r, _ in reqs:
+        r.wait(60.0)
+        r.free()
+    srv.close()
+    for (T, P, Y), out in zip(states, outs):
+        alone = _run(torch, ak, m, T, P, Y, torch.float32)
+        assert np.array_equal(out.numpy().astype(np.float64), alone)
