@@ -32,11 +32,24 @@ from paper_2008_08483_amd import roofline, synth  # noqa: E402
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_source_f32_53x325_1M.json")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(src=None) -> str:
+    """Identity of the FP32 source-term kernel the workload runs: the hash of
+    the generated source text (compiled kernels), else of the table
+    kernels' sources."""
     h = hashlib.sha256()
-    for f in ("source_kernels.hip", "ak_device.h", "ak_math.h"):
-        with open(os.path.join(ROOT, "paper_2008_08483_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    if src is None:
+        src = synth.workload("c1_full", n_cells=1)[0]
+    from paper_2008_08483_amd import annkin
+    try:
+        text = annkin.jit_source(src, "fp32")
+    except Exception:  # pragma: no cover - library missing: fall back to files
+        text = None
+    if text is not None and src.n_species <= 102:
+        h.update(text.encode())
+    else:
+        for f in ("source_kernels.hip", "ak_device.h", "ak_math.h"):
+            with open(os.path.join(ROOT, "paper_2008_08483_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -51,6 +64,32 @@ def measured_traffic():
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
+
+
+def accuracy(torch, annkin, mech, src, T, P, Y, n=4096):
+    """Error of both paths against the oracle on the first n cells: FP32 path
+    against the double oracle on the exact FP32 inputs, FP64 path against the
+    extended-precision oracle (metrics M1 = |d omega|/S, M2 = |d omega|/N over
+    entries with N >= S/kappa, M3 = |d omega|/|omega| over |omega| >= 1e-3 S)."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from metrics import grade
+    T, P, Y = (np.asarray(a)[..., :n] for a in (T, P, Y))
+    out = {}
+    for name, dt, prec, kappa in (("fp32", np.float32, "f64", 1e4), ("fp64", np.float64, "ld", 10.0)):
+        Ti, Pi, Yi = (np.ascontiguousarray(a.astype(dt)) for a in (T, P, Y))
+        tdt = torch.float32 if dt == np.float32 else torch.float64
+        om = annkin.eval_source(mech, *(torch.tensor(a, dtype=tdt, device="cuda") for a in (Ti, Pi, Yi)))
+        torch.cuda.synchronize()
+        om = om.cpu().numpy().astype(np.float64)
+        ref, S, N = oracle.source(src, *(a.astype(np.float64) for a in (Ti, Pi, Yi)),
+                                  precision=prec, scales=True)
+        g = grade(om, ref, S, N, kappa_max=kappa, s_floor=1e-30 if dt == np.float32 else 0.0)
+        out[name] = {k: g[k] for k in ("m1_max", "m1_median", "m2_max", "m3_median", "m3_p99",
+                                       "nonfinite")}
+    out["sample"] = f"first {n} cells of the workload; FP32 vs the double oracle, FP64 vs the " \
+                    "extended-precision oracle"
+    return out
 
 
 def time_path(torch, annkin, mech, T, P, Y, steps, warmup):
@@ -158,6 +197,27 @@ def c2_bench(torch, annkin):
     slots = roofline.method_slots(src.nu_f, src.nu_r)
     res["roofline_frac_fp32"] = slots * n / (res["fp32"]["kernel_ms"] * 1e-3) / \
         roofline.PEAK_VALU_SLOTS
+    mech.close()
+    return res
+
+
+def pdep_bench(torch, annkin, T32, P32, Y32, T, P, Y):
+    """The 53/325 mechanism with 20 % of its reactions pressure dependent
+    (third-body, Lindemann and Troe falloff; Sec. 2.4) on the same 2^20
+    states, both paths, and its error against the oracle."""
+    src = synth.with_pressure_dependence(synth.make_mechanism(53, 325), frac=0.2)
+    mech = annkin.Mechanism(src)
+    n = T32.shape[0]
+    counts = np.bincount(src.rtype, minlength=4)
+    res = {"workload": f"{src.n_species}sp/{src.n_reactions}rxn synthetic mechanism, "
+                       f"{int(counts[1])} third-body, {int(counts[2])} Lindemann, "
+                       f"{int(counts[3])} Troe reactions, x {n} cells"}
+    for name, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        Tt, Pt, Yt = (a.to(dt) for a in (T32, P32, Y32))
+        ms = kernel_ms(torch, annkin, mech, Tt, Pt, Yt, reps=10)
+        res[name] = {"kernel_ms": ms, "cells_per_s": n / (ms * 1e-3)}
+        del Tt, Pt, Yt
+    res["accuracy"] = accuracy(torch, annkin, mech, src, T, P, Y, n=2048)
     mech.close()
     return res
 
@@ -316,6 +376,7 @@ def main():
     ap.add_argument("--no-deriv", action="store_true")
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--no-saturation", action="store_true")
+    ap.add_argument("--no-pdep", action="store_true")
     ap.add_argument("--only-main", action="store_true",
                     help="time only the main FP32 leg (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -394,6 +455,11 @@ def main():
             "unit": "T VALU lane-slots/s",
             "frac": achieved / roofline.PEAK_VALU_SLOTS,
             "traffic": traffic,
+            "counts_per_cell": dict(zip(("transcendental", "fp32", "fp64"),
+                                        roofline.method_counts(src.nu_f, src.nu_r))),
+            "t_roof_us": roofline.t_valu(src.nu_f, src.nu_r, n) * 1e6,
+            "frac_measured_rates": roofline.t_valu(src.nu_f, src.nu_r, n, "measured") /
+                                   k_avg_s,
             "kernel": ("ak_src (compiled for the mechanism)" if mech.compiled(torch.float32)
                        else "ak::source_kernel<float>"),
             "slots_per_cell": slots,
@@ -404,7 +470,14 @@ def main():
 
     if args.only_main:
         args.no_fp64 = args.no_cpu_baseline = args.no_serving = args.no_deriv = True
-        args.no_c2 = args.no_saturation = True
+        args.no_c2 = args.no_saturation = args.no_pdep = True
+    result["kernel_compiled"] = bool(mech.compiled(torch.float32))
+    if not args.only_main:
+        result["accuracy"] = accuracy(torch, annkin, mech, src, T, P, Y)
+        # the table-driven kernel on the same launch, for comparison
+        mt = annkin.Mechanism(src, kernels="table")
+        result["table_kernel_fp32_ms"] = kernel_ms(torch, annkin, mt, T32, P32, Y32, reps=10)
+        mt.close()
     if not args.no_fp64:
         T64, P64, Y64 = (t.double() for t in (T32, P32, Y32))
         wall64, ms64, om64 = time_path(torch, annkin, mech, T64, P64, Y64,
@@ -435,6 +508,9 @@ def main():
 
     if args.workload == "c1_full" and not args.no_saturation:
         result["saturation_fp32"] = saturation(torch, annkin, mech, T32, P32, Y32)
+
+    if args.workload == "c1_full" and not args.no_pdep:
+        result["pdep_20pct"] = pdep_bench(torch, annkin, T32, P32, Y32, T, P, Y)
 
     if not args.no_deriv:
         result["differentiation"] = deriv_bench(torch, annkin)
