@@ -240,6 +240,26 @@ int ak_eval_vjp(const ak_mechanism *mech, ak_precision prec, const void *T, cons
                 void *g_Y, int64_t ldGY, void *g_T, void *stream);
 
 /*
+ * 0-D constant-pressure adiabatic reactor (the paper's 0-D ignition test,
+ * Sec. 3.1): advances every cell's (T, Y) in place by n_steps forward-Euler
+ * steps of dt seconds at its fixed P,
+ *     Y_k <- Y_k + dt W_k omega_k / rho,   T <- T + dt omega_T,
+ * with omega from Eq. 2 (the same kernels as ak_eval_source), rho the mass
+ * density and omega_T = -sum_k H_k omega_k / sum_k C_k cp_k (molar enthalpy
+ * and heat capacity from the NASA-7 polynomials).  T[n], P[n] and
+ * Y[NS][ldY] are device arrays of the precision's type; T and Y are
+ * overwritten.  Forward Euler is stable only for dt below the fastest
+ * chemical time scale (1/|largest Jacobian eigenvalue|).  Uses a scratch
+ * buffer of NS * n_cells elements for omega, allocated and freed
+ * stream-ordered (hipMallocAsync) within the call.  Asynchronous on stream.
+ * Errors: as ak_eval_source, plus AK_EINVAL for dt <= 0 or non-finite and
+ * n_steps < 0, AK_ENOMEM.
+ */
+int ak_integrate_euler(const ak_mechanism *mech, ak_precision prec, void *T, const void *P,
+                       void *Y, int64_t ldY, int64_t n_cells, double dt, int n_steps,
+                       void *stream);
+
+/*
  * Read and reset the number of bad cells (non-finite input, T <= 0 or
  * P <= 0) seen by all evaluations with this mechanism since the last call.
  * Synchronises `stream`.  Errors: AK_EINVAL, AK_EDEVICE.

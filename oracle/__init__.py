@@ -79,6 +79,9 @@ def _lib_handle():
             getattr(lib, f"ora_temp_source_{sfx}").argtypes = [
                 C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                 C.c_void_p, C.c_int]
+            getattr(lib, f"ora_integrate_euler_{sfx}").argtypes = [
+                C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                C.c_double, C.c_int, C.c_int]
             getattr(lib, f"ora_jacobian_{sfx}").argtypes = [
                 C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                 C.c_void_p, C.c_int64, C.c_int]
@@ -234,3 +237,22 @@ def jacobian(mech, T, P, Y, precision: str = "f64", scales: bool = False, n_thre
     if rc:
         raise RuntimeError("oracle jacobian failed")
     return (J, Ja) if scales else J
+
+
+def integrate_euler(mech, T, P, Y, dt: float, n_steps: int, precision: str = "f64",
+                    n_threads: int = 0):
+    """0-D constant-pressure reactor, n_steps forward-Euler steps of dt
+    (Sec. 3.1): returns new (T [n], Y [NS, n]); P [n] is held fixed."""
+    m = _as_mech(mech)
+    _dtype(precision)
+    T = np.array(T, dtype=np.float64, copy=True)
+    P = _f64(P)
+    Y = np.array(Y, dtype=np.float64, copy=True, order="C")
+    n = T.shape[0]
+    assert P.shape == (n,) and Y.shape == (m.ns, n)
+    rc = getattr(_lib_handle(), f"ora_integrate_euler_{precision}")(
+        m.ptr, n, T.ctypes.data, P.ctypes.data, Y.ctypes.data, n, float(dt), int(n_steps),
+        int(n_threads))
+    if rc:
+        raise RuntimeError("oracle integrate_euler failed")
+    return T, Y

@@ -64,6 +64,8 @@ typedef struct {
                             const double *Y, int64_t ldY, R *omega_T, int n_threads);          \
     int ora_jacobian_##S(const ora_mech *m, int64_t n, const double *T, const double *P,     \
                          const double *Y, int64_t ldY, R *J, int64_t ldJ, int n_threads);      \
+    int ora_integrate_euler_##S(const ora_mech *m, int64_t n, double *T, const double *P,      \
+                                double *Y, int64_t ldY, double dt, int n_steps, int n_threads); \
     int ora_jacobian_scaled_##S(const ora_mech *m, int64_t n, const double *T,                 \
                                 const double *P, const double *Y, int64_t ldY, R *J, R *Jabs,  \
                                 int64_t ldJ, int n_threads);

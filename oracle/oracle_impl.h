@@ -408,3 +408,68 @@ int SFX(ora_jacobian_scaled)(const ora_mech *m, int64_t n, const double *T, cons
     }
     return err;
 }
+
+/* 0-D constant-pressure adiabatic reactor, forward Euler (the paper's 0-D
+ * ignition test, Sec. 3.1): per step, with omega from Eq. 2 and
+ * omega_T = -sum_k H_k omega_k / sum_k C_k cp_k (molar enthalpy and heat
+ * capacity from the NASA-7 polynomials),
+ *     Y_k <- Y_k + dt W_k omega_k / rho,   T <- T + dt omega_T,
+ * rho = sum_k C_k W_k the mass density.  T and Y are updated in place
+ * (double in, the step evaluated in REAL, rounded back to double). */
+int SFX(ora_integrate_euler)(const ora_mech *m, int64_t n, double *T, const double *P,
+                             double *Y, int64_t ldY, double dt, int n_steps, int n_threads)
+{
+    const int ns = m->ns, nr = m->nr;
+    int err = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+#endif
+    {
+        REAL *buf = (REAL *)malloc(sizeof(REAL) * 5 * ns);
+        if (!buf) {
+            err = -1;
+        } else {
+            REAL *Yc = buf, *C = Yc + ns, *h = C + ns, *s = h + ns, *om = s + ns;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+            for (int64_t i = 0; i < n; ++i) {
+                REAL Ti = T[i];
+                const REAL Pi = P[i];
+                for (int k = 0; k < ns; ++k) Yc[k] = Y[k * ldY + i];
+                for (int step = 0; step < n_steps; ++step) {
+                    SFX(concentrations)(m, Ti, Pi, Yc, C);
+                    for (int k = 0; k < ns; ++k) {
+                        SFX(thermo1)(m, k, Ti, &h[k], &s[k], 0, 0);
+                        om[k] = 0;
+                    }
+                    for (int j = 0; j < nr; ++j) {
+                        REAL kf, Kc, qf, qr;
+                        SFX(reaction1)(m, j, Ti, C, h, s, &kf, &Kc, &qf, &qr);
+                        const int8_t *nf = &m->nu_f[j * ns], *nrr = &m->nu_r[j * ns];
+                        for (int k = 0; k < ns; ++k) {
+                            int nu = nrr[k] - nf[k];
+                            if (nu) om[k] += nu * (qf - qr);
+                        }
+                    }
+                    REAL num = 0, den = 0, rho = 0;
+                    for (int k = 0; k < ns; ++k) {
+                        REAL cp;
+                        SFX(thermo1)(m, k, Ti, 0, 0, &cp, 0);
+                        num += (REAL)ORA_RU * Ti * h[k] * om[k];
+                        den += C[k] * (REAL)ORA_RU * cp;
+                        rho += C[k] * (REAL)m->W[k];
+                    }
+                    const REAL omT = -num / den;
+                    for (int k = 0; k < ns; ++k) Yc[k] += (REAL)dt * (REAL)m->W[k] * om[k] / rho;
+                    Ti += (REAL)dt * omT;
+                }
+                T[i] = (double)Ti;
+                for (int k = 0; k < ns; ++k) Y[k * ldY + i] = (double)Yc[k];
+            }
+            free(buf);
+        }
+    }
+    return err;
+}

@@ -81,6 +81,9 @@ def lib():
         h.ak_jit_tables.argtypes = [C.POINTER(MechanismDesc), C.c_int, C.c_void_p, C.c_size_t,
                                     C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t),
                                     C.POINTER(C.c_size_t)]
+        h.ak_integrate_euler.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_int64, C.c_int64, C.c_double, C.c_int,
+                                         C.c_void_p]
         h.ak_free_mechanism.argtypes = [C.c_void_p]
         h.ak_mechanism_n_species.argtypes = [C.c_void_p]
         h.ak_mechanism_n_reactions.argtypes = [C.c_void_p]
@@ -318,6 +321,18 @@ def eval_vjp(mech: Mechanism, T, P, Y, g_omega, stream=None):
                              Y.data_ptr(), ldY, n, g_omega.data_ptr(), ldG, gY.data_ptr(),
                              n, gT.data_ptr(), _stream_ptr(stream)))
     return gY, gT
+
+
+def integrate_euler(mech: Mechanism, T, P, Y, dt: float, n_steps: int, stream=None):
+    """Advance (T [n], Y [NS, n]) in place by n_steps forward-Euler steps of
+    dt seconds of the 0-D constant-pressure reactor at fixed P [n]
+    (Sec. 3.1).  float32 tensors select the FP32 path, float64 the FP64 path.
+    Asynchronous on ``stream`` (default: torch's current stream)."""
+    n = _check_state(mech, T, P, Y)
+    _check(lib().ak_integrate_euler(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
+                                    Y.data_ptr(), Y.stride(0), n, float(dt), int(n_steps),
+                                    _stream_ptr(stream)))
+    return T, Y
 
 
 def _source_function():

@@ -46,6 +46,16 @@ hipError_t source_launch(const MechView &m, bool f64, const void *T, const void 
 // max_ns: the largest species count among the batch's mechanisms
 hipError_t source_batch_launch(bool f64, const BatchDesc *d_desc, int nreq, int64_t blocks,
                                size_t lds, int max_ns, hipStream_t st);
+hipError_t euler_update_launch(const MechView &m, bool f64, void *T, const void *P, void *Y,
+                               int64_t ldY, int64_t n, const void *om, int64_t ldO, double dt,
+                               hipStream_t st);
+// Argument checks of the integrators (fn names the entry point in messages)
+// and their body: n_steps of (source term into `omega` [NS][n], update).
+int integrate_check(const char *fn, const ak_mechanism *m, int prec, const void *T,
+                    const void *P, const void *Y, int64_t ldY, int64_t n, double dt,
+                    int n_steps);
+int integrate_run(const ak_mechanism *m, int prec, void *T, const void *P, void *Y,
+                  int64_t ldY, int64_t n, double dt, int n_steps, void *omega, void *stream);
 size_t jacobian_lds_bytes(int ns);
 hipError_t jacobian_launch(const MechView &m, int lds_max, bool f64, const void *T, const void *P,
                            const void *Y, int64_t ldY, int64_t n, void *J, int64_t ldJ,

@@ -605,6 +605,68 @@ int ak_eval_vjp(const ak_mechanism *m, ak_precision prec, const void *T, const v
     return AK_OK;
 }
 
+}  // extern "C"
+
+namespace ak {
+
+int integrate_check(const char *fn, const ak_mechanism *m, int prec, const void *T,
+                    const void *P, const void *Y, int64_t ldY, int64_t n, double dt,
+                    int n_steps)
+{
+    int rc = check_state(fn, m, (ak_precision)prec, T, P, Y, ldY, n);
+    if (rc) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt))
+        return set_error(AK_EINVAL, "%s: dt must be positive and finite", fn);
+    if (n_steps < 0) return set_error(AK_EINVAL, "%s: n_steps < 0", fn);
+    if (!m->jit[prec].src && m->pdep)
+        return set_error(AK_EUNSUPPORTED, "%s: third-body and falloff reactions need the "
+                                          "compiled kernel for this precision", fn);
+    return AK_OK;
+}
+
+int integrate_run(const ak_mechanism *m, int prec, void *T, const void *P, void *Y,
+                  int64_t ldY, int64_t n, double dt, int n_steps, void *omega, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    const JitKernels &jk = m->jit[prec];
+    for (int s = 0; s < n_steps; ++s) {
+        hipError_t e = jk.src ? jit_launch(jk, T, P, Y, ldY, n, omega, n, m->view.err, st)
+                              : source_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, omega,
+                                              n, st);
+        if (e == hipSuccess)
+            e = euler_update_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, omega, n, dt, st);
+        if (e != hipSuccess) return hip_error(e, "integrator step");
+    }
+    return AK_OK;
+}
+
+}  // namespace ak
+
+extern "C" {
+
+int ak_integrate_euler(const ak_mechanism *m, ak_precision prec, void *T, const void *P,
+                       void *Y, int64_t ldY, int64_t n, double dt, int n_steps, void *stream)
+{
+    int rc = integrate_check("ak_integrate_euler", m, prec, T, P, Y, ldY, n, dt, n_steps);
+    if (rc) return rc;
+    if (n == 0 || n_steps == 0) return AK_OK;
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "ak_integrate_euler: cannot select device %d",
+                                m->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = (size_t)m->ns * (size_t)n * (prec == AK_FP64 ? 8 : 4);
+    void *omega = nullptr;
+    hipError_t e = hipMallocAsync(&omega, bytes, st);
+    if (e != hipSuccess)
+        return set_error(AK_ENOMEM, "ak_integrate_euler: scratch of %zu bytes: %s", bytes,
+                         hipGetErrorString(e));
+    rc = integrate_run(m, prec, T, P, Y, ldY, n, dt, n_steps, omega, stream);
+    e = hipFreeAsync(omega, st);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_error(e, "ak_integrate_euler: freeing the scratch");
+    return AK_OK;
+}
+
 int ak_error_count(const ak_mechanism *m, void *stream, int64_t *n_bad)
 {
     if (!m || !n_bad) return set_error(AK_EINVAL, "ak_error_count: null argument");

@@ -142,7 +142,8 @@ _SHAPES = (((1,), 0.22), ((2,), 0.04), ((1, 1), 0.60), ((2, 1), 0.10), ((2, 2), 
 
 
 def make_mechanism(ns: int, nr: int, seed: int | None = None, name: str | None = None,
-                   max_tries: int = 200) -> Mechanism:
+                   max_tries: int = 200, ln_A_range=(20.0, 35.0),
+                   Ea_range=(0.0, 40000.0)) -> Mechanism:
     """Random atom-balanced reversible mechanism with ns species, nr reactions.
 
     Reactions have 1-2 reactant species and 1-2 product species with
@@ -150,7 +151,8 @@ def make_mechanism(ns: int, nr: int, seed: int | None = None, name: str | None =
     same atom vector, the two sides have no species in common, no reaction is
     drawn twice (in either direction), and every species takes part in at
     least one reaction.  Arrhenius: ln A ~ U[20, 35] (cgs), beta ~ U[-2, 2],
-    Ea ~ U[0, 40000] cal/mol.
+    Ea ~ U[0, 40000] cal/mol (``ln_A_range`` and ``Ea_range`` change the
+    first and last).
     """
     if seed is None:
         seed = MECH_SEEDS.get((ns, nr), 0)
@@ -166,9 +168,9 @@ def make_mechanism(ns: int, nr: int, seed: int | None = None, name: str | None =
     n_atoms = comp.sum(axis=1)
     W = comp.astype(np.float64) @ ELEMENT_MASSES
     low, high = _nasa_sets(ns, n_atoms, rng)
-    ln_A = rng.uniform(20.0, 35.0, nr)
+    ln_A = rng.uniform(ln_A_range[0], ln_A_range[1], nr)
     beta = rng.uniform(-2.0, 2.0, nr)
-    Ea = rng.uniform(0.0, 40000.0, nr)
+    Ea = rng.uniform(Ea_range[0], Ea_range[1], nr)
     species = []
     count = {}
     for k in range(ns):
