@@ -260,6 +260,22 @@ int ak_integrate_euler(const ak_mechanism *mech, ak_precision prec, void *T, con
                        void *stream);
 
 /*
+ * ak_integrate_euler without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid it).  Same arguments, results and errors; the
+ * scratch for omega is a 64 MiB device array inside the library, one per GPU
+ * (present from the library's load until the process ends), so
+ * NS * n_cells * element size may not exceed 64 MiB (else AK_E2BIG; e.g.
+ * 158,275 cells at 53 species FP64).  Every call on one GPU uses that GPU's
+ * array: calls that overlap on one GPU (other threads or streams) race and
+ * must be serialised by the caller.  The array needs no clearing: each step
+ * overwrites it before reading it.
+ */
+int ak_integrate_euler_noalloc(const ak_mechanism *mech, ak_precision prec, void *T,
+                               const void *P, void *Y, int64_t ldY, int64_t n_cells, double dt,
+                               int n_steps, void *stream);
+
+/*
  * Read and reset the number of bad cells (non-finite input, T <= 0 or
  * P <= 0) seen by all evaluations with this mechanism since the last call.
  * Synchronises `stream`.  Errors: AK_EINVAL, AK_EDEVICE.

@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "annkin.h"
 #include "ak_device.h"
@@ -79,3 +80,63 @@ hipError_t euler_update_launch(const MechView &m, bool f64, void *T, const void 
 }
 
 }  // namespace ak
+
+// ---------------------------------------------------------------------------
+// The integrator without allocations: its scratch (the production rates
+// between the two kernels of a step) is this file-scope device array, one
+// copy per GPU, held until the process ends.  Host code uses the address
+// hipGetSymbolAddress returns for the current device, never the array's
+// name.
+
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];   // device address of `scratch` per ordinal
+
+// The scratch address on device `dev` (made current by the caller): looked
+// up at the first call on that device and kept.
+int scratch_on(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return ak::set_error(AK_EINVAL, "ak_integrate_euler_noalloc: device %d", dev);
+    std::lock_guard<std::mutex> l(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return ak::hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                 "ak_integrate_euler_noalloc: scratch address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return AK_OK;
+}
+
+}  // namespace
+
+extern "C" int ak_integrate_euler_noalloc(const ak_mechanism *m, ak_precision prec, void *T,
+                                          const void *P, void *Y, int64_t ldY, int64_t n,
+                                          double dt, int n_steps, void *stream)
+{
+    int rc = ak::integrate_check("ak_integrate_euler_noalloc", m, prec, T, P, Y, ldY, n, dt,
+                                 n_steps);
+    if (rc) return rc;
+    if (n == 0 || n_steps == 0) return AK_OK;
+    const size_t bytes = (size_t)m->ns * (size_t)n * (prec == AK_FP64 ? 8 : 4);
+    if (bytes > kNoAllocScratchBytes)
+        return ak::set_error(AK_E2BIG,
+                             "ak_integrate_euler_noalloc: %d species x %lld cells need %zu bytes "
+                             "of scratch, at most %zu",
+                             m->ns, (long long)n, bytes, kNoAllocScratchBytes);
+    ak::DeviceGuard g(m->device);
+    if (!g.ok)
+        return ak::set_error(AK_EDEVICE, "ak_integrate_euler_noalloc: cannot select device %d",
+                             m->device);
+    void *omega = nullptr;
+    if ((rc = scratch_on(m->device, &omega))) return rc;
+    return ak::integrate_run(m, prec, T, P, Y, ldY, n, dt, n_steps, omega, stream);
+}
