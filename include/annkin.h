@@ -164,6 +164,12 @@ int ak_load_mechanism_ex(const ak_mechanism_desc *desc, int device, int kernels,
  * precision, 0 if the table-driven one, negative on bad arguments. */
 int ak_mechanism_compiled(const ak_mechanism *mech, ak_precision prec);
 
+/* 1 if the mechanism has a compiled state Jacobian (what
+ * ak_eval_jacobian_interleaved needs and ak_eval_jacobian runs unless the
+ * environment variable AK_JIT_JACOBIAN=0 is set), 0 if not, negative on
+ * bad arguments.  The same for both precisions. */
+int ak_mechanism_compiled_jacobian(const ak_mechanism *mech, ak_precision prec);
+
 /*
  * Diagnostic, no device needed: the HIP source text the library generates
  * for a mechanism and precision (what ak_load_mechanism compiles).  Writes
@@ -185,6 +191,29 @@ int ak_jit_source(const ak_mechanism_desc *desc, ak_precision prec, char *buf, s
  */
 int ak_jit_tables(const ak_mechanism_desc *desc, ak_precision prec, double *sp, size_t cap_sp,
                   double *rx, size_t cap_rx, size_t *n_sp, size_t *n_rx);
+
+/*
+ * Diagnostic, no device needed: the HIP source text of the state Jacobian
+ * compiled for a mechanism (what ak_eval_jacobian, interleaved = 0, or
+ * ak_eval_jacobian_interleaved, interleaved = 1, compiles at its first call
+ * for the mechanism and precision), same buffer convention as
+ * ak_jit_source.  Errors: as ak_jit_source, plus AK_EUNSUPPORTED for a
+ * mechanism without a compiled Jacobian (third-body or falloff reactions,
+ * more species than the compiled form takes).
+ */
+int ak_jit_jacobian_source(const ak_mechanism_desc *desc, ak_precision prec, int interleaved,
+                           char *buf, size_t cap, size_t *needed);
+
+/*
+ * Diagnostic, no device needed: the constant tables of that kernel (the same
+ * for both precisions): per species 32 doubles (1/W, T_mid, the Gibbs-layer
+ * weights of both ranges with log2(1/W) in the biases, the NASA-7 sets
+ * a1..a7 low then high, two zeros); per reaction 4 doubles (log2 A less the
+ * reactants' log2 W, beta, -(E/R) log2 e, E/R).  Buffer convention and
+ * errors as ak_jit_tables / ak_jit_jacobian_source.
+ */
+int ak_jit_jacobian_tables(const ak_mechanism_desc *desc, double *sp, size_t cap_sp, double *rx,
+                           size_t cap_rx, size_t *n_sp, size_t *n_rx);
 
 /* Free a mechanism.  The caller must ensure no enqueued work still uses it
  * (synchronise the streams first).  NULL is a no-op. */
@@ -220,13 +249,45 @@ int ak_eval_source(const ak_mechanism *mech, ak_precision prec, const void *T, c
  * float for AK_FP32, double for AK_FP64 (both evaluate in double).  Where
  * Y_m < 0 the column of Y_m is zero (the clamp); at Y_m = 0 the one-sided
  * derivative from above is returned.
- * Errors: as ak_eval_source, plus AK_EINVAL for ldJ < (NS+1)^2 and
- * AK_EUNSUPPORTED when (NS+1)^2 + 11 NS + 257 doubles exceed one
- * workgroup's LDS (NS > 135 on gfx950).
+ * Mechanisms of elementary reactions that fit one 64-cell tile's LDS (see
+ * ak_eval_jacobian_interleaved; 53 species and 325 reactions do) use a kernel
+ * compiled for the mechanism (one 64-cell tile per workgroup, every sum in
+ * a fixed order: results are bitwise reproducible); it is generated and
+ * compiled at the first call for the mechanism and precision (seconds; the
+ * code object is cached like the source-term kernels'), which also makes
+ * one small device allocation for its tables, freed with the mechanism.
+ * Larger mechanisms, or the environment variable AK_JIT_JACOBIAN=0, use the
+ * table-driven kernel (one cell per workgroup, LDS atomics: the summation
+ * order, and so the last bits, may vary between runs).
+ * Errors: as ak_eval_source, plus AK_EINVAL for ldJ < (NS+1)^2,
+ * AK_EUNSUPPORTED when neither kernel takes the mechanism (the table-driven
+ * one needs (NS+1)^2 + 11 NS + 257 doubles in one workgroup's LDS: NS <= 135
+ * on gfx950), AK_EDEVICE / AK_ENOMEM when compiling or loading the compiled
+ * kernel fails.
  */
 int ak_eval_jacobian(const ak_mechanism *mech, ak_precision prec, const void *T, const void *P,
                      const void *Y, int64_t ldY, int64_t n_cells, void *J, int64_t ldJ,
                      void *stream);
+
+/*
+ * The same Jacobian in the interleaved (cell-minor) layout a batched solver
+ * with one lane per cell reads: entry (r, c) of cell i at
+ * J[(r * (NS+1) + c) * ldJ + i], ldJ >= n_cells, like Y and omega (species
+ * outermost).  Consecutive cells are adjacent, so the kernel's stores are
+ * contiguous across a wavefront; the cell-major layout of ak_eval_jacobian
+ * scatters them by the cell stride, which caps its write bandwidth.  Always
+ * the kernel compiled for the mechanism (generated and compiled at the first
+ * call for the mechanism and precision, as for ak_eval_jacobian), bitwise
+ * the same values as ak_eval_jacobian's compiled kernel.
+ * Errors: as ak_eval_source, plus AK_EINVAL for ldJ < n_cells,
+ * AK_EUNSUPPORTED for a mechanism without a compiled Jacobian (third-body or
+ * falloff reactions; more species than fit one 64-cell tile's LDS:
+ * 5 * 512 NS + 8 max(4 NR, 1024) + 12288 bytes <= 160 KB, and NS <= 64),
+ * AK_EDEVICE / AK_ENOMEM when compiling or loading it fails.
+ */
+int ak_eval_jacobian_interleaved(const ak_mechanism *mech, ak_precision prec, const void *T,
+                                 const void *P, const void *Y, int64_t ldY, int64_t n_cells,
+                                 void *J, int64_t ldJ, void *stream);
 
 /*
  * Vector-Jacobian product of omega (Eq. 2) with respect to (Y, T) at fixed P:

@@ -81,6 +81,11 @@ def lib():
         h.ak_jit_tables.argtypes = [C.POINTER(MechanismDesc), C.c_int, C.c_void_p, C.c_size_t,
                                     C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t),
                                     C.POINTER(C.c_size_t)]
+        h.ak_jit_jacobian_source.argtypes = [C.POINTER(MechanismDesc), C.c_int, C.c_int,
+                                             C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
+        h.ak_jit_jacobian_tables.argtypes = [C.POINTER(MechanismDesc), C.c_void_p, C.c_size_t,
+                                             C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t),
+                                             C.POINTER(C.c_size_t)]
         h.ak_integrate_euler.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_int64, C.c_int64, C.c_double, C.c_int,
                                          C.c_void_p]
@@ -90,6 +95,10 @@ def lib():
         h.ak_eval_source.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
         h.ak_error_count.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]
+        h.ak_mechanism_compiled_jacobian.argtypes = [C.c_void_p, C.c_int]
+        h.ak_eval_jacobian_interleaved.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                                   C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                                   C.c_int64, C.c_void_p]
         h.ak_eval_jacobian.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
         h.ak_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]
@@ -188,6 +197,34 @@ def jit_tables(src, precision: str = "fp32"):
     return sp, rx
 
 
+def jit_jacobian_source(src, precision: str = "fp64", interleaved: bool = False) -> str:
+    """HIP source text of the state Jacobian compiled for a mechanism (no GPU
+    needed); ``interleaved`` for the cell-minor output layout."""
+    d, keep = _desc(src)
+    prec = {"fp32": AK_FP32, "fp64": AK_FP64}[precision]
+    il = int(bool(interleaved))
+    need = C.c_size_t()
+    _check(lib().ak_jit_jacobian_source(C.byref(d), prec, il, None, 0, C.byref(need)))
+    buf = C.create_string_buffer(need.value)
+    _check(lib().ak_jit_jacobian_source(C.byref(d), prec, il, buf, need.value, C.byref(need)))
+    return buf.value.decode()
+
+
+def jit_jacobian_tables(src):
+    """(species table, reaction table) of the compiled Jacobian (no GPU
+    needed)."""
+    d, keep = _desc(src)
+    nsp, nrx = C.c_size_t(), C.c_size_t()
+    _check(lib().ak_jit_jacobian_tables(C.byref(d), None, 0, None, 0, C.byref(nsp),
+                                        C.byref(nrx)))
+    sp = np.zeros(nsp.value)
+    rx = np.zeros(nrx.value)
+    _check(lib().ak_jit_jacobian_tables(C.byref(d), sp.ctypes.data_as(C.c_void_p), sp.size,
+                                        rx.ctypes.data_as(C.c_void_p), rx.size, C.byref(nsp),
+                                        C.byref(nrx)))
+    return sp, rx
+
+
 class Mechanism:
     """A mechanism uploaded to one GPU.  ``src`` is any object with the
     attributes of ``synth.Mechanism`` (W, nu_f, nu_r, ln_A, beta, Ea,
@@ -227,6 +264,15 @@ class Mechanism:
         """Whether eval_source runs the mechanism-compiled kernel for the
         precision of ``dtype`` (torch.float32 or torch.float64)."""
         rc = lib().ak_mechanism_compiled(self._h, _prec(dtype))
+        if rc < 0:
+            _check(rc)
+        return rc == 1
+
+    def compiled_jacobian(self, dtype) -> bool:
+        """Whether the mechanism has a compiled state Jacobian (eval_jacobian
+        runs it unless AK_JIT_JACOBIAN=0; eval_jacobian_interleaved needs
+        it)."""
+        rc = lib().ak_mechanism_compiled_jacobian(self._h, _prec(dtype))
         if rc < 0:
             _check(rc)
         return rc == 1
@@ -303,6 +349,26 @@ def eval_jacobian(mech: Mechanism, T, P, Y, out=None, stream=None):
     _check(lib().ak_eval_jacobian(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
                                   Y.data_ptr(), ldY, n, out.data_ptr(), ldJ,
                                   _stream_ptr(stream)))
+    return out
+
+
+def eval_jacobian_interleaved(mech: Mechanism, T, P, Y, out=None, stream=None):
+    """The same Jacobian in the interleaved layout [NS+1, NS+1, n] (cells
+    innermost, like Y): out[r, c, i] = d x_r' / d x_c of cell i.  Always the
+    kernel compiled for the mechanism.  Asynchronous."""
+    torch = _torch()
+    n = _check_state(mech, T, P, Y)
+    nv = mech.n_species + 1
+    if out is None:
+        out = torch.empty((nv, nv, n), dtype=T.dtype, device=T.device)
+    elif (out.shape != (nv, nv, n) or out.dtype != T.dtype or not out.is_cuda
+          or out.stride(2) != 1 or out.stride(0) != nv * out.stride(1)):
+        raise ValueError("out must be a GPU [NS+1, NS+1, n] tensor, cells contiguous")
+    ldY = Y.stride(0) if mech.n_species > 1 else n
+    ldJ = out.stride(1) if nv * nv > 1 else n
+    _check(lib().ak_eval_jacobian_interleaved(mech.handle, _prec(T.dtype), T.data_ptr(),
+                                              P.data_ptr(), Y.data_ptr(), ldY, n,
+                                              out.data_ptr(), ldJ, _stream_ptr(stream)))
     return out
 
 

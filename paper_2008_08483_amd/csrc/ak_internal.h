@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <vector>
 
 #include "ak_device.h"
@@ -19,6 +20,16 @@ struct ak_mechanism {
     std::vector<int> rxn_order;         // file index of each sorted reaction
     ak::JitKernels jit[2];              // mechanism-compiled kernels per precision (FP64, FP32)
     bool pdep = false;                  // third-body or falloff reactions (compiled kernels only)
+    // what the compiled Jacobian is generated from (host copies, sorted order)
+    std::vector<ak::RxnAux> host_aux;
+    std::vector<ak::ThermoRec> host_th;
+    // the compiled Jacobian per precision and layout (cell-major,
+    // interleaved), built at the first call that uses it: state 0 not
+    // tried, 1 loaded
+    mutable std::mutex jac_mu;
+    mutable ak::JitKernels jac[2][2];
+    mutable int jac_state[2][2] = {{0, 0}, {0, 0}};
+    mutable unsigned char *jac_dev = nullptr;   // its constant tables
 };
 
 namespace ak {

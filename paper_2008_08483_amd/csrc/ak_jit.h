@@ -28,6 +28,7 @@ struct PdepRec {
 struct JitMech {
     int ns = 0, nr = 0;
     const SpeciesRec *sp = nullptr;   // [ns]
+    const ThermoRec *th = nullptr;    // [ns] NASA-7 coefficients
     const RxnRec *rx = nullptr;       // [nr]
     const RxnAux *aux = nullptr;      // [nr]
     const PdepRec *pd = nullptr;      // [nr], or null when all are elementary
@@ -93,16 +94,35 @@ JitProgram jit_program(const JitMech &m, bool f64);
 // which the waves then add up in a fixed order.
 JitProgram jit_program_tile(const JitMech &m, bool f64, int waves);
 
+// The state Jacobian (rows omega_1..omega_NS, omega_T; columns Y_1..Y_NS,
+// T) compiled for the mechanism: kernel ak_jac(T, P, Y, ldY, n, J, ldJ, SP,
+// RX, err), one 64-cell tile per workgroup of JitProgram::threads threads.
+// `f64out`: double states and J, else float (the arithmetic is double in
+// both).  `interleaved`: J[(row (NS+1) + col) ldJ + cell], else
+// J[cell ldJ + row (NS+1) + col].  Elementary reactions only.
+JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved = false);
+// Compiler options of that kernel beyond the common ones (the machine
+// scheduler that interleaves independent reactions: with two waves per SIMD
+// the kernel needs the instruction-level parallelism).
+std::vector<std::string> jac_compile_options();
+// LDS of a tile of the compiled Jacobian; the kernel needs it below the
+// device's 160 KB.
+size_t jac_lds_bytes(int ns, int nr);
+bool jac_suitable(const JitMech &m);
+
 // The form that suits the mechanism (lane-per-cell for small ones, tiled
 // otherwise).
 JitProgram jit_generate(const JitMech &m, bool f64);
 
 // Compile the text for gfx950 with hiprtc; returns 0 or an AK_E* code (the
 // compiler log goes to `log`).  Results are cached in the process by text.
-int jit_compile(const std::string &src, std::vector<char> &code, std::string &log);
+int jit_compile(const std::string &src, std::vector<char> &code, std::string &log,
+                const std::vector<std::string> &extra = {});
 
-// Load a code object on the current device.
-int jit_load(const std::vector<char> &code, JitKernels &out);
+// Load a code object on the current device; `fn` and `batch` (may be null)
+// are the kernels' names.
+int jit_load(const std::vector<char> &code, JitKernels &out, const char *fn = "ak_src",
+             const char *batch = "ak_src_batch");
 void jit_unload(JitKernels &k);
 
 hipError_t jit_launch(const JitKernels &k, const void *T, const void *P, const void *Y,

@@ -316,6 +316,7 @@ static JitMech jit_view(const Prepared &p)
     j.ns = (int)p.sp.size();
     j.nr = (int)p.rx.size();
     j.sp = p.sp.data();
+    j.th = p.th.data();
     j.rx = p.rx.data();
     j.aux = p.aux.data();
     j.pd = p.pdep ? p.pd.data() : nullptr;
@@ -356,6 +357,49 @@ int ak_jit_tables(const ak_mechanism_desc *d, ak_precision prec, double *sp, siz
     int rc = prepare(d, p);
     if (rc) return rc;
     const JitProgram prog = jit_generate(jit_view(p), prec == AK_FP64);
+    *n_sp = prog.sp.size();
+    *n_rx = prog.rx.size();
+    if (sp) std::memcpy(sp, prog.sp.data(), sizeof(double) * std::min(cap_sp, prog.sp.size()));
+    if (rx) std::memcpy(rx, prog.rx.data(), sizeof(double) * std::min(cap_rx, prog.rx.size()));
+    return AK_OK;
+}
+
+int ak_jit_jacobian_source(const ak_mechanism_desc *d, ak_precision prec, int interleaved,
+                           char *buf, size_t cap, size_t *needed)
+{
+    if (!d || !needed) return set_error(AK_EINVAL, "ak_jit_jacobian_source: null argument");
+    if (prec != AK_FP32 && prec != AK_FP64)
+        return set_error(AK_EINVAL, "ak_jit_jacobian_source: bad precision %d", (int)prec);
+    Prepared p;
+    int rc = prepare(d, p);
+    if (rc) return rc;
+    const JitMech jm = jit_view(p);
+    if (!jac_suitable(jm))
+        return set_error(AK_EUNSUPPORTED, "ak_jit_jacobian_source: no compiled Jacobian for this "
+                                          "mechanism (pressure-dependent reactions or %d species)",
+                         jm.ns);
+    const std::string src = jit_program_jac(jm, prec == AK_FP64, interleaved != 0).src;
+    *needed = src.size() + 1;
+    if (buf && cap > 0) {
+        const size_t n = std::min(cap - 1, src.size());
+        std::memcpy(buf, src.data(), n);
+        buf[n] = 0;
+    }
+    return AK_OK;
+}
+
+int ak_jit_jacobian_tables(const ak_mechanism_desc *d, double *sp, size_t cap_sp, double *rx,
+                           size_t cap_rx, size_t *n_sp, size_t *n_rx)
+{
+    if (!d || !n_sp || !n_rx) return set_error(AK_EINVAL, "ak_jit_jacobian_tables: null argument");
+    Prepared p;
+    int rc = prepare(d, p);
+    if (rc) return rc;
+    const JitMech jm = jit_view(p);
+    if (!jac_suitable(jm))
+        return set_error(AK_EUNSUPPORTED, "ak_jit_jacobian_tables: no compiled Jacobian for this "
+                                          "mechanism");
+    const JitProgram prog = jit_program_jac(jm, true);
     *n_sp = prog.sp.size();
     *n_rx = prog.rx.size();
     if (sp) std::memcpy(sp, prog.sp.data(), sizeof(double) * std::min(cap_sp, prog.sp.size()));
@@ -487,6 +531,8 @@ int ak_load_mechanism_ex(const ak_mechanism_desc *d, int device, int kernels, ak
         }
     }
     m->pdep = p.pdep;
+    m->host_aux = p.aux;
+    m->host_th = p.th;
     m->host_species = std::move(p.sp);
     m->host_rxn = std::move(p.rx);
     m->rxn_order = std::move(p.order);
@@ -498,7 +544,12 @@ int ak_free_mechanism(ak_mechanism *m)
 {
     if (!m) return AK_OK;
     DeviceGuard g(m->device);
-    for (int f = 0; f < 2; ++f) jit_unload(m->jit[f]);
+    for (int f = 0; f < 2; ++f) {
+        jit_unload(m->jit[f]);
+        jit_unload(m->jac[f][0]);
+        jit_unload(m->jac[f][1]);
+    }
+    if (m->jac_dev) (void)hipFree(m->jac_dev);
     (void)hipFree(m->dev);
     delete m;
     return AK_OK;
@@ -557,6 +608,84 @@ static int check_state(const char *fn, const ak_mechanism *m, ak_precision prec,
     return AK_OK;
 }
 
+}  // extern "C"
+
+namespace ak {
+
+namespace {
+
+JitMech jit_view(const ak_mechanism *m)
+{
+    JitMech j;
+    j.ns = m->ns;
+    j.nr = m->nr;
+    j.sp = m->host_species.data();
+    j.th = m->host_th.data();
+    j.rx = m->host_rxn.data();
+    j.aux = m->host_aux.data();
+    return j;
+}
+
+bool jac_wanted()
+{
+    const char *e = std::getenv("AK_JIT_JACOBIAN");
+    return !e || std::atoi(e) != 0;
+}
+
+bool jac_fits(const ak_mechanism *m) { return !m->pdep && jac_suitable(jit_view(m)); }
+
+// The compiled Jacobian of this precision and layout (1 interleaved),
+// generated, compiled and loaded on the first call that uses it (the device
+// is current).  Leaves jac_state[prec][layout] at 1 when it is there;
+// mechanisms it does not take keep the table-driven kernel.
+int compiled_jacobian(const ak_mechanism *m, ak_precision prec, int layout)
+{
+    std::lock_guard<std::mutex> l(m->jac_mu);
+    if (m->jac_state[prec][layout]) return AK_OK;
+    const JitMech jm = jit_view(m);
+    const JitProgram prog = jit_program_jac(jm, prec == AK_FP64, layout == 1);
+    std::vector<char> code;
+    std::string log;
+    int rc = jit_compile(prog.src, code, log, jac_compile_options());
+    if (rc) return set_error(rc, "ak_eval_jacobian: compiling the mechanism's Jacobian failed: %s",
+                             log.c_str());
+    if (!m->jac_dev) {
+        // the tables are the same for both precisions and layouts
+        const size_t o_rx = (sizeof(double) * prog.sp.size() + 255) & ~(size_t)255;
+        const size_t bytes = o_rx + sizeof(double) * prog.rx.size();
+        unsigned char *dev = nullptr;
+        hipError_t e = hipMalloc((void **)&dev, bytes);
+        if (e != hipSuccess)
+            return set_error(AK_ENOMEM, "ak_eval_jacobian: device allocation failed: %s",
+                             hipGetErrorString(e));
+        std::vector<unsigned char> host(bytes, 0);
+        std::memcpy(host.data(), prog.sp.data(), sizeof(double) * prog.sp.size());
+        std::memcpy(host.data() + o_rx, prog.rx.data(), sizeof(double) * prog.rx.size());
+        if ((e = hipMemcpy(dev, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(dev);
+            return hip_error(e, "ak_eval_jacobian: upload");
+        }
+        m->jac_dev = dev;
+        for (int f = 0; f < 2; ++f)
+            for (int y = 0; y < 2; ++y) {
+                m->jac[f][y].sp = (const double *)dev;
+                m->jac[f][y].rx = (const double *)(dev + o_rx);
+            }
+    }
+    JitKernels &k = m->jac[prec][layout];
+    if ((rc = jit_load(code, k, "ak_jac", nullptr))) return rc;
+    k.block = 64;
+    k.threads = prog.threads;
+    m->jac_state[prec][layout] = 1;
+    return AK_OK;
+}
+
+}  // namespace
+
+}  // namespace ak
+
+extern "C" {
+
 int ak_eval_jacobian(const ak_mechanism *m, ak_precision prec, const void *T, const void *P,
                      const void *Y, int64_t ldY, int64_t n, void *J, int64_t ldJ, void *stream)
 {
@@ -571,13 +700,52 @@ int ak_eval_jacobian(const ak_mechanism *m, ak_precision prec, const void *T, co
     if (m->pdep)
         return set_error(AK_EUNSUPPORTED, "ak_eval_jacobian: third-body and falloff reactions "
                                           "are not differentiated");
-    if (jacobian_lds_bytes(m->ns) > (size_t)m->lds_max)
+    const bool compiled = jac_wanted() && jac_fits(m);
+    if (jacobian_lds_bytes(m->ns) > (size_t)m->lds_max && !compiled)
         return set_error(AK_EUNSUPPORTED, "ak_eval_jacobian: %d species exceed the LDS", m->ns);
     DeviceGuard g(m->device);
     if (!g.ok) return set_error(AK_EDEVICE, "ak_eval_jacobian: cannot select device %d", m->device);
-    hipError_t e = jacobian_launch(m->view, m->lds_max, prec == AK_FP64, T, P, Y, ldY, n, J, ldJ,
-                                   (hipStream_t)stream);
+    if (compiled && (rc = compiled_jacobian(m, prec, 0))) return rc;
+    hipError_t e;
+    if (compiled)
+        e = jit_launch(m->jac[prec][0], T, P, Y, ldY, n, J, ldJ, m->view.err, (hipStream_t)stream);
+    else
+        e = jacobian_launch(m->view, m->lds_max, prec == AK_FP64, T, P, Y, ldY, n, J, ldJ,
+                            (hipStream_t)stream);
     if (e != hipSuccess) return hip_error(e, "ak_eval_jacobian: launch");
+    return AK_OK;
+}
+
+int ak_mechanism_compiled_jacobian(const ak_mechanism *m, ak_precision prec)
+{
+    if (!m || (prec != AK_FP32 && prec != AK_FP64))
+        return set_error(AK_EINVAL, "ak_mechanism_compiled_jacobian: bad argument");
+    return jac_fits(m) ? 1 : 0;
+}
+
+int ak_eval_jacobian_interleaved(const ak_mechanism *m, ak_precision prec, const void *T,
+                                 const void *P, const void *Y, int64_t ldY, int64_t n, void *J,
+                                 int64_t ldJ, void *stream)
+{
+    int rc = check_state("ak_eval_jacobian_interleaved", m, prec, T, P, Y, ldY, n);
+    if (rc) return rc;
+    if (n == 0) return AK_OK;
+    if (!J) return set_error(AK_EINVAL, "ak_eval_jacobian_interleaved: null J");
+    if (ldJ < n)
+        return set_error(AK_EINVAL, "ak_eval_jacobian_interleaved: ldJ=%lld < n_cells=%lld",
+                         (long long)ldJ, (long long)n);
+    if (!jac_fits(m))
+        return set_error(AK_EUNSUPPORTED, "ak_eval_jacobian_interleaved: no compiled Jacobian for "
+                                          "this mechanism (pressure-dependent reactions or %d "
+                                          "species)", m->ns);
+    DeviceGuard g(m->device);
+    if (!g.ok)
+        return set_error(AK_EDEVICE, "ak_eval_jacobian_interleaved: cannot select device %d",
+                         m->device);
+    if ((rc = compiled_jacobian(m, prec, 1))) return rc;
+    hipError_t e = jit_launch(m->jac[prec][1], T, P, Y, ldY, n, J, ldJ, m->view.err,
+                              (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "ak_eval_jacobian_interleaved: launch");
     return AK_OK;
 }
 

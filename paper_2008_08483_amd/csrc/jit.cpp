@@ -30,6 +30,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <string>
@@ -41,54 +42,9 @@
 #include "annkin.h"
 #include "ak_internal.h"
 #include "ak_jit.h"
+#include "jit_text.h"
 
 namespace ak {
-
-namespace {
-
-struct Text {
-    std::string s;
-    void operator()(const char *fmt, ...) __attribute__((format(printf, 2, 3)))
-    {
-        char buf[1024];
-        va_list ap;
-        va_start(ap, fmt);
-        const int n = vsnprintf(buf, sizeof buf, fmt, ap);
-        va_end(ap);
-        if (n >= (int)sizeof buf) {
-            std::vector<char> big(n + 1);
-            va_start(ap, fmt);
-            vsnprintf(big.data(), big.size(), fmt, ap);
-            va_end(ap);
-            s.append(big.data(), n);
-        } else {
-            s.append(buf, n);
-        }
-    }
-};
-
-// exact decimal-free spelling of a double for the generated text
-std::string lit(double x)
-{
-    char b[64];
-    snprintf(b, sizeof b, "%a", x);
-    return b;
-}
-
-// ln(2)^k / k!, the Taylor coefficients of 2^f, rounded to double
-std::vector<double> exp2_taylor(int deg)
-{
-    std::vector<double> c(deg + 1);
-    long double t = 1.0L;
-    const long double ln2 = 0.693147180559945309417232121458176568L;
-    for (int k = 0; k <= deg; ++k) {
-        c[k] = (double)t;
-        t = t * ln2 / (long double)(k + 1);
-    }
-    return c;
-}
-
-}  // namespace
 
 bool jit_suitable(int ns, bool f64)
 {
@@ -112,18 +68,6 @@ double g2_host(const SpeciesRec &s, double T)
     const double *c = T >= s.T_mid ? s.hi : s.lo;
     return c[0] * std::log(T) + c[1] * T + c[2] * T * T + c[3] * T * T * T +
            c[4] * T * T * T * T + c[5] / T + c[6];
-}
-
-// Species of each reaction, each once.
-std::vector<std::vector<int>> reaction_species(const JitMech &m)
-{
-    std::vector<std::vector<int>> rs(m.nr);
-    for (int j = 0; j < m.nr; ++j)
-        for (int i = 0; i < m.aux[j].nf + m.aux[j].nr; ++i) {
-            const int k = m.aux[j].sp[i];
-            if (std::find(rs[j].begin(), rs[j].end(), k) == rs[j].end()) rs[j].push_back(k);
-        }
-    return rs;
 }
 
 // Order of the reactions in the generated code.  A species' registers are
@@ -1055,7 +999,7 @@ uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull)
 
 // optional on-disk cache of code objects (AK_JIT_CACHE_DIR, else
 // $HOME/.cache/annkin; "off" disables it)
-std::string cache_path(const std::string &src)
+std::string cache_path(const std::string &src, const std::vector<std::string> &extra)
 {
     const char *dir = std::getenv("AK_JIT_CACHE_DIR");
     std::string d;
@@ -1069,6 +1013,7 @@ std::string cache_path(const std::string &src)
     }
     std::string key = src;
     for (const char *opt : kOpts) key += opt;
+    for (const std::string &opt : extra) key += opt;
     int ver_major = 0, ver_minor = 0;
     hiprtcVersion(&ver_major, &ver_minor);
     key += std::to_string(ver_major) + "." + std::to_string(ver_minor);
@@ -1118,20 +1063,23 @@ void write_file(const std::string &p, const std::vector<char> &data)
 
 }  // namespace
 
-int jit_compile(const std::string &src, std::vector<char> &code, std::string &log)
+int jit_compile(const std::string &src, std::vector<char> &code, std::string &log,
+                const std::vector<std::string> &extra)
 {
+    std::string key = src;
+    for (const std::string &opt : extra) key += "\n// " + opt;
     {
         std::lock_guard<std::mutex> l(g_cache_mu);
-        auto it = g_cache.find(src);
+        auto it = g_cache.find(key);
         if (it != g_cache.end()) {
             code = it->second;
             return AK_OK;
         }
     }
-    const std::string path = cache_path(src);
+    const std::string path = cache_path(src, extra);
     if (!path.empty() && read_file(path, code)) {
         std::lock_guard<std::mutex> l(g_cache_mu);
-        g_cache[src] = code;
+        g_cache[key] = code;
         return AK_OK;
     }
     hiprtcProgram prog;
@@ -1140,8 +1088,9 @@ int jit_compile(const std::string &src, std::vector<char> &code, std::string &lo
         log = "hiprtcCreateProgram failed";
         return AK_EDEVICE;
     }
-    const hiprtcResult r =
-        hiprtcCompileProgram(prog, (int)(sizeof kOpts / sizeof kOpts[0]), kOpts);
+    std::vector<const char *> opts(std::begin(kOpts), std::end(kOpts));
+    for (const std::string &opt : extra) opts.push_back(opt.c_str());
+    const hiprtcResult r = hiprtcCompileProgram(prog, (int)opts.size(), opts.data());
     size_t ls = 0;
     if (hiprtcGetProgramLogSize(prog, &ls) == HIPRTC_SUCCESS && ls > 1) {
         std::vector<char> b(ls + 1, 0);
@@ -1167,16 +1116,16 @@ int jit_compile(const std::string &src, std::vector<char> &code, std::string &lo
     }
     if (!path.empty()) write_file(path, code);
     std::lock_guard<std::mutex> l(g_cache_mu);
-    g_cache[src] = code;
+    g_cache[key] = code;
     return AK_OK;
 }
 
-int jit_load(const std::vector<char> &code, JitKernels &out)
+int jit_load(const std::vector<char> &code, JitKernels &out, const char *fn, const char *batch)
 {
     hipError_t e = hipModuleLoadData(&out.mod, code.data());
     if (e != hipSuccess) return hip_error(e, "loading the mechanism's kernels");
-    if ((e = hipModuleGetFunction(&out.src, out.mod, "ak_src")) != hipSuccess ||
-        (e = hipModuleGetFunction(&out.batch, out.mod, "ak_src_batch")) != hipSuccess) {
+    if ((e = hipModuleGetFunction(&out.src, out.mod, fn)) != hipSuccess ||
+        (batch && (e = hipModuleGetFunction(&out.batch, out.mod, batch)) != hipSuccess)) {
         (void)hipModuleUnload(out.mod);
         out.mod = nullptr;
         return hip_error(e, "finding the mechanism's kernels");

@@ -5,6 +5,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -115,3 +117,26 @@ def test_pressure_dependent_descriptor_checks():
         with pytest.raises(annkin.AnnkinError) as e:
             annkin.jit_source(m, "fp32")
         assert e.value.code == -1, annkin.lib().ak_last_error()
+
+
+def test_compiled_jacobian_generation_without_gpu():
+    """The Jacobian generator runs on the host: both layouts, one kernel, the
+    tables' sizes (32 doubles per species, 4 per reaction), and the refusal
+    of pressure-dependent mechanisms."""
+    from paper_2008_08483_amd import annkin, synth
+
+    src = synth.make_mechanism(9, 21)
+    for prec in ("fp32", "fp64"):
+        a = annkin.jit_jacobian_source(src, prec)
+        b = annkin.jit_jacobian_source(src, prec, interleaved=True)
+        assert 'extern "C" __global__' in a and "void ak_jac(" in a
+        assert "cell-major J" in a and "interleaved J" in b
+        assert a.count("__syncthreads()") == b.count("__syncthreads()")
+    sp, rx = annkin.jit_jacobian_tables(src)
+    assert sp.shape == (32 * 9,) and rx.shape == (4 * 21,)
+    # NASA-7 sets copied as given: low range of species 0
+    assert np.allclose(sp[16:23], src.nasa_low[0])
+    pd = synth.with_pressure_dependence(src, frac=0.5)
+    with pytest.raises(annkin.AnnkinError) as e:
+        annkin.jit_jacobian_source(pd, "fp64")
+    assert e.value.code == -7
