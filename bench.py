@@ -332,32 +332,60 @@ def serving_bench(torch, annkin, n_req=10000, warmup=500, trials=3):
 
 def deriv_bench(torch, annkin, steps=10):
     """Differentiation configuration: 53/325 mechanism x 65,536 cells; the
-    dense 54 x 54 per-cell Jacobian and the VJP, FP64 and FP32 states."""
+    dense 54 x 54 per-cell Jacobian (compiled kernel in both output layouts,
+    and the table-driven kernel beside it) and the VJP, FP64 and FP32 states.
+    The Jacobian's roofline is its HBM write (n (NS+1)^2 elements)."""
     src, T, P, Y = synth.workload("c4")
     mech = annkin.Mechanism(src)
     n, nv = T.shape[0], src.n_species + 1
-    out = {"workload": f"{src.n_species}sp/{src.n_reactions}rxn synthetic mechanism x {n} cells"}
+    out = {"workload": f"{src.n_species}sp/{src.n_reactions}rxn synthetic mechanism x {n} cells",
+           "jacobian_kernel": "compiled" if mech.compiled_jacobian(torch.float64) else "table"}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
     for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
         Tt, Pt, Yt = (torch.tensor(a, dtype=dt, device="cuda") for a in (T, P, Y))
         J = torch.empty((n, nv, nv), dtype=dt, device="cuda")
         g = torch.randn((src.n_species, n), dtype=dt, device="cuda")
         res = {}
-        for what, fn in (("jacobian", lambda: annkin.eval_jacobian(mech, Tt, Pt, Yt, out=J)),
-                         ("vjp", lambda: annkin.eval_vjp(mech, Tt, Pt, Yt, g))):
-            fn()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(steps):
-                fn()
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / steps
+        es = 8 if dt == torch.float64 else 4
+        jbytes = n * nv * nv * es
+        legs = [("jacobian", lambda: annkin.eval_jacobian(mech, Tt, Pt, Yt, out=J)),
+                ("vjp", lambda: annkin.eval_vjp(mech, Tt, Pt, Yt, g))]
+        if mech.compiled_jacobian(dt):
+            Ji = torch.empty((nv, nv, n), dtype=dt, device="cuda")
+            legs.append(("jacobian_interleaved",
+                         lambda: annkin.eval_jacobian_interleaved(mech, Tt, Pt, Yt, out=Ji)))
+        for what, fn in legs:
+            ms = timed(fn)
             res[what + "_ms"] = ms
             res[what + "_per_s"] = n / (ms * 1e-3)
-        es = 8 if dt == torch.float64 else 4
-        res["jacobian_write_GBps"] = n * nv * nv * es / (res["jacobian_ms"] * 1e-3) / 1e9
-        res["jacobian_write_frac_of_hbm"] = res["jacobian_write_GBps"] * 1e9 / roofline.PEAK_HBM
+            if what.startswith("jacobian"):
+                res[what + "_write_GBps"] = jbytes / (ms * 1e-3) / 1e9
+                res[what + "_write_frac_of_hbm"] = jbytes / (ms * 1e-3) / roofline.PEAK_HBM
+        if mech.compiled_jacobian(dt):
+            # bitwise: repeated calls and the two layouts
+            J2 = annkin.eval_jacobian(mech, Tt, Pt, Yt)
+            torch.cuda.synchronize()
+            res["jacobian_bitwise_repeat"] = bool(torch.equal(J, J2))
+            res["jacobian_layouts_bitwise_equal"] = bool(torch.equal(J.permute(1, 2, 0), Ji))
+            del J2, Ji
+            os.environ["AK_JIT_JACOBIAN"] = "0"
+            try:
+                res["jacobian_table_kernel_ms"] = timed(
+                    lambda: annkin.eval_jacobian(mech, Tt, Pt, Yt, out=J))
+            finally:
+                del os.environ["AK_JIT_JACOBIAN"]
+        res["jacobian_roofline_ms"] = jbytes / roofline.PEAK_HBM * 1e3
         out[name] = res
         del Tt, Pt, Yt, J, g
     mech.close()
@@ -379,6 +407,8 @@ def main():
     ap.add_argument("--no-pdep", action="store_true")
     ap.add_argument("--only-main", action="store_true",
                     help="time only the main FP32 leg (for profiler runs)")
+    ap.add_argument("--only-deriv", action="store_true",
+                    help="time only the differentiation configuration (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -390,6 +420,10 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.only_deriv:
+        from paper_2008_08483_amd import annkin
+        print(json.dumps({"differentiation": deriv_bench(torch, annkin)}), flush=True)
+        return
     from paper_2008_08483_amd import annkin
 
     if not torch.cuda.is_available():

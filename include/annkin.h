@@ -193,15 +193,16 @@ int ak_jit_tables(const ak_mechanism_desc *desc, ak_precision prec, double *sp, 
                   double *rx, size_t cap_rx, size_t *n_sp, size_t *n_rx);
 
 /*
- * Diagnostic, no device needed: the HIP source text of the state Jacobian
- * compiled for a mechanism (what ak_eval_jacobian, interleaved = 0, or
- * ak_eval_jacobian_interleaved, interleaved = 1, compiles at its first call
- * for the mechanism and precision), same buffer convention as
- * ak_jit_source.  Errors: as ak_jit_source, plus AK_EUNSUPPORTED for a
- * mechanism without a compiled Jacobian (third-body or falloff reactions,
- * more species than the compiled form takes).
+ * Diagnostic, no device needed: the HIP source text of a derivative kernel
+ * compiled for a mechanism, what the first call for the mechanism and
+ * precision compiles: variant 0 ak_eval_jacobian's, 1
+ * ak_eval_jacobian_interleaved's, 2 ak_eval_vjp's.  Same buffer convention
+ * as ak_jit_source.  Errors: as ak_jit_source, plus AK_EINVAL for another
+ * variant and AK_EUNSUPPORTED for a mechanism without compiled derivatives
+ * (third-body or falloff reactions, more species than the compiled form
+ * takes).
  */
-int ak_jit_jacobian_source(const ak_mechanism_desc *desc, ak_precision prec, int interleaved,
+int ak_jit_jacobian_source(const ak_mechanism_desc *desc, ak_precision prec, int variant,
                            char *buf, size_t cap, size_t *needed);
 
 /*
@@ -294,7 +295,14 @@ int ak_eval_jacobian_interleaved(const ak_mechanism *mech, ak_precision prec, co
  * given g_omega [NS][ldG], returns g_Y[m] = sum_k g_omega_k d omega_k / dY_m
  * ([NS][ldGY]) and g_T = sum_k g_omega_k d omega_k / dT ([n_cells]), without
  * forming the Jacobian.  Same clamp convention as ak_eval_jacobian.
- * Errors: as ak_eval_source, plus AK_EINVAL for ldG or ldGY < n_cells.
+ * Mechanisms with a compiled Jacobian (ak_mechanism_compiled_jacobian) use a
+ * kernel compiled the same way: with gamma_j = sum_k g_omega_k nu_kj every
+ * wave of a 64-cell tile sweeps a share of the reactions once and the
+ * waves' sums are added in a fixed order, so results are bitwise
+ * reproducible (compiled at the first call, as for ak_eval_jacobian).
+ * Others, or AK_JIT_VJP=0, use the table-driven kernel (LDS atomics).
+ * Errors: as ak_eval_source, plus AK_EINVAL for ldG or ldGY < n_cells,
+ * AK_EDEVICE / AK_ENOMEM when compiling or loading the compiled kernel fails.
  */
 int ak_eval_vjp(const ak_mechanism *mech, ak_precision prec, const void *T, const void *P,
                 const void *Y, int64_t ldY, int64_t n_cells, const void *g_omega, int64_t ldG,

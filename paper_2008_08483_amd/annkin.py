@@ -197,12 +197,14 @@ def jit_tables(src, precision: str = "fp32"):
     return sp, rx
 
 
-def jit_jacobian_source(src, precision: str = "fp64", interleaved: bool = False) -> str:
+def jit_jacobian_source(src, precision: str = "fp64", interleaved: bool = False,
+                        vjp: bool = False) -> str:
     """HIP source text of the state Jacobian compiled for a mechanism (no GPU
-    needed); ``interleaved`` for the cell-minor output layout."""
+    needed); ``interleaved`` for the cell-minor output layout, ``vjp`` for
+    the vector-Jacobian product instead."""
     d, keep = _desc(src)
     prec = {"fp32": AK_FP32, "fp64": AK_FP64}[precision]
-    il = int(bool(interleaved))
+    il = 2 if vjp else int(bool(interleaved))
     need = C.c_size_t()
     _check(lib().ak_jit_jacobian_source(C.byref(d), prec, il, None, 0, C.byref(need)))
     buf = C.create_string_buffer(need.value)

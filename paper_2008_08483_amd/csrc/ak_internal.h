@@ -29,7 +29,10 @@ struct ak_mechanism {
     mutable std::mutex jac_mu;
     mutable ak::JitKernels jac[2][2];
     mutable int jac_state[2][2] = {{0, 0}, {0, 0}};
-    mutable unsigned char *jac_dev = nullptr;   // its constant tables
+    // the compiled vector-Jacobian product per precision (same tables)
+    mutable ak::JitKernels vjp[2];
+    mutable int vjp_state[2] = {0, 0};
+    mutable unsigned char *jac_dev = nullptr;   // their constant tables
 };
 
 namespace ak {

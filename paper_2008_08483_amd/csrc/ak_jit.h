@@ -101,6 +101,13 @@ JitProgram jit_program_tile(const JitMech &m, bool f64, int waves);
 // both).  `interleaved`: J[(row (NS+1) + col) ldJ + cell], else
 // J[cell ldJ + row (NS+1) + col].  Elementary reactions only.
 JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved = false);
+// The vector-jacobian product of omega compiled for the mechanism: kernel
+// ak_vjp(T, P, Y, ldY, n, G, ldG, GY, ldGY, GT, SP, RX, err) (layouts of
+// ak_eval_vjp), the same tiles, tables and limits as the Jacobian.
+JitProgram jit_program_vjp(const JitMech &m, bool f64out);
+hipError_t jit_vjp_launch(const JitKernels &k, const void *T, const void *P, const void *Y,
+                          int64_t ldY, int64_t n, const void *G, int64_t ldG, void *GY,
+                          int64_t ldGY, void *GT, unsigned long long *err, hipStream_t st);
 // Compiler options of that kernel beyond the common ones (the machine
 // scheduler that interleaves independent reactions: with two waves per SIMD
 // the kernel needs the instruction-level parallelism).

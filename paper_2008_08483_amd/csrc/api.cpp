@@ -364,7 +364,7 @@ int ak_jit_tables(const ak_mechanism_desc *d, ak_precision prec, double *sp, siz
     return AK_OK;
 }
 
-int ak_jit_jacobian_source(const ak_mechanism_desc *d, ak_precision prec, int interleaved,
+int ak_jit_jacobian_source(const ak_mechanism_desc *d, ak_precision prec, int variant,
                            char *buf, size_t cap, size_t *needed)
 {
     if (!d || !needed) return set_error(AK_EINVAL, "ak_jit_jacobian_source: null argument");
@@ -378,7 +378,10 @@ int ak_jit_jacobian_source(const ak_mechanism_desc *d, ak_precision prec, int in
         return set_error(AK_EUNSUPPORTED, "ak_jit_jacobian_source: no compiled Jacobian for this "
                                           "mechanism (pressure-dependent reactions or %d species)",
                          jm.ns);
-    const std::string src = jit_program_jac(jm, prec == AK_FP64, interleaved != 0).src;
+    if (variant < 0 || variant > 2)
+        return set_error(AK_EINVAL, "ak_jit_jacobian_source: bad variant %d", variant);
+    const std::string src = variant == 2 ? jit_program_vjp(jm, prec == AK_FP64).src
+                                         : jit_program_jac(jm, prec == AK_FP64, variant == 1).src;
     *needed = src.size() + 1;
     if (buf && cap > 0) {
         const size_t n = std::min(cap - 1, src.size());
@@ -548,6 +551,7 @@ int ak_free_mechanism(ak_mechanism *m)
         jit_unload(m->jit[f]);
         jit_unload(m->jac[f][0]);
         jit_unload(m->jac[f][1]);
+        jit_unload(m->vjp[f]);
     }
     if (m->jac_dev) (void)hipFree(m->jac_dev);
     (void)hipFree(m->dev);
@@ -634,20 +638,29 @@ bool jac_wanted()
 
 bool jac_fits(const ak_mechanism *m) { return !m->pdep && jac_suitable(jit_view(m)); }
 
-// The compiled Jacobian of this precision and layout (1 interleaved),
-// generated, compiled and loaded on the first call that uses it (the device
-// is current).  Leaves jac_state[prec][layout] at 1 when it is there;
-// mechanisms it does not take keep the table-driven kernel.
-int compiled_jacobian(const ak_mechanism *m, ak_precision prec, int layout)
+bool vjp_wanted()
+{
+    const char *e = std::getenv("AK_JIT_VJP");
+    return !e || std::atoi(e) != 0;
+}
+
+// The compiled derivative kernel `which` (0 the cell-major Jacobian, 1 the
+// interleaved one, 2 the VJP) of this precision, generated, compiled and
+// loaded on the first call that uses it (the device is current; the caller
+// has checked jac_fits).
+int compiled_jacobian(const ak_mechanism *m, ak_precision prec, int which)
 {
     std::lock_guard<std::mutex> l(m->jac_mu);
-    if (m->jac_state[prec][layout]) return AK_OK;
+    int &state = which == 2 ? m->vjp_state[prec] : m->jac_state[prec][which];
+    JitKernels &k = which == 2 ? m->vjp[prec] : m->jac[prec][which];
+    if (state) return AK_OK;
     const JitMech jm = jit_view(m);
-    const JitProgram prog = jit_program_jac(jm, prec == AK_FP64, layout == 1);
+    const JitProgram prog = which == 2 ? jit_program_vjp(jm, prec == AK_FP64)
+                                       : jit_program_jac(jm, prec == AK_FP64, which == 1);
     std::vector<char> code;
     std::string log;
     int rc = jit_compile(prog.src, code, log, jac_compile_options());
-    if (rc) return set_error(rc, "ak_eval_jacobian: compiling the mechanism's Jacobian failed: %s",
+    if (rc) return set_error(rc, "compiling the mechanism's derivative kernel failed: %s",
                              log.c_str());
     if (!m->jac_dev) {
         // the tables are the same for both precisions and layouts
@@ -666,17 +679,19 @@ int compiled_jacobian(const ak_mechanism *m, ak_precision prec, int layout)
             return hip_error(e, "ak_eval_jacobian: upload");
         }
         m->jac_dev = dev;
-        for (int f = 0; f < 2; ++f)
+        for (int f = 0; f < 2; ++f) {
             for (int y = 0; y < 2; ++y) {
                 m->jac[f][y].sp = (const double *)dev;
                 m->jac[f][y].rx = (const double *)(dev + o_rx);
             }
+            m->vjp[f].sp = (const double *)dev;
+            m->vjp[f].rx = (const double *)(dev + o_rx);
+        }
     }
-    JitKernels &k = m->jac[prec][layout];
-    if ((rc = jit_load(code, k, "ak_jac", nullptr))) return rc;
+    if ((rc = jit_load(code, k, which == 2 ? "ak_vjp" : "ak_jac", nullptr))) return rc;
     k.block = 64;
     k.threads = prog.threads;
-    m->jac_state[prec][layout] = 1;
+    state = 1;
     return AK_OK;
 }
 
@@ -763,12 +778,16 @@ int ak_eval_vjp(const ak_mechanism *m, ak_precision prec, const void *T, const v
     if (m->pdep)
         return set_error(AK_EUNSUPPORTED, "ak_eval_vjp: third-body and falloff reactions are "
                                           "not differentiated");
-    if (m->vjp_tile < 16)
+    const bool compiled = vjp_wanted() && jac_fits(m);
+    if (m->vjp_tile < 16 && !compiled)
         return set_error(AK_EUNSUPPORTED, "ak_eval_vjp: %d species exceed the LDS", m->ns);
     DeviceGuard g(m->device);
     if (!g.ok) return set_error(AK_EDEVICE, "ak_eval_vjp: cannot select device %d", m->device);
-    hipError_t e = vjp_launch(m->view, m->vjp_tile, prec == AK_FP64, T, P, Y, ldY, n, g_omega,
-                              ldG, g_Y, ldGY, g_T, (hipStream_t)stream);
+    if (compiled && (rc = compiled_jacobian(m, prec, 2))) return rc;
+    hipError_t e = compiled ? jit_vjp_launch(m->vjp[prec], T, P, Y, ldY, n, g_omega, ldG, g_Y,
+                                             ldGY, g_T, m->view.err, (hipStream_t)stream)
+                            : vjp_launch(m->view, m->vjp_tile, prec == AK_FP64, T, P, Y, ldY, n,
+                                         g_omega, ldG, g_Y, ldGY, g_T, (hipStream_t)stream);
     if (e != hipSuccess) return hip_error(e, "ak_eval_vjp: launch");
     return AK_OK;
 }

@@ -1156,6 +1156,21 @@ hipError_t jit_launch(const JitKernels &k, const void *T, const void *P, const v
                                  nullptr);
 }
 
+hipError_t jit_vjp_launch(const JitKernels &k, const void *T, const void *P, const void *Y,
+                          int64_t ldY, int64_t n, const void *G, int64_t ldG, void *GY,
+                          int64_t ldGY, void *GT, unsigned long long *err, hipStream_t st)
+{
+    const int64_t blocks = (n + k.block - 1) / k.block;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const double *SP = k.sp, *RX = k.rx;
+    void *args[] = {(void *)&T,  (void *)&P,    (void *)&Y,  (void *)&ldY, (void *)&n,
+                    (void *)&G,  (void *)&ldG,  (void *)&GY, (void *)&ldGY, (void *)&GT,
+                    (void *)&SP, (void *)&RX,   (void *)&err};
+    return hipModuleLaunchKernel(k.src, (unsigned)blocks, 1, 1, k.threads, 1, 1, 0, st, args,
+                                 nullptr);
+}
+
 hipError_t jit_batch_launch(const JitKernels &k, const JitBatchDesc *d_desc, int nreq,
                             int64_t blocks, unsigned long long *err, hipStream_t st)
 {

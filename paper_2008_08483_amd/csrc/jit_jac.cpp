@@ -80,6 +80,7 @@ std::string A(int k) { return "a_" + std::to_string(k); }
 std::string V(int k) { return "v_" + std::to_string(k); }
 std::string Wv(int k) { return "w_" + std::to_string(k); }
 std::string H(int k) { return "h_" + std::to_string(k); }
+std::string Gw(int k) { return "g_" + std::to_string(k); }
 
 struct Lds {
     // LDS read of the value `q` (0 a, 1 v, 2 w, 3 h) of species k; the row
@@ -88,6 +89,12 @@ struct Lds {
     std::string read(int q, int k) const
     {
         static const char *reg[4] = {"Ra", "Rv", "Rw", "Rh"};
+        if (q == 4) {
+            // the VJP's g_omega (in the place of the clamp flags)
+            char b[64];
+            snprintf(b, sizeof b, "LD(bf, %d)", 512 * k);
+            return b;
+        }
         if (k == row) return reg[q];
         // a and v' from the low base, w and h from the high one (two arrays
         // past it): every offset fits an LDS instruction's 16-bit immediate
@@ -102,15 +109,17 @@ struct Lds {
 // Derivatives of reaction j (position p of the wave's walk) at the lane's
 // cell, as locals of the enclosing block: qf, qr, qn, uf (= n_f q_f - n_r
 // q_r), dqT (= dq/dT at fixed Y), dH (= sum nu h, if `want_dH` or
-// reversible), and for each species l of the reaction d<l> = |dq/dC_l|
-// with sign s<l> (+1 / -1 / 0 when d<l> already carries its sign).
+// reversible), ga (= sum nu g_omega, if `want_gamma`), and for each species
+// l of the reaction d<l> = |dq/dC_l| with sign s<l> (+1 / -1 / 0 when d<l>
+// already carries its sign).
 struct Deriv {
     std::vector<int> sp;      // species of the reaction
     std::vector<int> sign;    // sign of d<l> in dq/dC_l
 };
 
 Deriv emit_jac_rxn(Text &o, const char *ind, const JitMech &m, bool f64out, int p, int j,
-                   const std::vector<int> &rsj, bool want_dH, const Lds &L)
+                   const std::vector<int> &rsj, bool want_dH, const Lds &L,
+                   bool want_gamma = false)
 {
     const RxnAux &x = m.aux[j];
     const int nf = x.nf, np = x.nr;
@@ -130,6 +139,20 @@ Deriv emit_jac_rxn(Text &o, const char *ind, const JitMech &m, bool f64out, int 
         if (deriv) o("%sconst double %s = %s;\n", ind, Wv(k).c_str(), L.read(2, k).c_str());
         if (need_h && mf[i] != mr[i])
             o("%sconst double %s = %s;\n", ind, H(k).c_str(), L.read(3, k).c_str());
+        if (want_gamma && mf[i] != mr[i])
+            o("%sconst double %s = %s;\n", ind, Gw(k).c_str(), L.read(4, k).c_str());
+    }
+    if (want_gamma) {
+        // the reaction's weight in the VJP: sum_k nu_kj g_omega_k
+        std::string s;
+        for (size_t i = 0; i < rsj.size(); ++i) {
+            const int nu = mr[i] - mf[i];
+            if (!nu) continue;
+            if (s.empty()) s = nu == 1 ? Gw(rsj[i]) : nu == -1 ? "-" + Gw(rsj[i]) :
+                               std::to_string(nu) + ".0 * " + Gw(rsj[i]);
+            else s = "__builtin_fma(" + std::to_string(nu) + ".0, " + Gw(rsj[i]) + ", " + s + ")";
+        }
+        o("%sconst double ga = %s;\n", ind, s.empty() ? "0.0" : s.c_str());
     }
     // k_f prod_r v with the reactants' 1/W folded into the Arrhenius bias:
     // E' = 2^(t'), t' = log2 k_f - sum_r log2 W_r, and v' = W v
@@ -265,15 +288,27 @@ bool jac_suitable(const JitMech &m)
     return jac_lds_bytes(m.ns, m.nr) <= 160 * 1024 && 2 * 512 * m.ns <= 65536;
 }
 
-JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
+namespace {
+
+// The Jacobian kernel, or with `vjp` the vector-Jacobian product of omega:
+// g_Y[m] = sum_k g_k d omega_k/dY_m, g_T = sum_k g_k d omega_k/dT.  With
+// gamma_j = sum_k nu_kj g_k these are the temperature row's sums with gamma_j
+// in the place of dH_j:
+//     g_Y[m] = f_m (rho_hat sum_j gamma_j dq_j/dC_m - sum_j gamma_j uf_j / sigma)
+//     g_T    = sum_j gamma_j dq_j/dT
+// so every wave sweeps a share of the reactions once, and the waves' sums are
+// added in a fixed order.
+JitProgram gen_deriv(const JitMech &m, bool f64out, bool interleaved, bool vjp)
 {
     const int ns = m.ns, nr = m.nr, nv = ns + 1;
     const int W = kJacWaves;
-    const int WT = kJacTempWaves;
+    const int WT = vjp ? W : kJacTempWaves;   // waves that sweep all reactions
     const int WR = W - WT;
     int group = 3;
     if (const char *g = std::getenv("AK_JAC_GROUP")) group = std::max(1, std::atoi(g));
     // the temperature-row waves hold NS + 3 more sums: smaller groups
+    bool xcd = true;
+    if (const char *e = std::getenv("AK_JAC_XCD")) xcd = std::atoi(e) != 0;
     int tgroup = 2;
     if (const char *g = std::getenv("AK_JAC_TGROUP")) tgroup = std::max(1, std::atoi(g));
     const char *IO = f64out ? "double" : "float";
@@ -365,9 +400,14 @@ JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
     }
 
     Text o;
-    o("// generated by libannkin: state Jacobian for a mechanism of %d species and %d "
-      "reactions (%s states and output, %s, one 64-cell tile per %d-wave workgroup)\n", ns, nr,
-      f64out ? "FP64" : "FP32", interleaved ? "interleaved J" : "cell-major J", W);
+    if (vjp)
+        o("// generated by libannkin: vector-Jacobian product of the source term for a mechanism "
+          "of %d species and %d reactions (%s states, one 64-cell tile per %d-wave workgroup)\n",
+          ns, nr, f64out ? "FP64" : "FP32", W);
+    else
+        o("// generated by libannkin: state Jacobian for a mechanism of %d species and %d "
+          "reactions (%s states and output, %s, one 64-cell tile per %d-wave workgroup)\n", ns,
+          nr, f64out ? "FP64" : "FP32", interleaved ? "interleaved J" : "cell-major J", W);
     o("typedef long long i64;\ntypedef unsigned long long u64;\n");
     const std::vector<double> c = exp2_taylor(12);
     // 2^t: degree-12 Taylor polynomial of 2^f, |f| <= 1/2 (below one ulp of
@@ -390,10 +430,17 @@ JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
     const int LR = LF + 64 * ns;
     const int LX = LR + jac_rx_doubles(nr);
     o("#define AK_JAC_LDS __shared__ double L[%d];\n", LX + 3 * 64 * W);
-    o("__device__ __forceinline__ void tile(i64 c0, i64 n, const %s *__restrict__ Tg, "
-      "const %s *__restrict__ Pg, const %s *__restrict__ Yg, i64 ldY, %s *__restrict__ Jg, "
-      "i64 ldJ, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err, "
-      "double *L) {\n", IO, IO, IO, IO);
+    if (vjp)
+        o("__device__ __forceinline__ void tile(i64 c0, i64 n, const %s *__restrict__ Tg, "
+          "const %s *__restrict__ Pg, const %s *__restrict__ Yg, i64 ldY, "
+          "const %s *__restrict__ Gg, i64 ldG, %s *__restrict__ GYg, i64 ldGY, "
+          "%s *__restrict__ GTg, const double *__restrict__ SP, const double *__restrict__ RX, "
+          "u64 *err, double *L) {\n", IO, IO, IO, IO, IO, IO);
+    else
+        o("__device__ __forceinline__ void tile(i64 c0, i64 n, const %s *__restrict__ Tg, "
+          "const %s *__restrict__ Pg, const %s *__restrict__ Yg, i64 ldY, %s *__restrict__ Jg, "
+          "i64 ldJ, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err, "
+          "double *L) {\n", IO, IO, IO, IO);
     // L: a [ns][64] | v' [ns][64] | w [ns][64] | h [ns][64] | f [ns][64] | partials
     o("  const unsigned lane = threadIdx.x & 63u;\n");
     o("  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));\n");
@@ -408,11 +455,15 @@ JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
     for (int k = 0; k < ns; ++k) own[k % W].push_back(k);
     const int maxown = (ns + W - 1) / W;
     o("  double ys[%d];\n  double sgp = 0.0, chk = 0.0;\n", std::max(1, maxown));
+    if (vjp) o("  double gs[%d];\n", std::max(1, maxown));
     for (int w = 0; w < W; ++w) {
         if (own[w].empty()) continue;
         o("  %sif (wave == %d) {\n", w ? "else " : "", w);
         for (size_t i = 0; i < own[w].size(); ++i)
             o("    ys[%d] = (double)(Yg + (i64)%d * ldY)[ci];\n", (int)i, own[w][i]);
+        if (vjp)
+            for (size_t i = 0; i < own[w].size(); ++i)
+                o("    gs[%d] = (double)(Gg + (i64)%d * ldG)[ci];\n", (int)i, own[w][i]);
         for (size_t i = 0; i < own[w].size(); ++i)
             o("    chk += ys[%d];\n    sgp += __builtin_fmax(ys[%d], 0.0) * SP[%d];\n", (int)i,
               (int)i, kJacSpStride * own[w][i]);
@@ -489,13 +540,20 @@ JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
             o("      O *= f;\n      const int ni = (int)nn;\n");
             o("      const double y = ys[%d], yp = __builtin_fmax(y, 0.0);\n", (int)i);
             o("      const double wp = __builtin_ldexp(E + O, ni);\n");   // 2^g' = w / W
-            o("      L[%d + lane] = rh * yp * wp;\n", 64 * k);                        // a
+            if (vjp)   // a, with the sign of zero keeping Y < 0 for the clamp
+                o("      L[%d + lane] = y >= 0.0 ? rh * y * wp : -0.0;\n", 64 * k);
+            else
+                o("      L[%d + lane] = rh * yp * wp;\n", 64 * k);                    // a
             o("      L[%d + lane] = __builtin_ldexp(E - O, -ni);\n", 64 * (ns + k));  // v' = W v
             o("      L[%d + lane] = wp * %s;\n", 64 * (2 * ns + k),                  // w
               lit(1.0 / m.sp[k].inv_W).c_str());
             o("      double hl = %s, hh = %s;\n", hpoly(16).c_str(), hpoly(23).c_str());
             o("      asm(\"\" : \"+v\"(hl), \"+v\"(hh));\n");
             o("      L[%d + lane] = %s ? hh : hl;\n", 64 * (3 * ns + k), hiname(k).c_str());
+            if (vjp) {
+                o("      L[%d + lane] = gs[%d];\n    }\n", LF + 64 * k, (int)i);     // g_omega
+                continue;
+            }
             o("      L[%d + lane] = y >= 0.0 ? SP[%d] : 0.0;\n", LF + 64 * k, b);   // f = [Y >= 0] / W
             o("      const double C = rh * yp * SP[%d];\n", b);
             emit_cp(o, "      ", "cp", k, hiname(k));
@@ -512,7 +570,8 @@ JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
     // where this lane's cell's matrix goes: cell-major (J[cell][row][col])
     // or interleaved (J[row * nv + col][cell]); the lanes past the end write
     // the last cell's again, bit for bit
-    if (interleaved) {
+    if (vjp) {
+    } else if (interleaved) {
         o("  const i64 ldJb = ldJ * %d;\n", SZ);
         o("  char *Jb = (char *)(Jg + c0) + (unsigned)(ci - c0) * %du;\n", SZ);
     } else {
@@ -619,7 +678,8 @@ JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
                 o("    {\n");
                 if (!trow)
                     o("      const double Ra = Ra%d, Rv = Rv%d, Rw = Rw%d, Rh = Rh%d;\n", k, k, k, k);
-                const Deriv d = emit_jac_rxn(o, "      ", m, f64out, q, j, rs[j], trow, rl);
+                const Deriv d = emit_jac_rxn(o, "      ", m, f64out, q, j, rs[j], trow && !vjp, rl,
+                                             vjp);
                 if (!trow) {
                     int a, b;
                     side_counts(m, j, k, a, b);
@@ -633,15 +693,18 @@ JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
                     accumulate(o, "      ", "u" + std::to_string(k), nu, 2, "uf");
                     accumulate(o, "      ", "om" + std::to_string(k), nu, 2, "qn");
                 } else {
+                    // the weight: dH_j for the temperature row, gamma_j for the VJP
+                    const char *wt = vjp ? "ga" : "dH";
                     for (size_t i = 0; i < d.sp.size(); ++i) {
                         if (!d.sign[i]) continue;
                         const int l = d.sp[i];
                         if (d.sign[i] == -1)
-                            o("      St%d = __builtin_fma(-dH, d_%d, St%d);\n", l, l, l);
-                        else o("      St%d = __builtin_fma(dH, d_%d, St%d);\n", l, l, l);
+                            o("      St%d = __builtin_fma(-%s, d_%d, St%d);\n", l, wt, l, l);
+                        else o("      St%d = __builtin_fma(%s, d_%d, St%d);\n", l, wt, l, l);
                     }
-                    o("      St%d = __builtin_fma(dH, dqT, St%d);\n", ns, ns);
-                    o("      SU = __builtin_fma(dH, uf, SU);\n      SN = __builtin_fma(dH, qn, SN);\n");
+                    o("      St%d = __builtin_fma(%s, dqT, St%d);\n", ns, wt, ns);
+                    o("      SU = __builtin_fma(%s, uf, SU);\n", wt);
+                    if (!vjp) o("      SN = __builtin_fma(dH, qn, SN);\n");
                 }
                 o("      zz = dqT;\n    }\n");
             }
@@ -653,9 +716,53 @@ JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
         if (!trow) o("    LXp[threadIdx.x] = cpw;\n");
         o("  }\n");
     }
-    // every wave is done with the tile values: the first temperature-row
-    // wave's sums go to LDS, the last one adds its own (fixed order)
+    // every wave is done with the tile values
     o("  __syncthreads();\n");
+    if (vjp) {
+        // the eight waves' sums (St_0..St_NS, SU) added in the fixed order
+        // ((w0 + w1) + (w2 + w3)) + ((w4 + w5) + (w6 + w7)) through two LDS
+        // slots past the a area (a keeps the clamp in its sign)
+        const int S0 = 64 * ns, S1 = S0 + 64 * (nv + 1);
+        const int stages[4][4] = {{1, 0, 3, 2}, {5, 4, 7, 6}, {2, 0, 6, 4}, {4, 0, -1, -1}};
+        for (const auto &st : stages) {
+            for (int h = 0; h < 2; ++h) {
+                if (st[2 * h] < 0) continue;
+                o("  if (wave == %d) {\n", st[2 * h]);
+                for (int cc = 0; cc < nv; ++cc) o("    L[%d + lane] = St%d;\n", (h ? S1 : S0) + 64 * cc, cc);
+                o("    L[%d + lane] = SU;\n  }\n", (h ? S1 : S0) + 64 * nv);
+            }
+            o("  __syncthreads();\n");
+            for (int h = 0; h < 2; ++h) {
+                if (st[2 * h] < 0) continue;
+                o("  if (wave == %d) {\n", st[2 * h + 1]);
+                for (int cc = 0; cc < nv; ++cc)
+                    o("    St%d += L[%d + lane];\n", cc, (h ? S1 : S0) + 64 * cc);
+                o("    SU += L[%d + lane];\n  }\n", (h ? S1 : S0) + 64 * nv);
+            }
+            o("  __syncthreads();\n");
+        }
+        // g_Y[m] = f_m (rho_hat St_m - SU / sigma), g_T = St_NS; the lanes past
+        // the end write the last cell's again
+        o("  if (wave == 0) {\n    const double us = SU * isg;\n");
+        for (int cc = 0; cc < ns; ++cc)
+            o("    GYg[(i64)%d * ldGY + ci] = (%s)((__builtin_signbit(L[%d + lane]) ? 0.0 : %s) * "
+              "__builtin_fma(rh, St%d, -us));\n", cc, IO, 64 * cc, lit(m.sp[cc].inv_W).c_str(), cc);
+        o("    GTg[ci] = (%s)(St%d + nanb);\n", IO, ns);
+        o("    if (live && bad) atomicAdd(err, 1ull);\n  }\n}\n");
+        o("extern \"C\" __global__ __launch_bounds__(%d) void ak_vjp(const %s *__restrict__ T, "
+          "const %s *__restrict__ P, const %s *__restrict__ Y, i64 ldY, i64 n, "
+          "const %s *__restrict__ G, i64 ldG, %s *__restrict__ GY, i64 ldGY, %s *__restrict__ GT, "
+          "const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n", 64 * W,
+          IO, IO, IO, IO, IO, IO);
+        o("  AK_JAC_LDS\n  const unsigned nb = gridDim.x, per = nb / 8u, b = blockIdx.x;\n"
+          "  const unsigned t = %s;\n"
+          "  tile((i64)t * 64, n, T, P, Y, ldY, G, ldG, GY, ldGY, GT, SP, RX, err, L);\n}\n",
+          xcd ? "b < per * 8u ? (b % 8u) * per + b / 8u : b" : "b");
+        prog.src = std::move(o.s);
+        return prog;
+    }
+    // the first temperature-row wave's sums go to LDS, the last one adds its
+    // own (fixed order)
     if (WT == 2) {
         o("  if (wave == %d) {\n", WR);
         for (int cc = 0; cc < nv; ++cc) o("    L[%d + lane] = St%d;\n", 64 * cc, cc);
@@ -690,9 +797,30 @@ JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
       "const %s *__restrict__ P, const %s *__restrict__ Y, i64 ldY, i64 n, %s *__restrict__ J, "
       "i64 ldJ, const double *__restrict__ SP, const double *__restrict__ RX, u64 *err) {\n",
       64 * W, IO, IO, IO, IO);
-    o("  AK_JAC_LDS\n  tile((i64)blockIdx.x * 64, n, T, P, Y, ldY, J, ldJ, SP, RX, err, L);\n}\n");
+    if (xcd) {
+        // workgroups go to the eight XCDs in turn: give each XCD a contiguous
+        // range of tiles, so that the tiles sharing an L2 write neighbouring
+        // cells (the rest, fewer than eight, keep their own index)
+        o("  AK_JAC_LDS\n  const unsigned nb = gridDim.x, per = nb / 8u, b = blockIdx.x;\n"
+          "  const unsigned t = b < per * 8u ? (b %% 8u) * per + b / 8u : b;\n"
+          "  tile((i64)t * 64, n, T, P, Y, ldY, J, ldJ, SP, RX, err, L);\n}\n");
+    } else {
+        o("  AK_JAC_LDS\n  tile((i64)blockIdx.x * 64, n, T, P, Y, ldY, J, ldJ, SP, RX, err, L);\n}\n");
+    }
     prog.src = std::move(o.s);
     return prog;
+}
+
+}  // namespace
+
+JitProgram jit_program_jac(const JitMech &m, bool f64out, bool interleaved)
+{
+    return gen_deriv(m, f64out, interleaved, false);
+}
+
+JitProgram jit_program_vjp(const JitMech &m, bool f64out)
+{
+    return gen_deriv(m, f64out, false, true);
 }
 
 }  // namespace ak

@@ -185,3 +185,48 @@ def test_interleaved_refuses(torch, ak):
                                                Pt.data_ptr(), Yt.data_ptr(), 8, 8,
                                                out.data_ptr(), 4, None)
     assert rc == -1      # ldJ < n_cells
+
+
+def test_compiled_vjp_parity_and_bitwise(torch, ak):
+    """The compiled VJP (gamma_j = sum_k g_k nu_kj, every reaction swept once
+    per tile, waves' sums added in a fixed order) against J^T g from the
+    oracle's Jacobian, bitwise under repetition and batch position, and
+    against the table-driven kernel."""
+    for ns, nr, irr in ((9, 21, 0.0), (53, 325, 0.3)):
+        src, m = _mech(ak, ns, nr, irr)
+        n = 157
+        T, P, Y = synth.make_states(src, n, 40 + ns)
+        Y[3, ::5] = -1e-9
+        g = np.random.default_rng(ns).standard_normal((ns, n))
+        for dt, tol in ((torch.float64, 1e-11), (torch.float32, 1e-6)):
+            Tt, Pt, Yt, gt = _dev(torch, dt, T, P, Y, g)
+            gY, gT = ak.eval_vjp(m, Tt, Pt, Yt, gt)
+            gY2, gT2 = ak.eval_vjp(m, Tt, Pt, Yt, gt)
+            Tb, Pb, Yb, gb = (torch.cat([a[..., :21], a], dim=-1).contiguous()
+                              for a in (Tt, Pt, Yt, gt))
+            gYb, gTb = ak.eval_vjp(m, Tb, Pb, Yb, gb)
+            os.environ["AK_JIT_VJP"] = "0"
+            try:
+                gYt, gTt = ak.eval_vjp(m, Tt, Pt, Yt, gt)
+            finally:
+                del os.environ["AK_JIT_VJP"]
+            torch.cuda.synchronize()
+            assert torch.equal(gY, gY2) and torch.equal(gT, gT2)
+            assert torch.equal(gYb[:, 21:], gY) and torch.equal(gTb[21:], gT)
+            if dt == torch.float32:
+                Tc, Pc, Yc, gc = (a.astype(np.float32).astype(np.float64) for a in (T, P, Y, g))
+            else:
+                Tc, Pc, Yc, gc = T, P, Y, g
+            Jr, Ja = oracle.jacobian(src, Tc, Pc, Yc, precision="ld", scales=True)
+            ref = np.einsum("ki,ikc->ci", gc, Jr[:, :ns, :].astype(np.float64))
+            scale = np.einsum("ki,ikc->ci", np.abs(gc), Ja[:, :ns, :].astype(np.float64))
+            got = np.vstack([gY.cpu().numpy().astype(np.float64),
+                             gT.cpu().numpy().astype(np.float64)[None, :]])
+            tab = np.vstack([gYt.cpu().numpy().astype(np.float64),
+                             gTt.cpu().numpy().astype(np.float64)[None, :]])
+            e = np.abs(got - ref) / np.maximum(scale, 1e-300)
+            print("vjp", ns, nr, dt, "max err/scale", float(e.max()), flush=True)
+            assert float(e.max()) <= tol
+            assert float((np.abs(got - tab) / np.maximum(scale, 1e-300)).max()) <= 2 * tol
+            # the clamped species' adjoint is zero
+            assert np.all(got[3, ::5] == 0.0)
