@@ -379,6 +379,10 @@ typedef struct {
     int64_t max_batch_cells;    /* cells per batch (0: 2^16) */
     size_t arena_bytes;         /* device arena for staged requests (0: 1 GiB) */
     int64_t small_request_cells; /* larger requests are never fused (0: 4096) */
+    void *arena;                /* NULL: the server allocates the arena; else a caller-owned
+                                   device buffer of arena_bytes (> 0) bytes on `device`,
+                                   256-byte aligned, that the caller keeps and does not
+                                   touch until ak_server_destroy has returned */
 } ak_server_config;
 
 typedef struct {
@@ -391,9 +395,11 @@ typedef struct {
     double cells_per_s;                              /* cells / (last completion - first submit) */
 } ak_server_stats;
 
-/* Create a server: allocates the device arena, max_inflight streams (default
- * priority) and descriptor tables, and starts the batcher and completion
- * threads.  Errors: AK_EINVAL, AK_ENOMEM, AK_EDEVICE. */
+/* Create a server: allocates the device arena (unless the caller passes one
+ * in cfg->arena), max_inflight streams (default priority) and descriptor
+ * tables, and starts the batcher and completion threads.  Errors: AK_EINVAL
+ * (also for a caller arena that is not device memory of cfg->device, not
+ * 256-byte aligned, or has arena_bytes 0), AK_ENOMEM, AK_EDEVICE. */
 int ak_server_create(const ak_server_config *cfg, ak_server **out);
 
 /*

@@ -50,7 +50,7 @@ class ServerConfig(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32),
                 ("max_batch_requests", C.c_int32), ("batching", C.c_int32),
                 ("max_batch_cells", C.c_int64), ("arena_bytes", C.c_size_t),
-                ("small_request_cells", C.c_int64)]
+                ("small_request_cells", C.c_int64), ("arena", C.c_void_p)]
 
 
 class ServerStats(C.Structure):
@@ -246,6 +246,15 @@ class Mechanism:
         _check(lib().ak_load_mechanism_ex(C.byref(d), self.device, _KERNELS[kernels], C.byref(h)))
         self._h = h
         self.name = getattr(src, "name", "mechanism")
+
+    @classmethod
+    def from_file(cls, path, device: int | None = None, kernels: str = "auto"):
+        """Read a CHEMKIN-II mechanism file (ELEMENTS, SPECIES, THERMO and
+        REACTIONS blocks in one file) and upload it.  Parsing is host work
+        in ``chemkin``; the result goes through the same loader as any other
+        mechanism."""
+        from . import chemkin
+        return cls(chemkin.load(path), device=device, kernels=kernels)
 
     @property
     def handle(self):
@@ -507,12 +516,23 @@ class Server:
     def __init__(self, device: int | None = None, max_inflight: int = 3,
                  max_batch_requests: int = 64, batching: bool = True,
                  max_batch_cells: int = 1 << 16, arena_bytes: int = 1 << 30,
-                 small_request_cells: int = 4096):
+                 small_request_cells: int = 4096, arena=None):
+        """``arena``: optionally a caller-owned GPU tensor (any dtype,
+        contiguous, 256-byte aligned) that the server stages requests in
+        instead of allocating its own; its size in bytes replaces
+        ``arena_bytes`` and it must outlive the server."""
         if device is None:
             device = _torch().cuda.current_device()
+        ptr = None
+        if arena is not None:
+            if not arena.is_cuda or not arena.is_contiguous():
+                raise ValueError("arena must be a contiguous GPU tensor")
+            arena_bytes = arena.numel() * arena.element_size()
+            ptr = arena.data_ptr()
+            self._arena = arena
         cfg = ServerConfig(int(device), int(max_inflight), int(max_batch_requests),
                            1 if batching else 0, int(max_batch_cells), int(arena_bytes),
-                           int(small_request_cells))
+                           int(small_request_cells), ptr)
         h = C.c_void_p()
         _check(lib().ak_server_create(C.byref(cfg), C.byref(h)))
         self._h = h

@@ -40,20 +40,36 @@ struct GpuExec {
     };
     int device = 0;
     unsigned char *arena = nullptr;
+    bool own_arena = true;           // false: the caller's buffer
     int max_req = 64;
     std::vector<Slot> slots;
     std::mutex mu;
 
-    int init(int dev, size_t arena_bytes, int inflight, int max_requests)
+    int init(int dev, size_t arena_bytes, int inflight, int max_requests, void *ext)
     {
         device = dev;
         max_req = max_requests;
         DeviceGuard g(dev);
         if (!g.ok) return set_error(AK_EDEVICE, "ak_server_create: cannot select device %d", dev);
-        hipError_t e = hipMalloc((void **)&arena, arena_bytes);
-        if (e != hipSuccess)
+        hipError_t e;
+        if (ext) {
+            // the caller's arena: device memory of this device, aligned
+            hipPointerAttribute_t at{};
+            e = hipPointerGetAttributes(&at, ext);
+            if (e != hipSuccess || at.type != hipMemoryTypeDevice || at.device != dev) {
+                (void)hipGetLastError();
+                return set_error(AK_EINVAL, "ak_server_create: the arena is not device memory of "
+                                            "device %d", dev);
+            }
+            if ((uintptr_t)ext % 256)
+                return set_error(AK_EINVAL, "ak_server_create: the arena is not 256-byte aligned");
+            arena = (unsigned char *)ext;
+            own_arena = false;
+        } else if ((e = hipMalloc((void **)&arena, arena_bytes)) != hipSuccess) {
+            arena = nullptr;
             return set_error(AK_ENOMEM, "ak_server_create: arena of %zu bytes: %s", arena_bytes,
                              hipGetErrorString(e));
+        }
         slots.resize(inflight);
         for (Slot &s : slots) {
             if ((e = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking)) != hipSuccess)
@@ -96,7 +112,7 @@ struct GpuExec {
             if (s.st) (void)hipStreamDestroy(s.st);
         }
         slots.clear();
-        if (arena) (void)hipFree(arena);
+        if (arena && own_arena) (void)hipFree(arena);
         arena = nullptr;
     }
 
@@ -288,6 +304,8 @@ int ak_server_create(const ak_server_config *c, ak_server **out)
     if (!c || !out) return set_error(AK_EINVAL, "ak_server_create: null argument");
     *out = nullptr;
     SchedConfig cfg;
+    if (c->arena && c->arena_bytes == 0)
+        return set_error(AK_EINVAL, "ak_server_create: a caller arena needs arena_bytes > 0");
     cfg.arena_bytes = c->arena_bytes ? c->arena_bytes : ((size_t)1 << 30);
     cfg.max_inflight = c->max_inflight > 0 ? c->max_inflight : 3;
     cfg.max_batch_requests = c->max_batch_requests > 0 ? c->max_batch_requests : 64;
@@ -300,7 +318,8 @@ int ak_server_create(const ak_server_config *c, ak_server **out)
     if (!s) return set_error(AK_ENOMEM, "ak_server_create: out of host memory");
     s->device = c->device;
     s->cfg = cfg;
-    int rc = s->exec.init(c->device, cfg.arena_bytes, cfg.max_inflight, cfg.max_batch_requests);
+    int rc = s->exec.init(c->device, cfg.arena_bytes, cfg.max_inflight, cfg.max_batch_requests,
+                          c->arena);
     if (rc) {
         s->exec.destroy();
         delete s;

@@ -227,3 +227,32 @@ def test_mix_with_large_mechanisms(torch, ak, mechs):
             assert np.all(np.abs(om - alone) <= 1e-6 * S), (i, ns)
     for _, m in big.values():
         m.close()
+
+
+def test_caller_provided_arena(torch, ak, mechs):
+    """The server stages requests in a device buffer the caller owns: results
+    bitwise as alone, the arena's size in the statistics, the buffer left to
+    the caller after the server is gone; bad buffers are refused."""
+    arena = torch.empty(32 << 20, dtype=torch.uint8, device="cuda")
+    srv = ak.Server(max_inflight=2, batching=True, arena=arena)
+    assert srv.stats()["arena_bytes"] == 32 << 20
+    reqs = []
+    for i, (ns, n) in enumerate(((53, 1000), (9, 70), (53, 5000), (9, 3000))):
+        src, m = mechs[ns]
+        T, P, Y = _request_states(src, n, 700 + i, np.float32)
+        out = torch.zeros(Y.shape, dtype=torch.float32).pin_memory()
+        pins = [_pinned(torch, a) for a in (T, P, Y)]
+        reqs.append((srv.submit(m, *pins, out), m, (T, P, Y), out, pins))
+    for r, *_ in reqs:
+        r.wait(60.0)
+        r.free()
+    srv.close()
+    for _, m, (T, P, Y), out, _ in reqs:
+        assert np.array_equal(out.numpy(), _alone(torch, ak, m, T, P, Y))
+    arena.fill_(1)                       # still the caller's, usable
+    torch.cuda.synchronize()
+    with pytest.raises(ValueError):
+        ak.Server(arena=torch.empty(1 << 20, dtype=torch.uint8))       # host memory
+    with pytest.raises(ak.AnnkinError) as e:
+        ak.Server(arena=arena[1:])                                     # not aligned
+    assert e.value.code == -1
