@@ -133,3 +133,20 @@ def test_pdep_served_bitwise_as_alone(torch, ak):
     for (T, P, Y), out in zip(states, outs):
         alone = _run(torch, ak, m, T, P, Y, torch.float32)
         assert np.array_equal(out.numpy().astype(np.float64), alone)
+
+
+def test_mechanism_from_chemkin_file(torch, ak, tmp_path):
+    # a CHEMKIN file of the pressure-dependent mechanism, read by
+    # Mechanism.from_file and checked against the oracle on what was read
+    from paper_2008_08483_amd import chemkin
+    src0, _ = _mech(ak, 53, 325, 0.2)
+    path = tmp_path / "mech53.inp"
+    path.write_text(chemkin.write(src0))
+    src = chemkin.load(str(path))
+    m = ak.Mechanism.from_file(str(path))
+    assert m.n_species == 53 and m.n_reactions == 325
+    T, P, Y = synth.make_states(src, 1031, 79, (800.0, 2800.0), (1.0, 20.0), 0.3)
+    om = _run(torch, ak, m, T, P, Y, torch.float64)
+    _check64(src, T, P, Y, om)
+    T32, P32, Y32 = (a.astype(np.float32) for a in (T, P, Y))
+    _check32(src, T32, P32, Y32, _run(torch, ak, m, T32, P32, Y32, torch.float32))
