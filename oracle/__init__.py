@@ -10,6 +10,9 @@ constants (Eq. 5), equilibrium constants from NASA-7 enthalpy and entropy
 changes (Eq. 8), reverse constants k_r = k_f / K_c (Eq. 7), rates of progress
 as products of concentrations (Eq. 3), and net production rates (Eq. 2).
 ``source(..., precision="ld")`` evaluates in x86 extended precision.
+``lnkc`` gives ln K_c alone, ``source_lnkc`` the source term with a given
+ln K_c in place of Eq. 8, and ``kcnet`` the approximate ln K_c network of
+Sec. 2.3 (Architecture 2) written out in numpy float64.
 
 Pins (``tests/test_oracle_pins.py``): two hand-worked reactions in closed
 form, detailed balance at a constructed equilibrium state, atom and mass
@@ -88,6 +91,11 @@ def _lib_handle():
             getattr(lib, f"ora_jacobian_scaled_{sfx}").argtypes = [
                 C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                 C.c_void_p, C.c_void_p, C.c_int64, C.c_int]
+            getattr(lib, f"ora_lnkc_{sfx}").argtypes = [C.c_void_p, C.c_int64, C.c_void_p,
+                                                        C.c_void_p, C.c_int64]
+            getattr(lib, f"ora_source_lnkc_{sfx}").argtypes = [
+                C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int]
         _lib = lib
     return _lib
 
@@ -201,6 +209,76 @@ def source(mech, T, P, Y, precision: str = "f64", scales: bool = False, n_thread
     if rc:
         raise RuntimeError("oracle source failed")
     return (om, S, N) if scales else om
+
+
+def lnkc(mech, T, precision: str = "f64"):
+    """ln K_c (Eq. 8) [NR, n] of every reaction (file order) at temperatures T [n]."""
+    m = _as_mech(mech)
+    dt = _dtype(precision)
+    T = _f64(T)
+    n = T.shape[0]
+    out = np.zeros((m.nr, n), dt)
+    rc = getattr(_lib_handle(), f"ora_lnkc_{precision}")(m.ptr, n, T.ctypes.data,
+                                                         out.ctypes.data, n)
+    if rc:
+        raise RuntimeError("oracle lnkc failed")
+    return out
+
+
+def source_lnkc(mech, T, P, Y, lnK, precision: str = "f64", scales: bool = False,
+                n_threads: int = 0):
+    """As ``source``, with ln K_c of reaction j in cell i taken from
+    ``lnK[j, i]`` (a trained ln K_c as a drop-in, Sec. 2.3)."""
+    m = _as_mech(mech)
+    dt = _dtype(precision)
+    T, P, Y = _f64(T), _f64(P), _f64(Y)
+    lnK = _f64(lnK)
+    n = T.shape[0]
+    assert P.shape == (n,) and Y.shape == (m.ns, n) and lnK.shape == (m.nr, n)
+    om = np.zeros((m.ns, n), dt)
+    S = np.zeros((m.ns, n), dt) if scales else None
+    N = np.zeros((m.ns, n), dt) if scales else None
+    rc = getattr(_lib_handle(), f"ora_source_lnkc_{precision}")(
+        m.ptr, n, T.ctypes.data, P.ctypes.data, Y.ctypes.data, n, lnK.ctypes.data, n,
+        om.ctypes.data, S.ctypes.data if scales else None, N.ctypes.data if scales else None,
+        n, int(n_threads))
+    if rc:
+        raise RuntimeError("oracle source_lnkc failed")
+    return (om, S, N) if scales else om
+
+
+def _elu(x):
+    return np.where(x >= 0.0, x, np.expm1(np.minimum(x, 0.0)))
+
+
+def kcnet(net, T, bound: bool = False):
+    """The approximate ln K_c network of Sec. 2.3, Architecture 2, in float64:
+    input the standardized log temperature, N_L hidden layers
+    X_{l+1} = elu(X_l W_l + B_l) (Eqs. 12 and 14), then a linear output layer
+    to the N_R standardized outputs, mapped back by the training set's
+    standard deviation and mean.  ``net`` has ``weights`` (N_L + 1 matrices,
+    [1, N_H], [N_H, N_H] ..., [N_H, N_R]), ``biases``, ``x_mean``, ``x_std``
+    (scalars) and ``y_mean``, ``y_std`` ([N_R]).  Returns ln K_c [N_R, n].
+
+    With ``bound``, also returns the running magnitude of the same
+    computation (every product and sum taken in absolute value, elu by its
+    slope bound 1), the scale a rounding-error bound of another evaluation
+    is proportional to."""
+    W = [np.asarray(w, np.float64) for w in net.weights]
+    B = [np.asarray(b, np.float64) for b in net.biases]
+    x = (np.log(np.asarray(T, np.float64)) - float(net.x_mean)) / float(net.x_std)
+    X = x[:, None]
+    Xa = np.abs(X)
+    for l in range(len(W) - 1):
+        X = _elu(X @ W[l] + B[l])
+        Xa = Xa @ np.abs(W[l]) + np.abs(B[l])
+    out = X @ W[-1] + B[-1]
+    ys, ym = np.asarray(net.y_std, np.float64), np.asarray(net.y_mean, np.float64)
+    lnk = (out * ys + ym).T.copy()
+    if not bound:
+        return lnk
+    mag = ((Xa @ np.abs(W[-1]) + np.abs(B[-1])) * np.abs(ys) + np.abs(ym)).T.copy()
+    return lnk, mag
 
 
 def temp_source(mech, T, P, Y, precision: str = "f64", n_threads: int = 0):

@@ -68,7 +68,11 @@ typedef struct {
                                 double *Y, int64_t ldY, double dt, int n_steps, int n_threads); \
     int ora_jacobian_scaled_##S(const ora_mech *m, int64_t n, const double *T,                 \
                                 const double *P, const double *Y, int64_t ldY, R *J, R *Jabs,  \
-                                int64_t ldJ, int n_threads);
+                                int64_t ldJ, int n_threads);                                   \
+    int ora_lnkc_##S(const ora_mech *m, int64_t n, const double *T, R *lnK, int64_t ldK);       \
+    int ora_source_lnkc_##S(const ora_mech *m, int64_t n, const double *T, const double *P,    \
+                            const double *Y, int64_t ldY, const double *lnK, int64_t ldK,      \
+                            R *omega, R *S, R *N, int64_t ldO, int n_threads);
 
 ORA_DECL(double, f64)
 ORA_DECL(long double, ld)

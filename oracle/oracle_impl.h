@@ -102,16 +102,12 @@ static REAL SFX(ipow)(REAL x, int n)
     return r;
 }
 
-/* Per-reaction quantities for one cell at given concentrations:
- * kf (Eq. 5), Kc (Eq. 8), kr = kf/Kc (Eq. 7, zero for irreversible
- * reactions), qf and qr (Eq. 3).  h_RT and s_R are the species values at T. */
-static void SFX(reaction1)(const ora_mech *m, int j, REAL T, const REAL *C,
-                           const REAL *h_RT, const REAL *s_R,
-                           REAL *kf, REAL *Kc, REAL *qf, REAL *qr)
+/* Equilibrium constant in concentration units of reaction j (Eq. 8):
+ *   K_c = (p_ref/(Ru T))^dn exp(dS/R - dH/(R T)),  dn = sum_k nu_kj. */
+static REAL SFX(kc1)(const ora_mech *m, int j, REAL T, const REAL *h_RT, const REAL *s_R)
 {
     const int ns = m->ns;
     const int8_t *nf = &m->nu_f[j * ns], *nr = &m->nu_r[j * ns];
-    REAL k_f = SFX(kf1)(m, j, T, C);
     REAL dn = 0, dS = 0, dH = 0;
     for (int k = 0; k < ns; ++k) {
         int nu = nr[k] - nf[k];
@@ -120,7 +116,22 @@ static void SFX(reaction1)(const ora_mech *m, int j, REAL T, const REAL *C,
         dS += nu * s_R[k];
         dH += nu * h_RT[k];
     }
-    REAL K_c = POW((REAL)ORA_PREF / ((REAL)ORA_RU * T), dn) * EXP(dS - dH);
+    return POW((REAL)ORA_PREF / ((REAL)ORA_RU * T), dn) * EXP(dS - dH);
+}
+
+/* Per-reaction quantities for one cell at given concentrations:
+ * kf (Eq. 5), Kc (Eq. 8), kr = kf/Kc (Eq. 7, zero for irreversible
+ * reactions), qf and qr (Eq. 3).  h_RT and s_R are the species values at T.
+ * With lnK not NULL, *lnK is used as ln K_c instead of Eq. 8 (a trained
+ * approximation of ln K_c as a drop-in, Sec. 2.3). */
+static void SFX(reaction_kc)(const ora_mech *m, int j, REAL T, const REAL *C,
+                             const REAL *h_RT, const REAL *s_R, const REAL *lnK,
+                             REAL *kf, REAL *Kc, REAL *qf, REAL *qr)
+{
+    const int ns = m->ns;
+    const int8_t *nf = &m->nu_f[j * ns], *nr = &m->nu_r[j * ns];
+    REAL k_f = SFX(kf1)(m, j, T, C);
+    REAL K_c = lnK ? EXP(*lnK) : SFX(kc1)(m, j, T, h_RT, s_R);
     REAL k_r = (m->reversible == 0 || m->reversible[j]) ? k_f / K_c : 0;
     REAL pf = 1, pr = 1;
     for (int k = 0; k < ns; ++k) {
@@ -131,6 +142,30 @@ static void SFX(reaction1)(const ora_mech *m, int j, REAL T, const REAL *C,
     *Kc = K_c;
     *qf = k_f * pf;
     *qr = k_r * pr;
+}
+
+static void SFX(reaction1)(const ora_mech *m, int j, REAL T, const REAL *C,
+                           const REAL *h_RT, const REAL *s_R,
+                           REAL *kf, REAL *Kc, REAL *qf, REAL *qr)
+{
+    SFX(reaction_kc)(m, j, T, C, h_RT, s_R, 0, kf, Kc, qf, qr);
+}
+
+/* ln K_c (Eq. 8) of every reaction at each of n temperatures:
+ * lnK[j*ldK + i] for reaction j (file order) and temperature T[i]. */
+int SFX(ora_lnkc)(const ora_mech *m, int64_t n, const double *T, REAL *lnK, int64_t ldK)
+{
+    const int ns = m->ns;
+    REAL *h = (REAL *)malloc(sizeof(REAL) * 2 * ns);
+    if (!h) return -1;
+    REAL *s = h + ns;
+    for (int64_t i = 0; i < n; ++i) {
+        REAL Ti = T[i];
+        for (int k = 0; k < ns; ++k) SFX(thermo1)(m, k, Ti, &h[k], &s[k], 0, 0);
+        for (int j = 0; j < m->nr; ++j) lnK[j * ldK + i] = LOG(SFX(kc1)(m, j, Ti, h, s));
+    }
+    free(h);
+    return 0;
 }
 
 int SFX(ora_thermo)(const ora_mech *m, double T, REAL *h_RT, REAL *s_R, REAL *cp_R)
@@ -164,9 +199,32 @@ int SFX(ora_rates)(const ora_mech *m, double T, double P, const double *Y,
  * N likewise with ldO.  S_ik = sum_j |nu_kj| (qf + qr) is the gross rate
  * scale and N_ik = sum_j |nu_kj| |qf - qr| the net rate scale (used to grade
  * rounding error); either may be NULL. */
+static int SFX(source_body)(const ora_mech *m, int64_t n, const double *T, const double *P,
+                           const double *Y, int64_t ldY, const double *lnKin, int64_t ldK,
+                           REAL *omega, REAL *S, REAL *N, int64_t ldO, int n_threads);
+
 int SFX(ora_source)(const ora_mech *m, int64_t n, const double *T, const double *P,
                     const double *Y, int64_t ldY, REAL *omega, REAL *S, REAL *N,
                     int64_t ldO, int n_threads)
+{
+    return SFX(source_body)(m, n, T, P, Y, ldY, 0, 0, omega, S, N, ldO, n_threads);
+}
+
+/* As ora_source, with ln K_c of reaction j in cell i taken from
+ * lnK[j*ldK + i] instead of Eq. 8 (the drop-in of a trained ln K_c,
+ * Sec. 2.3); the forward rates, and so the irreversible reactions, are
+ * unchanged. */
+int SFX(ora_source_lnkc)(const ora_mech *m, int64_t n, const double *T, const double *P,
+                         const double *Y, int64_t ldY, const double *lnK, int64_t ldK,
+                         REAL *omega, REAL *S, REAL *N, int64_t ldO, int n_threads)
+{
+    if (!lnK) return -1;
+    return SFX(source_body)(m, n, T, P, Y, ldY, lnK, ldK, omega, S, N, ldO, n_threads);
+}
+
+static int SFX(source_body)(const ora_mech *m, int64_t n, const double *T, const double *P,
+                           const double *Y, int64_t ldY, const double *lnKin, int64_t ldK,
+                           REAL *omega, REAL *S, REAL *N, int64_t ldO, int n_threads)
 {
     const int ns = m->ns, nr = m->nr;
     int err = 0;
@@ -193,8 +251,8 @@ int SFX(ora_source)(const ora_mech *m, int64_t n, const double *T, const double 
                 SFX(concentrations)(m, Ti, Pi, Yc, C);
                 for (int k = 0; k < ns; ++k) SFX(thermo1)(m, k, Ti, &h[k], &s[k], 0, 0);
                 for (int j = 0; j < nr; ++j) {
-                    REAL kf, Kc, qf, qr;
-                    SFX(reaction1)(m, j, Ti, C, h, s, &kf, &Kc, &qf, &qr);
+                    REAL kf, Kc, qf, qr, lk = lnKin ? (REAL)lnKin[j * ldK + i] : 0;
+                    SFX(reaction_kc)(m, j, Ti, C, h, s, lnKin ? &lk : 0, &kf, &Kc, &qf, &qr);
                     REAL qn = qf - qr;
                     const int8_t *nf = &m->nu_f[j * ns], *nrr = &m->nu_r[j * ns];
                     for (int k = 0; k < ns; ++k) {
