@@ -352,6 +352,98 @@ int ak_integrate_euler_noalloc(const ak_mechanism *mech, ak_precision prec, void
 int ak_error_count(const ak_mechanism *mech, void *stream, int64_t *n_bad_cells);
 
 /* ------------------------------------------------------------------------
+ * The equilibrium constant on its own, and a trained network in its place
+ * (Sec. 2.3).  ln K_c is in natural-log units of (kmol m^-3)^dn, stored
+ * reaction-major and cell-minor: lnK[j*ldK + i] for reaction j (descriptor
+ * order) and cell i, ldK >= n_cells, of the precision's element type.
+ */
+
+/*
+ * ln K_c of every reaction from the Gibbs layer and the net stoichiometric
+ * layer (Eqs. 9-11): ln K_c,j = -sum_k nu_kj (G_k - ln(p_ref/(R T))), with
+ * the NASA-7 range chosen per species and cell.  The arithmetic is double
+ * in both precisions (AK_FP32 rounds the result).  A cell with T <= 0 or
+ * non-finite T gets NaN and is counted (ak_error_count).  Errors: AK_EINVAL,
+ * AK_EUNSUPPORTED (more species than the LDS holds: 8 * 64 bytes each),
+ * AK_EDEVICE.
+ */
+int ak_eval_lnkc(const ak_mechanism *mech, ak_precision prec, const void *T, int64_t n_cells,
+                 void *lnK, int64_t ldK, void *stream);
+
+#define AK_KCNET_MAX_LAYERS 16
+#define AK_KCNET_MAX_HIDDEN 64
+
+/*
+ * The approximate ln K_c network of Sec. 2.3, Architecture 2 (Fig. 2): input
+ * the standardized log temperature x = (ln T - x_mean) / x_std, then n_layers
+ * hidden layers of n_hidden neurons, X_{l+1} = elu(X_l W_l + B_l) (Eqs. 12
+ * and 14), then a linear readout to n_out standardized outputs y, and
+ * ln K_c,j = y_j y_std[j] + y_mean[j].  Row-major matrices, input index
+ * first (X W):
+ *   weights = W_0 [1][n_hidden], W_1 .. W_{n_layers-1} [n_hidden][n_hidden],
+ *             W_{n_layers} [n_hidden][n_out], concatenated;
+ *   biases  = B_0 .. B_{n_layers-1} [n_hidden], B_{n_layers} [n_out].
+ * Host arrays, read during ak_load_kcnet only.
+ */
+typedef struct {
+    int32_t n_layers;   /* N_L hidden layers, 1 .. AK_KCNET_MAX_LAYERS */
+    int32_t n_hidden;   /* N_H neurons per hidden layer, 1 .. AK_KCNET_MAX_HIDDEN */
+    int32_t n_out;      /* N_R outputs, one per reaction */
+    int32_t pad;
+    const double *weights;
+    const double *biases;
+    double x_mean, x_std;              /* standardization of ln T (x_std > 0) */
+    const double *y_mean, *y_std;      /* [n_out] standardization of ln K_c */
+} ak_kcnet_desc;
+
+typedef struct ak_kcnet ak_kcnet; /* opaque; owns its device weights */
+
+/*
+ * Copy a network's weights to `device` (in double and in float; widths
+ * below 64 are padded with zero weights to 8, 16, 32 or 64).  The output
+ * standardization is folded into the readout.  Errors: AK_EINVAL (sizes,
+ * non-finite values, x_std <= 0), AK_EDEVICE.
+ */
+int ak_load_kcnet(const ak_kcnet_desc *desc, int device, ak_kcnet **out);
+int ak_free_kcnet(ak_kcnet *net);
+int ak_kcnet_n_out(const ak_kcnet *net);
+
+/*
+ * ln K_c from the network for n_cells temperatures, one cell per lane with
+ * its activations in registers.  AK_FP64 evaluates in double; AK_FP32 in
+ * float (ln T in double, then standardized and rounded).  Each output is a
+ * sum in a fixed order, so repeated calls agree bitwise.  A cell with
+ * T <= 0 or non-finite T gets NaN (there is no counter for networks).
+ * Errors: AK_EINVAL, AK_EDEVICE.
+ */
+int ak_eval_lnkc_net(const ak_kcnet *net, ak_precision prec, const void *T, int64_t n_cells,
+                     void *lnK, int64_t ldK, void *stream);
+
+/*
+ * The source term (Eqs. 2-7) with ln K_c of reaction j in cell i taken from
+ * lnK[j*ldK + i] in place of Eq. 8: q_r = k_f exp(-ln K_c) prod C^nu''.
+ * Irreversible reactions do not read lnK.  Arguments otherwise as
+ * ak_eval_source.  The arithmetic is double in both precisions; the
+ * accumulation order is fixed (bitwise reproducible).  Errors: AK_EINVAL,
+ * AK_EUNSUPPORTED (third-body or falloff reactions; more species than the
+ * LDS holds: 16 * 64 bytes each), AK_EDEVICE.
+ */
+int ak_eval_source_lnkc(const ak_mechanism *mech, ak_precision prec, const void *T,
+                        const void *P, const void *Y, int64_t ldY, int64_t n_cells,
+                        const void *lnK, int64_t ldK, void *omega, int64_t ldO, void *stream);
+
+/*
+ * ak_eval_lnkc_net into a scratch buffer of N_R x n_cells elements
+ * (allocated and freed stream-ordered on `stream`), then
+ * ak_eval_source_lnkc: the network as a drop-in for ln K_c.  The network's
+ * n_out must equal the mechanism's reaction count, and both must live on
+ * the same device.  Errors: as the two calls, AK_ENOMEM.
+ */
+int ak_eval_source_net(const ak_mechanism *mech, const ak_kcnet *net, ak_precision prec,
+                       const void *T, const void *P, const void *Y, int64_t ldY,
+                       int64_t n_cells, void *omega, int64_t ldO, void *stream);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of many callers' source-term requests.
  *
  * The paper's use is an MPI rank offloading its cells to the GPU (Sec. 1,

@@ -46,6 +46,13 @@ class MechanismDesc(C.Structure):
     ]
 
 
+class KcNetDesc(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("n_hidden", C.c_int32), ("n_out", C.c_int32),
+                ("pad", C.c_int32), ("weights", C.c_void_p), ("biases", C.c_void_p),
+                ("x_mean", C.c_double), ("x_std", C.c_double), ("y_mean", C.c_void_p),
+                ("y_std", C.c_void_p)]
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32),
                 ("max_batch_requests", C.c_int32), ("batching", C.c_int32),
@@ -114,6 +121,19 @@ def lib():
         h.ak_eval_vjp.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                   C.c_int64, C.c_void_p, C.c_void_p]
+        h.ak_eval_lnkc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p,
+                                   C.c_int64, C.c_void_p]
+        h.ak_load_kcnet.argtypes = [C.POINTER(KcNetDesc), C.c_int, C.POINTER(C.c_void_p)]
+        h.ak_free_kcnet.argtypes = [C.c_void_p]
+        h.ak_kcnet_n_out.argtypes = [C.c_void_p]
+        h.ak_eval_lnkc_net.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int64, C.c_void_p,
+                                       C.c_int64, C.c_void_p]
+        h.ak_eval_source_lnkc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                          C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+        h.ak_eval_source_net.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                         C.c_void_p, C.c_int64, C.c_void_p]
         _lib = h
     return _lib
 
@@ -410,6 +430,140 @@ def integrate_euler(mech: Mechanism, T, P, Y, dt: float, n_steps: int, stream=No
                                     Y.data_ptr(), Y.stride(0), n, float(dt), int(n_steps),
                                     _stream_ptr(stream)))
     return T, Y
+
+
+# ---------------------------------------------------------------------------
+# ln K_c alone and the approximate network in its place (Sec. 2.3)
+
+def _check_T(T):
+    torch = _torch()
+    if not isinstance(T, torch.Tensor) or not T.is_cuda:
+        raise TypeError("T must be a GPU tensor")
+    if T.dim() != 1 or not T.is_contiguous():
+        raise ValueError("T must be a contiguous [n] tensor")
+    _prec(T.dtype)
+    return T.shape[0]
+
+
+def _lnk_out(out, nr, n, T):
+    torch = _torch()
+    if out is None:
+        return torch.empty((nr, n), dtype=T.dtype, device=T.device)
+    if (out.shape != (nr, n) or out.dtype != T.dtype or not out.is_cuda
+            or out.stride(1) != 1):
+        raise ValueError("out must be a GPU [NR, n] tensor of T's dtype, cells contiguous")
+    return out
+
+
+def eval_lnkc(mech: Mechanism, T, out=None, stream=None):
+    """ln K_c [NR, n] (Eq. 8 through the Gibbs and stoichiometric layers,
+    Eqs. 9-11) at temperatures T [n].  Asynchronous."""
+    n = _check_T(T)
+    out = _lnk_out(out, mech.n_reactions, n, T)
+    ldK = out.stride(0) if mech.n_reactions > 1 else n
+    _check(lib().ak_eval_lnkc(mech.handle, _prec(T.dtype), T.data_ptr(), n, out.data_ptr(),
+                              ldK, _stream_ptr(stream)))
+    return out
+
+
+class KcNet:
+    """The approximate ln K_c network of Sec. 2.3 (Architecture 2) uploaded
+    to one GPU.  ``net`` has ``weights`` (N_L + 1 matrices [1, N_H],
+    [N_H, N_H] ..., [N_H, N_R]), ``biases``, ``x_mean``, ``x_std``,
+    ``y_mean`` and ``y_std`` (for instance ``kcnet.KcNetWeights``)."""
+
+    def __init__(self, net, device: int | None = None):
+        torch = _torch()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        W = [np.ascontiguousarray(w, dtype=np.float64) for w in net.weights]
+        B = [np.ascontiguousarray(b, dtype=np.float64).reshape(-1) for b in net.biases]
+        if len(W) < 2 or len(W) != len(B):
+            raise ValueError("a network needs at least one hidden layer and a readout")
+        nh = W[0].shape[1]
+        nr = W[-1].shape[1]
+        if W[0].shape != (1, nh) or any(w.shape != (nh, nh) for w in W[1:-1]) \
+                or W[-1].shape != (nh, nr) or any(b.shape != (w.shape[1],) for w, b in zip(W, B)):
+            raise ValueError("inconsistent layer shapes")
+        self.n_layers, self.n_hidden, self.n_out = len(W) - 1, nh, nr
+        self._w = np.concatenate([w.reshape(-1) for w in W])
+        self._b = np.concatenate(B)
+        self._ym = np.ascontiguousarray(net.y_mean, dtype=np.float64).reshape(-1)
+        self._ys = np.ascontiguousarray(net.y_std, dtype=np.float64).reshape(-1)
+        if self._ym.shape != (nr,) or self._ys.shape != (nr,):
+            raise ValueError("y_mean and y_std must have one entry per output")
+        d = KcNetDesc(self.n_layers, nh, nr, 0, self._w.ctypes.data, self._b.ctypes.data,
+                      float(net.x_mean), float(net.x_std), self._ym.ctypes.data,
+                      self._ys.ctypes.data)
+        h = C.c_void_p()
+        _check(lib().ak_load_kcnet(C.byref(d), self.device, C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ak_free_kcnet(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_lnkc_net(net: KcNet, T, out=None, stream=None):
+    """ln K_c [N_R, n] from the network at temperatures T [n].  Asynchronous."""
+    n = _check_T(T)
+    out = _lnk_out(out, net.n_out, n, T)
+    ldK = out.stride(0) if net.n_out > 1 else n
+    _check(lib().ak_eval_lnkc_net(net.handle, _prec(T.dtype), T.data_ptr(), n, out.data_ptr(),
+                                  ldK, _stream_ptr(stream)))
+    return out
+
+
+def eval_source_lnkc(mech: Mechanism, T, P, Y, lnK, out=None, stream=None):
+    """omega [NS, n] with ln K_c of reaction j in cell i taken from
+    lnK [NR, n] in place of Eq. 8.  Asynchronous."""
+    torch = _torch()
+    n = _check_state(mech, T, P, Y)
+    if (not isinstance(lnK, torch.Tensor) or not lnK.is_cuda or lnK.dtype != T.dtype
+            or lnK.shape != (mech.n_reactions, n) or lnK.stride(1) != 1):
+        raise ValueError("lnK must be a GPU [NR, n] tensor of the state dtype, cells contiguous")
+    if out is None:
+        out = torch.empty((mech.n_species, n), dtype=T.dtype, device=T.device)
+    elif (out.shape != (mech.n_species, n) or out.dtype != T.dtype or out.stride(1) != 1
+          or not out.is_cuda):
+        raise ValueError("out must be a GPU [NS, n] tensor of the state dtype")
+    ldY = Y.stride(0) if mech.n_species > 1 else n
+    ldO = out.stride(0) if mech.n_species > 1 else n
+    ldK = lnK.stride(0) if mech.n_reactions > 1 else n
+    _check(lib().ak_eval_source_lnkc(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
+                                     Y.data_ptr(), ldY, n, lnK.data_ptr(), ldK, out.data_ptr(),
+                                     ldO, _stream_ptr(stream)))
+    return out
+
+
+def eval_source_net(mech: Mechanism, net: KcNet, T, P, Y, out=None, stream=None):
+    """omega [NS, n] with the network's ln K_c in place of Eq. 8 (the
+    drop-in of Sec. 2.3).  Asynchronous."""
+    torch = _torch()
+    n = _check_state(mech, T, P, Y)
+    if out is None:
+        out = torch.empty((mech.n_species, n), dtype=T.dtype, device=T.device)
+    elif (out.shape != (mech.n_species, n) or out.dtype != T.dtype or out.stride(1) != 1
+          or not out.is_cuda):
+        raise ValueError("out must be a GPU [NS, n] tensor of the state dtype")
+    ldY = Y.stride(0) if mech.n_species > 1 else n
+    ldO = out.stride(0) if mech.n_species > 1 else n
+    _check(lib().ak_eval_source_net(mech.handle, net.handle, _prec(T.dtype), T.data_ptr(),
+                                    P.data_ptr(), Y.data_ptr(), ldY, n, out.data_ptr(), ldO,
+                                    _stream_ptr(stream)))
+    return out
 
 
 def _source_function():

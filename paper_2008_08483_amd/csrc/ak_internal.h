@@ -33,6 +33,9 @@ struct ak_mechanism {
     mutable ak::JitKernels vjp[2];
     mutable int vjp_state[2] = {0, 0};
     mutable unsigned char *jac_dev = nullptr;   // their constant tables
+    // the ln K_c tables (descriptor-order reactions, sorted-to-descriptor
+    // index), uploaded at the first call that needs them
+    mutable unsigned char *kc_dev = nullptr;
 };
 
 namespace ak {

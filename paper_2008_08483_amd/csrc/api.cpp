@@ -554,6 +554,7 @@ int ak_free_mechanism(ak_mechanism *m)
         jit_unload(m->vjp[f]);
     }
     if (m->jac_dev) (void)hipFree(m->jac_dev);
+    if (m->kc_dev) (void)hipFree(m->kc_dev);
     (void)hipFree(m->dev);
     delete m;
     return AK_OK;

@@ -1,0 +1,574 @@
+// The equilibrium-constant layer on its own and its trained replacement
+// (Sec. 2.3):
+//  - ak_eval_lnkc: ln K_c of every reaction and cell from the Gibbs layer
+//    (Eq. 10, with p_ref/(R T) folded into its bias, Eq. 11) followed by the
+//    net stoichiometric layer: ln K_c,j = -sum_k nu_kj g_k;
+//  - ak_eval_lnkc_net: the approximate network of Architecture 2, one input
+//    (ln T, standardized), N_L hidden layers X_{l+1} = elu(X_l W_l + B_l)
+//    (Eqs. 12 and 14), a linear readout to the N_R standardized outputs;
+//  - ak_eval_source_lnkc: the source term (Eqs. 2-7) with a given ln K_c in
+//    place of Eq. 8, the consumer of either;
+//  - ak_eval_source_net: the two in sequence, the network as a drop-in for
+//    the Gibbs and stoichiometric layers of the reverse rates.
+// ln K_c is in (kmol m^-3)^dn, reaction-major and cell-minor:
+// lnK[j * ldK + i] for reaction j (descriptor order) and cell i.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <type_traits>
+#include <vector>
+
+#include "annkin.h"
+#include "ak_device.h"
+#include "ak_internal.h"
+
+struct ak_kcnet {
+    int device = 0;
+    int nl = 0, nh = 0, nhp = 0, nr = 0;   // hidden layers, width, padded width, outputs
+    double x_mean = 0.0, x_std = 1.0;
+    unsigned char *dev = nullptr;          // weights in double, then in float
+    size_t n_elems = 0;                    // elements per precision
+};
+
+namespace ak {
+
+// Per reaction, descriptor order (32 B): the distinct species of the
+// reaction and their net coefficients nu_kj = nu''_kj - nu'_kj (nonzero).
+struct KcRxn {
+    uint16_t sp[8];
+    int8_t nu[8];
+    int32_t cnt;
+    int32_t pad[1];
+};
+static_assert(sizeof(KcRxn) == 32, "KcRxn layout");
+
+namespace {
+
+constexpr double kLn2 = 0.693147180559945309417232121458;
+
+__device__ __forceinline__ double g2_of(const SpeciesRec &sr, double T, double lnT, double T2,
+                                        double T3, double T4, double invT)
+{
+    const double *w = T >= sr.T_mid ? sr.hi : sr.lo;
+    return w[0] * lnT + w[1] * T + w[2] * T2 + w[3] * T3 + w[4] * T4 + w[5] * invT + w[6];
+}
+
+// One 64-cell tile per workgroup (one wave), lane = cell.  Each lane keeps
+// its cell's Gibbs-layer outputs g2_k = log2(e) (G_k - ln(p_ref/(R T))) in
+// its own LDS column, so no barrier is needed; every reaction row is then
+// one coalesced store of 64 cells.
+template <typename IO>
+__global__ __launch_bounds__(64) void lnkc_kernel(MechView m, const KcRxn *__restrict__ kr,
+                                                  const IO *__restrict__ T, int64_t n,
+                                                  IO *__restrict__ lnK, int64_t ldK)
+{
+    extern __shared__ double g2[];
+    const int lane = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = i < n;
+    const double t = (double)T[live ? i : n - 1];
+    const bool bad = !(t > 0.0) || !__builtin_isfinite(t);
+    const double Tc = bad ? 1000.0 : t;
+    const double lnT = log(Tc), T2 = Tc * Tc, T3 = T2 * Tc, T4 = T3 * Tc, invT = 1.0 / Tc;
+    for (int k = 0; k < m.ns; ++k) g2[k * 64 + lane] = g2_of(m.sp[k], Tc, lnT, T2, T3, T4, invT);
+    const IO nan = (IO)__builtin_nan("");
+    for (int j = 0; j < m.nr; ++j) {
+        const KcRxn *r = &kr[j];
+        double acc = 0.0;
+        for (int q = 0; q < r->cnt; ++q) acc += (double)r->nu[q] * g2[r->sp[q] * 64 + lane];
+        if (live) lnK[(int64_t)j * ldK + i] = bad ? nan : (IO)(-acc * kLn2);
+    }
+    if (live && bad) atomicAdd(m.err, 1ull);
+}
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile
+// time so that register arrays indexed by i never go to scratch memory
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+template <typename E>
+__device__ __forceinline__ E elu(E x)
+{
+    if constexpr (sizeof(E) == 8)
+        return x >= 0.0 ? x : expm1(x);
+    else
+        return x >= 0.0f ? x : expm1f(x);
+}
+
+// The approximate network, lane = cell.  Weight layout (element type E,
+// width NH padded with zero weights to the template width):
+//   w0[NH], b0[NH];  per further hidden layer W^T[NH][NH] (output-major),
+//   b[NH];  readout W^T[nr][NH] and b[nr], with the outputs' standard
+//   deviation and mean folded in.
+// Every weight index is uniform across the wave (scalar loads); the
+// activations stay in registers.  Sums run in a fixed order.
+template <typename E, int NH>
+__global__ __launch_bounds__(256) void kcnet_kernel(const E *__restrict__ w, int nl, int nr,
+                                                    double x_mean, double x_std,
+                                                    const E *__restrict__ T, int64_t n,
+                                                    E *__restrict__ lnK, int64_t ldK)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double t = (double)T[i];
+    const bool bad = !(t > 0.0) || !__builtin_isfinite(t);
+    const E z = (E)((log(bad ? 1.0 : t) - x_mean) / x_std);
+    E h[NH];
+    static_for<0, NH>([&](auto o) { h[o] = elu<E>(z * w[o] + w[NH + o]); });
+    const E *p = w + 2 * NH;
+    for (int l = 1; l < nl; ++l) {
+        E g[NH];
+        static_for<0, NH>([&](auto o) {
+            E acc = p[NH * NH + o];
+            static_for<0, NH>([&](auto q) { acc = __builtin_fma(h[q], p[o * NH + q], acc); });
+            g[o] = elu<E>(acc);
+        });
+        static_for<0, NH>([&](auto o) { h[o] = g[o]; });
+        p += NH * NH + NH;
+    }
+    const E *bo = p + (int64_t)nr * NH;
+    const E nan = (E)__builtin_nan("");
+    for (int j = 0; j < nr; ++j) {
+        const E *wj = p + (int64_t)j * NH;
+        E acc = bo[j];
+        static_for<0, NH>([&](auto q) { acc = __builtin_fma(h[q], wj[q], acc); });
+        lnK[(int64_t)j * ldK + i] = bad ? nan : acc;
+    }
+}
+
+// The source term with a given ln K_c, one 64-cell tile per workgroup (one
+// wave), lane = cell.  LDS holds the lane's log2 C_k and its omega_k
+// accumulators (its own columns: no atomics, a fixed order of additions).
+// Reactions run in the library's sorted order; ln K_c is read at the
+// descriptor index of each.
+template <typename IO>
+__global__ __launch_bounds__(64) void source_lnkc_kernel(MechView m,
+                                                         const int32_t *__restrict__ order,
+                                                         const IO *__restrict__ T,
+                                                         const IO *__restrict__ P,
+                                                         const IO *__restrict__ Y, int64_t ldY,
+                                                         int64_t n, const IO *__restrict__ lnK,
+                                                         int64_t ldK, IO *__restrict__ om,
+                                                         int64_t ldO)
+{
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    double *l2C = lds, *acc = lds + (size_t)m.ns * 64;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = i < n;
+    const int64_t c = live ? i : n - 1;
+    const double Tc = (double)T[c], Pc = (double)P[c];
+    bool bad = !(Tc > 0.0) || !(Pc > 0.0) || !__builtin_isfinite(Tc) || !__builtin_isfinite(Pc);
+    double sigma = 0.0;
+    for (int k = 0; k < m.ns; ++k) {
+        const double y = (double)Y[(int64_t)k * ldY + c];
+        if (!__builtin_isfinite(y)) bad = true;
+        sigma += (y > 0.0 ? y : 0.0) * m.sp[k].inv_W;
+    }
+    if (!(sigma > 0.0) || !__builtin_isfinite(sigma)) bad = true;
+    const double Tu = bad ? 1000.0 : Tc;
+    const double rh = bad ? 0.0 : Pc / (kRu * Tu * sigma);
+    for (int k = 0; k < m.ns; ++k) {
+        const double y = (double)Y[(int64_t)k * ldY + c];
+        const double C = rh * (y > 0.0 ? y : 0.0) * m.sp[k].inv_W;
+        l2C[k * 64 + lane] = C > 0.0 ? log2(C) : -__builtin_inf();
+        acc[k * 64 + lane] = 0.0;
+    }
+    const double log2T = log2(Tu), invT = 1.0 / Tu;
+    for (int j = 0; j < m.nr; ++j) {
+        const RxnRec *r = &m.rx[j];
+        const RxnAux *x = &m.aux[j];
+        const int nf = x->nf, np = x->nr;
+        const double t0 = r->log2A + r->beta * log2T + r->negEoR2 * invT;
+        double tf = t0;
+        for (int q = 0; q < nf; ++q) tf += l2C[x->sp[q] * 64 + lane];
+        double qn = exp2(tf);
+        if (x->rev) {
+            double tr = t0 - (double)lnK[(int64_t)order[j] * ldK + c] * kLog2e;
+            for (int q = 0; q < np; ++q) tr += l2C[x->sp[nf + q] * 64 + lane];
+            qn -= exp2(tr);
+        }
+        for (int q = 0; q < nf; ++q) acc[x->sp[q] * 64 + lane] -= qn;
+        for (int q = 0; q < np; ++q) acc[x->sp[nf + q] * 64 + lane] += qn;
+    }
+    bool nonfinite = false;
+    const IO nan = (IO)__builtin_nan("");
+    for (int k = 0; k < m.ns; ++k) {
+        const double v = acc[k * 64 + lane];
+        if (!__builtin_isfinite(v)) nonfinite = true;
+        if (live) om[(int64_t)k * ldO + i] = bad ? nan : (IO)v;
+    }
+    if (live && (bad || nonfinite)) atomicAdd(m.err, 1ull);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+std::mutex g_kc_mu;   // guards the lazy tables of every mechanism
+
+size_t source_lnkc_lds(int ns) { return (size_t)ns * 64 * 2 * sizeof(double); }
+size_t lnkc_lds(int ns) { return (size_t)ns * 64 * sizeof(double); }
+
+// The descriptor-order reaction table and the sorted-to-descriptor index,
+// uploaded at the first call that needs them.
+int kc_tables(const ak_mechanism *m, const KcRxn **kr, const int32_t **order)
+{
+    std::lock_guard<std::mutex> l(g_kc_mu);
+    if (!m->kc_dev) {
+        const int nr = m->nr;
+        std::vector<KcRxn> t(nr);
+        for (int s = 0; s < nr; ++s) {
+            const RxnAux &x = m->host_aux[s];
+            KcRxn &r = t[m->rxn_order[s]];
+            std::memset(&r, 0, sizeof r);
+            int sp[8], nu[8], cnt = 0;
+            for (int q = 0; q < x.nf + x.nr; ++q) {
+                const int k = x.sp[q], d = q < x.nf ? -1 : 1;
+                int a = 0;
+                while (a < cnt && sp[a] != k) ++a;
+                if (a == cnt) { sp[cnt] = k; nu[cnt] = 0; ++cnt; }
+                nu[a] += d;
+            }
+            for (int a = 0; a < cnt; ++a)
+                if (nu[a] != 0) {
+                    r.sp[r.cnt] = (uint16_t)sp[a];
+                    r.nu[r.cnt] = (int8_t)nu[a];
+                    ++r.cnt;
+                }
+        }
+        std::vector<int32_t> ord(m->rxn_order.begin(), m->rxn_order.end());
+        const size_t bytes = sizeof(KcRxn) * nr + sizeof(int32_t) * nr;
+        unsigned char *d = nullptr;
+        hipError_t e = hipMalloc(&d, bytes);
+        if (e == hipSuccess) e = hipMemcpy(d, t.data(), sizeof(KcRxn) * nr, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(d + sizeof(KcRxn) * nr, ord.data(), sizeof(int32_t) * nr,
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (d) (void)hipFree(d);
+            return hip_error(e, "ln K_c tables");
+        }
+        m->kc_dev = d;
+    }
+    *kr = (const KcRxn *)m->kc_dev;
+    *order = (const int32_t *)(m->kc_dev + sizeof(KcRxn) * m->nr);
+    return AK_OK;
+}
+
+int check_prec(const char *fn, int prec)
+{
+    if (prec != AK_FP32 && prec != AK_FP64)
+        return set_error(AK_EINVAL, "%s: bad precision %d", fn, prec);
+    return AK_OK;
+}
+
+int check_cells(const char *fn, int64_t n)
+{
+    if (n < 0) return set_error(AK_EINVAL, "%s: n_cells < 0", fn);
+    if (n > (int64_t)1 << 40) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
+    return AK_OK;
+}
+
+template <typename E>
+hipError_t launch_kcnet(const ak_kcnet *net, const E *w, const void *T, int64_t n, void *lnK,
+                        int64_t ldK, hipStream_t st)
+{
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 g((unsigned)blocks), b(256);
+#define AK_KCNET(NH)                                                                         \
+    hipLaunchKernelGGL((kcnet_kernel<E, NH>), g, b, 0, st, w, net->nl, net->nr, net->x_mean,  \
+                       net->x_std, (const E *)T, n, (E *)lnK, ldK)
+    switch (net->nhp) {
+        case 8: AK_KCNET(8); break;
+        case 16: AK_KCNET(16); break;
+        case 32: AK_KCNET(32); break;
+        case 64: AK_KCNET(64); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef AK_KCNET
+    return hipGetLastError();
+}
+
+hipError_t kcnet_launch(const ak_kcnet *net, int prec, const void *T, int64_t n, void *lnK,
+                        int64_t ldK, hipStream_t st)
+{
+    if (prec == AK_FP64) return launch_kcnet<double>(net, (const double *)net->dev, T, n, lnK, ldK, st);
+    return launch_kcnet<float>(net, (const float *)(net->dev + net->n_elems * sizeof(double)), T, n,
+                               lnK, ldK, st);
+}
+
+hipError_t source_lnkc_launch(const ak_mechanism *m, const int32_t *order, int prec,
+                              const void *T, const void *P, const void *Y, int64_t ldY, int64_t n,
+                              const void *lnK, int64_t ldK, void *om, int64_t ldO, hipStream_t st)
+{
+    const int64_t blocks = (n + 63) / 64;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const size_t lds = source_lnkc_lds(m->ns);
+    hipError_t e;
+    if (prec == AK_FP64) {
+        auto fn = source_lnkc_kernel<double>;
+        if ((e = allow_dynamic_lds((const void *)fn)) != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, st, m->view, order,
+                           (const double *)T, (const double *)P, (const double *)Y, ldY, n,
+                           (const double *)lnK, ldK, (double *)om, ldO);
+    } else {
+        auto fn = source_lnkc_kernel<float>;
+        if ((e = allow_dynamic_lds((const void *)fn)) != hipSuccess) return e;
+        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, st, m->view, order,
+                           (const float *)T, (const float *)P, (const float *)Y, ldY, n,
+                           (const float *)lnK, ldK, (float *)om, ldO);
+    }
+    return hipGetLastError();
+}
+
+int check_source(const char *fn, const ak_mechanism *m, int prec, const void *T, const void *P,
+                 const void *Y, int64_t ldY, int64_t n, const void *om, int64_t ldO)
+{
+    if (!m) return set_error(AK_EINVAL, "%s: null mechanism", fn);
+    int rc = check_prec(fn, prec);
+    if (!rc) rc = check_cells(fn, n);
+    if (rc) return rc;
+    if (n > 0 && (!T || !P || !Y || !om)) return set_error(AK_EINVAL, "%s: null pointer", fn);
+    if (n > 0 && (ldY < n || ldO < n))
+        return set_error(AK_EINVAL, "%s: ldY=%lld ldO=%lld < n_cells=%lld", fn, (long long)ldY,
+                         (long long)ldO, (long long)n);
+    if (m->pdep)
+        return set_error(AK_EUNSUPPORTED, "%s: third-body and falloff reactions are not "
+                                          "supported with a given ln K_c", fn);
+    if (source_lnkc_lds(m->ns) > (size_t)m->lds_max)
+        return set_error(AK_EUNSUPPORTED, "%s: %d species exceed the LDS", fn, m->ns);
+    return AK_OK;
+}
+
+}  // namespace
+}  // namespace ak
+
+using namespace ak;
+
+extern "C" {
+
+int ak_eval_lnkc(const ak_mechanism *m, ak_precision prec, const void *T, int64_t n, void *lnK,
+                 int64_t ldK, void *stream)
+{
+    const char *fn = "ak_eval_lnkc";
+    if (!m) return set_error(AK_EINVAL, "%s: null mechanism", fn);
+    int rc = check_prec(fn, prec);
+    if (!rc) rc = check_cells(fn, n);
+    if (rc) return rc;
+    if (n == 0) return AK_OK;
+    if (!T || !lnK) return set_error(AK_EINVAL, "%s: null pointer", fn);
+    if (ldK < n)
+        return set_error(AK_EINVAL, "%s: ldK=%lld < n_cells=%lld", fn, (long long)ldK,
+                         (long long)n);
+    if (lnkc_lds(m->ns) > (size_t)m->lds_max)
+        return set_error(AK_EUNSUPPORTED, "%s: %d species exceed the LDS", fn, m->ns);
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, m->device);
+    const KcRxn *kr;
+    const int32_t *order;
+    if ((rc = kc_tables(m, &kr, &order))) return rc;
+    const int64_t blocks = (n + 63) / 64;
+    if (blocks > 0x7fffffff) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
+    const size_t lds = lnkc_lds(m->ns);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (prec == AK_FP64) {
+        auto k = lnkc_kernel<double>;
+        e = allow_dynamic_lds((const void *)k);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64), lds, st, m->view, kr,
+                               (const double *)T, n, (double *)lnK, ldK);
+            e = hipGetLastError();
+        }
+    } else {
+        auto k = lnkc_kernel<float>;
+        e = allow_dynamic_lds((const void *)k);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64), lds, st, m->view, kr,
+                               (const float *)T, n, (float *)lnK, ldK);
+            e = hipGetLastError();
+        }
+    }
+    if (e != hipSuccess) return hip_error(e, "ak_eval_lnkc: launch");
+    return AK_OK;
+}
+
+int ak_load_kcnet(const ak_kcnet_desc *d, int device, ak_kcnet **out)
+{
+    const char *fn = "ak_load_kcnet";
+    if (!d || !out) return set_error(AK_EINVAL, "%s: null argument", fn);
+    *out = nullptr;
+    const int nl = d->n_layers, nh = d->n_hidden, nr = d->n_out;
+    if (nl < 1 || nl > AK_KCNET_MAX_LAYERS || nh < 1 || nh > AK_KCNET_MAX_HIDDEN || nr < 1)
+        return set_error(AK_EINVAL, "%s: bad sizes (layers %d, hidden %d, outputs %d)", fn, nl,
+                         nh, nr);
+    if (!d->weights || !d->biases || !d->y_mean || !d->y_std)
+        return set_error(AK_EINVAL, "%s: null array", fn);
+    if (!(d->x_std > 0.0) || !std::isfinite(d->x_std) || !std::isfinite(d->x_mean))
+        return set_error(AK_EINVAL, "%s: bad input standardization", fn);
+    const size_t n_w = (size_t)nh + (size_t)(nl - 1) * nh * nh + (size_t)nh * nr;
+    const size_t n_b = (size_t)nh * nl + (size_t)nr;
+    for (size_t q = 0; q < n_w; ++q)
+        if (!std::isfinite(d->weights[q])) return set_error(AK_EINVAL, "%s: non-finite weight", fn);
+    for (size_t q = 0; q < n_b; ++q)
+        if (!std::isfinite(d->biases[q])) return set_error(AK_EINVAL, "%s: non-finite bias", fn);
+    for (int j = 0; j < nr; ++j)
+        if (!std::isfinite(d->y_mean[j]) || !std::isfinite(d->y_std[j]))
+            return set_error(AK_EINVAL, "%s: non-finite output standardization", fn);
+    const int nhp = nh <= 8 ? 8 : nh <= 16 ? 16 : nh <= 32 ? 32 : 64;
+    // device layout (kernel order), zero-padded to width nhp
+    const size_t ne = 2 * (size_t)nhp + (size_t)(nl - 1) * (nhp * nhp + nhp) +
+                      (size_t)nr * nhp + nr;
+    std::vector<double> w(ne, 0.0);
+    const double *W = d->weights, *B = d->biases;
+    for (int o = 0; o < nh; ++o) {
+        w[o] = W[o];
+        w[nhp + o] = B[o];
+    }
+    size_t p = 2 * (size_t)nhp, iw = nh, ib = nh;
+    for (int l = 1; l < nl; ++l) {
+        for (int o = 0; o < nh; ++o)
+            for (int q = 0; q < nh; ++q) w[p + (size_t)o * nhp + q] = W[iw + (size_t)q * nh + o];
+        for (int o = 0; o < nh; ++o) w[p + (size_t)nhp * nhp + o] = B[ib + o];
+        p += (size_t)nhp * nhp + nhp;
+        iw += (size_t)nh * nh;
+        ib += nh;
+    }
+    for (int j = 0; j < nr; ++j) {
+        for (int q = 0; q < nh; ++q)
+            w[p + (size_t)j * nhp + q] = W[iw + (size_t)q * nr + j] * d->y_std[j];
+        w[p + (size_t)nr * nhp + j] = B[ib + j] * d->y_std[j] + d->y_mean[j];
+    }
+    std::vector<float> wf(ne);
+    for (size_t q = 0; q < ne; ++q) wf[q] = (float)w[q];
+    ak_kcnet *net = new ak_kcnet;
+    net->device = device;
+    net->nl = nl;
+    net->nh = nh;
+    net->nhp = nhp;
+    net->nr = nr;
+    net->x_mean = d->x_mean;
+    net->x_std = d->x_std;
+    net->n_elems = ne;
+    DeviceGuard g(device);
+    if (!g.ok) {
+        delete net;
+        return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, device);
+    }
+    const size_t bytes = ne * (sizeof(double) + sizeof(float));
+    hipError_t e = hipMalloc(&net->dev, bytes);
+    if (e == hipSuccess) e = hipMemcpy(net->dev, w.data(), ne * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(net->dev + ne * sizeof(double), wf.data(), ne * sizeof(float),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (net->dev) (void)hipFree(net->dev);
+        delete net;
+        return hip_error(e, "ak_load_kcnet: upload");
+    }
+    *out = net;
+    return AK_OK;
+}
+
+int ak_free_kcnet(ak_kcnet *net)
+{
+    if (!net) return AK_OK;
+    DeviceGuard g(net->device);
+    (void)hipFree(net->dev);
+    delete net;
+    return AK_OK;
+}
+
+int ak_kcnet_n_out(const ak_kcnet *net) { return net ? net->nr : -1; }
+
+int ak_eval_lnkc_net(const ak_kcnet *net, ak_precision prec, const void *T, int64_t n, void *lnK,
+                     int64_t ldK, void *stream)
+{
+    const char *fn = "ak_eval_lnkc_net";
+    if (!net) return set_error(AK_EINVAL, "%s: null network", fn);
+    int rc = check_prec(fn, prec);
+    if (!rc) rc = check_cells(fn, n);
+    if (rc) return rc;
+    if (n == 0) return AK_OK;
+    if (!T || !lnK) return set_error(AK_EINVAL, "%s: null pointer", fn);
+    if (ldK < n)
+        return set_error(AK_EINVAL, "%s: ldK=%lld < n_cells=%lld", fn, (long long)ldK,
+                         (long long)n);
+    DeviceGuard g(net->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, net->device);
+    hipError_t e = kcnet_launch(net, prec, T, n, lnK, ldK, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "ak_eval_lnkc_net: launch");
+    return AK_OK;
+}
+
+int ak_eval_source_lnkc(const ak_mechanism *m, ak_precision prec, const void *T, const void *P,
+                        const void *Y, int64_t ldY, int64_t n, const void *lnK, int64_t ldK,
+                        void *omega, int64_t ldO, void *stream)
+{
+    const char *fn = "ak_eval_source_lnkc";
+    int rc = check_source(fn, m, prec, T, P, Y, ldY, n, omega, ldO);
+    if (rc) return rc;
+    if (n == 0) return AK_OK;
+    if (!lnK) return set_error(AK_EINVAL, "%s: null lnK", fn);
+    if (ldK < n)
+        return set_error(AK_EINVAL, "%s: ldK=%lld < n_cells=%lld", fn, (long long)ldK,
+                         (long long)n);
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, m->device);
+    const KcRxn *kr;
+    const int32_t *order;
+    if ((rc = kc_tables(m, &kr, &order))) return rc;
+    hipError_t e = source_lnkc_launch(m, order, prec, T, P, Y, ldY, n, lnK, ldK, omega, ldO,
+                                      (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "ak_eval_source_lnkc: launch");
+    return AK_OK;
+}
+
+int ak_eval_source_net(const ak_mechanism *m, const ak_kcnet *net, ak_precision prec,
+                       const void *T, const void *P, const void *Y, int64_t ldY, int64_t n,
+                       void *omega, int64_t ldO, void *stream)
+{
+    const char *fn = "ak_eval_source_net";
+    int rc = check_source(fn, m, prec, T, P, Y, ldY, n, omega, ldO);
+    if (rc) return rc;
+    if (!net) return set_error(AK_EINVAL, "%s: null network", fn);
+    if (net->nr != m->nr)
+        return set_error(AK_EINVAL, "%s: network has %d outputs, mechanism %d reactions", fn,
+                         net->nr, m->nr);
+    if (net->device != m->device)
+        return set_error(AK_EINVAL, "%s: network on device %d, mechanism on %d", fn,
+                         net->device, m->device);
+    if (n == 0) return AK_OK;
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, m->device);
+    const KcRxn *kr;
+    const int32_t *order;
+    if ((rc = kc_tables(m, &kr, &order))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = (size_t)m->nr * (size_t)n * (prec == AK_FP64 ? 8 : 4);
+    void *lnK = nullptr;
+    hipError_t e = hipMallocAsync(&lnK, bytes, st);
+    if (e != hipSuccess)
+        return set_error(AK_ENOMEM, "%s: scratch of %zu bytes: %s", fn, bytes,
+                         hipGetErrorString(e));
+    e = kcnet_launch(net, prec, T, n, lnK, n, st);
+    if (e == hipSuccess)
+        e = source_lnkc_launch(m, order, prec, T, P, Y, ldY, n, lnK, n, omega, ldO, st);
+    const hipError_t ef = hipFreeAsync(lnK, st);
+    if (e != hipSuccess) return hip_error(e, "ak_eval_source_net: launch");
+    if (ef != hipSuccess) return hip_error(ef, "ak_eval_source_net: freeing the scratch");
+    return AK_OK;
+}
+
+}  // extern "C"
