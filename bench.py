@@ -392,6 +392,98 @@ def deriv_bench(torch, annkin, steps=10):
     return out
 
 
+def kc_bench(torch, annkin, steps=20, train=True):
+    """The trained ln K_c network of Sec. 2.3 (Architecture 2) against the
+    exact Gibbs and stoichiometric layers, at the paper's N_C = 10^5 (its
+    Fig. 10 point): the time of each to write ln K_c [N_R, N_C] for the
+    9/21 and 53/325 mechanisms over N_L in {1, 2, 3} x N_H in
+    {8, 16, 32, 64}, FP32 and FP64, and the ratio exact / network.  Both
+    write N_R N_C elements, their HBM bound.  With ``train``, LF (1/8) and HF
+    (3/32) networks are fitted on the GPU to 10^6 (T, ln K_c) pairs of the
+    53/325 mechanism (T ~ U[300, 3000] K, ln K_c from ak_eval_lnkc) and the
+    source term with each network in place of ln K_c is compared with the
+    exact compiled source term on the differentiation states (53/325 x 65,536)."""
+    from paper_2008_08483_amd import kcnet
+    n = 100_000
+    rng = np.random.default_rng(77)
+    out = {"n_cells": n, "definition": "speedup = exact ln K_c time / network time "
+           "(both write ln K_c [N_R, N_C]); hbm_frac = (N_R + 1) N_C s / time / 8 TB/s"}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    grid = [(l, h) for l in (1, 2, 3) for h in (8, 16, 32, 64)]
+    for ns, nr in ((9, 21), (53, 325)):
+        src = synth.make_mechanism(ns, nr)
+        mech = annkin.Mechanism(src)
+        rows = {}
+        for pname, dt, es in (("fp32", torch.float32, 4), ("fp64", torch.float64, 8)):
+            Tt = torch.tensor(rng.uniform(800.0, 2800.0, n), dtype=dt, device="cuda")
+            K = torch.empty((nr, n), dtype=dt, device="cuda")
+            bytes_ = (nr + 1) * n * es
+            t_ex = timed(lambda: annkin.eval_lnkc(mech, Tt, out=K))
+            r = {"exact_ms": t_ex, "exact_hbm_frac": bytes_ / (t_ex * 1e-3) / roofline.PEAK_HBM}
+            for l, h in grid:
+                net = annkin.KcNet(kcnet.random_weights(l, h, nr, seed=l * 100 + h))
+                t = timed(lambda: annkin.eval_lnkc_net(net, Tt, out=K))
+                r[f"{l}/{h}"] = {"ms": t, "speedup": t_ex / t,
+                                 "hbm_frac": bytes_ / (t * 1e-3) / roofline.PEAK_HBM,
+                                 "flops_TF": 2.0 * n * (h + (l - 1) * h * h + h * nr) /
+                                             (t * 1e-3) / 1e12}
+                net.close()
+            rows[pname] = r
+            del Tt, K
+        out[f"{ns}x{nr}"] = rows
+        mech.close()
+    if not train:
+        return out
+    src, T, P, Y = synth.workload("c4")
+    mech = annkin.Mechanism(src)
+    t0 = time.perf_counter()
+    Ttr, Ktr = kcnet.training_set(mech, n=1_000_000, T_range=(300.0, 3000.0), seed=5)
+    out["training_set_s"] = time.perf_counter() - t0
+    Tt, Pt, Yt = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (T, P, Y))
+    ex = annkin.eval_source(mech, Tt, Pt, Yt)
+    Kst = annkin.eval_lnkc(mech, Tt)
+    big = ex.abs() >= 1e-6 * ex.abs().max()
+    Tv = torch.tensor(rng.uniform(300.0, 3000.0, 200_000), dtype=torch.float64, device="cuda")
+    Kv = annkin.eval_lnkc(mech, Tv)
+    t_src = timed(lambda: annkin.eval_source(mech, Tt, Pt, Yt))
+    for tag, (l, h) in (("LF_1x8", (1, 8)), ("HF_3x32", (3, 32))):
+        t0 = time.perf_counter()
+        w = kcnet.train(Ttr, Ktr, l, h, epochs=20, batch=4096, lr=1e-2 if h <= 8 else 3e-3,
+                        seed=1, device="cuda")
+        t_train = time.perf_counter() - t0
+        net = annkin.KcNet(w)
+        dK = (annkin.eval_lnkc_net(net, Tv) - Kv).abs()
+        om = annkin.eval_source_net(mech, net, Tt, Pt, Yt)
+        rel = ((om - ex).abs()[big] / ex.abs()[big]).float()
+        sel = rel[torch.randperm(rel.numel(), device=rel.device)[:1 << 20]]
+        t_net = timed(lambda: annkin.eval_source_net(mech, net, Tt, Pt, Yt))
+        t_lnk = timed(lambda: annkin.eval_source_lnkc(mech, Tt, Pt, Yt, Kst))
+        out[tag] = {"train_s": t_train, "final_mse_standardized": w.history[-1],
+                    "lnK_abs_err_median": float(dK.median()), "lnK_abs_err_max": float(dK.max()),
+                    "omega_rel_err_median": float(sel.median()),
+                    "omega_rel_err_p99": float(torch.quantile(sel, 0.99)),
+                    "source_net_ms": t_net, "source_given_lnK_ms": t_lnk,
+                    "exact_compiled_source_ms": t_src}
+        net.close()
+    out["accuracy_definition"] = ("FP64; omega with the network's ln K_c against the exact "
+                                  "compiled source term on the 65,536 c4 states, |d|/|w| over "
+                                  "entries with |w| >= 1e-6 max|w|; ln K_c errors on 2e5 "
+                                  "temperatures in the training range")
+    mech.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -409,6 +501,9 @@ def main():
                     help="time only the main FP32 leg (for profiler runs)")
     ap.add_argument("--only-deriv", action="store_true",
                     help="time only the differentiation configuration (for profiler runs)")
+    ap.add_argument("--no-kc", action="store_true")
+    ap.add_argument("--only-kc", action="store_true",
+                    help="time only the ln K_c network study (no training)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -423,6 +518,10 @@ def main():
     if args.only_deriv:
         from paper_2008_08483_amd import annkin
         print(json.dumps({"differentiation": deriv_bench(torch, annkin)}), flush=True)
+        return
+    if args.only_kc:
+        from paper_2008_08483_amd import annkin
+        print(json.dumps({"approx_lnkc": kc_bench(torch, annkin, train=False)}), flush=True)
         return
     from paper_2008_08483_amd import annkin
 
@@ -504,7 +603,7 @@ def main():
 
     if args.only_main:
         args.no_fp64 = args.no_cpu_baseline = args.no_serving = args.no_deriv = True
-        args.no_c2 = args.no_saturation = args.no_pdep = True
+        args.no_c2 = args.no_saturation = args.no_pdep = args.no_kc = True
     result["kernel_compiled"] = bool(mech.compiled(torch.float32))
     if not args.only_main:
         result["accuracy"] = accuracy(torch, annkin, mech, src, T, P, Y)
@@ -548,6 +647,9 @@ def main():
 
     if not args.no_deriv:
         result["differentiation"] = deriv_bench(torch, annkin)
+
+    if not args.no_kc:
+        result["approx_lnkc"] = kc_bench(torch, annkin)
 
     if not args.no_serving:
         result["serving"] = serving_bench(torch, annkin)

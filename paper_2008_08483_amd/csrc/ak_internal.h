@@ -36,6 +36,7 @@ struct ak_mechanism {
     // the ln K_c tables (descriptor-order reactions, sorted-to-descriptor
     // index), uploaded at the first call that needs them
     mutable unsigned char *kc_dev = nullptr;
+    mutable bool kc_wide = false;   // a reaction has more than 4 distinct species
 };
 
 namespace ak {

@@ -34,6 +34,19 @@ struct ak_kcnet {
     size_t n_elems = 0;                    // elements per precision
 };
 
+// Tuning: reaction rows per unrolled group in the two row loops, and how
+// much hidden-layer recomputation (as a fraction 1/AK_KCNET_CHUNK_DIV of the
+// readout's work) the output chunks may add.
+#ifndef AK_KCNET_UNROLL
+#define AK_KCNET_UNROLL 2
+#endif
+#ifndef AK_LNKC_UNROLL
+#define AK_LNKC_UNROLL 8
+#endif
+#ifndef AK_KCNET_CHUNK_DIV
+#define AK_KCNET_CHUNK_DIV 4
+#endif
+
 namespace ak {
 
 // Per reaction, descriptor order (32 B): the distinct species of the
@@ -50,20 +63,29 @@ namespace {
 
 constexpr double kLn2 = 0.693147180559945309417232121458;
 
+// Both NASA ranges with uniform (scalar) coefficients, then the per-cell
+// choice: a per-lane choice of coefficient address would make every load a
+// vector load.
 __device__ __forceinline__ double g2_of(const SpeciesRec &sr, double T, double lnT, double T2,
                                         double T3, double T4, double invT)
 {
-    const double *w = T >= sr.T_mid ? sr.hi : sr.lo;
-    return w[0] * lnT + w[1] * T + w[2] * T2 + w[3] * T3 + w[4] * T4 + w[5] * invT + w[6];
+    const double glo = sr.lo[0] * lnT + sr.lo[1] * T + sr.lo[2] * T2 + sr.lo[3] * T3 +
+                       sr.lo[4] * T4 + sr.lo[5] * invT + sr.lo[6];
+    const double ghi = sr.hi[0] * lnT + sr.hi[1] * T + sr.hi[2] * T2 + sr.hi[3] * T3 +
+                       sr.hi[4] * T4 + sr.hi[5] * invT + sr.hi[6];
+    return T >= sr.T_mid ? ghi : glo;
 }
 
-// One 64-cell tile per workgroup (one wave), lane = cell.  Each lane keeps
-// its cell's Gibbs-layer outputs g2_k = log2(e) (G_k - ln(p_ref/(R T))) in
-// its own LDS column, so no barrier is needed; every reaction row is then
-// one coalesced store of 64 cells.
-template <typename IO>
+// One 64-cell tile per workgroup (one wave), lane = cell; blockIdx.y picks
+// a chunk of `rpc` reactions, so that a batch of few tiles still gives the
+// chip enough waves.  Each lane keeps its cell's Gibbs-layer outputs
+// g2_k = log2(e) (G_k - ln(p_ref/(R T))) in its own LDS column (no barrier
+// needed); every reaction row is one coalesced store of 64 cells.  MAXT is
+// the records' entry count (unused entries carry nu = 0), so the reaction
+// loop has no data-dependent trip count and unrolls.
+template <typename IO, int MAXT>
 __global__ __launch_bounds__(64) void lnkc_kernel(MechView m, const KcRxn *__restrict__ kr,
-                                                  const IO *__restrict__ T, int64_t n,
+                                                  int rpc, const IO *__restrict__ T, int64_t n,
                                                   IO *__restrict__ lnK, int64_t ldK)
 {
     extern __shared__ double g2[];
@@ -76,13 +98,16 @@ __global__ __launch_bounds__(64) void lnkc_kernel(MechView m, const KcRxn *__res
     const double lnT = log(Tc), T2 = Tc * Tc, T3 = T2 * Tc, T4 = T3 * Tc, invT = 1.0 / Tc;
     for (int k = 0; k < m.ns; ++k) g2[k * 64 + lane] = g2_of(m.sp[k], Tc, lnT, T2, T3, T4, invT);
     const IO nan = (IO)__builtin_nan("");
-    for (int j = 0; j < m.nr; ++j) {
+    const int j0 = blockIdx.y * rpc, j1 = min(m.nr, j0 + rpc);
+#pragma unroll AK_LNKC_UNROLL
+    for (int j = j0; j < j1; ++j) {
         const KcRxn *r = &kr[j];
         double acc = 0.0;
-        for (int q = 0; q < r->cnt; ++q) acc += (double)r->nu[q] * g2[r->sp[q] * 64 + lane];
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) acc += (double)r->nu[q] * g2[r->sp[q] * 64 + lane];
         if (live) lnK[(int64_t)j * ldK + i] = bad ? nan : (IO)(-acc * kLn2);
     }
-    if (live && bad) atomicAdd(m.err, 1ull);
+    if (live && bad && blockIdx.y == 0) atomicAdd(m.err, 1ull);
 }
 
 // f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile
@@ -112,9 +137,11 @@ __device__ __forceinline__ E elu(E x)
 //   deviation and mean folded in.
 // Every weight index is uniform across the wave (scalar loads); the
 // activations stay in registers.  Sums run in a fixed order.
+// blockIdx.y picks a chunk of `rpc` outputs (each chunk recomputes the
+// hidden layers of its cells: cheap next to the readout when it is chosen).
 template <typename E, int NH>
 __global__ __launch_bounds__(256) void kcnet_kernel(const E *__restrict__ w, int nl, int nr,
-                                                    double x_mean, double x_std,
+                                                    int rpc, double x_mean, double x_std,
                                                     const E *__restrict__ T, int64_t n,
                                                     E *__restrict__ lnK, int64_t ldK)
 {
@@ -138,7 +165,9 @@ __global__ __launch_bounds__(256) void kcnet_kernel(const E *__restrict__ w, int
     }
     const E *bo = p + (int64_t)nr * NH;
     const E nan = (E)__builtin_nan("");
-    for (int j = 0; j < nr; ++j) {
+    const int j0 = blockIdx.y * rpc, j1 = min(nr, j0 + rpc);
+#pragma unroll AK_KCNET_UNROLL
+    for (int j = j0; j < j1; ++j) {
         const E *wj = p + (int64_t)j * NH;
         E acc = bo[j];
         static_for<0, NH>([&](auto q) { acc = __builtin_fma(h[q], wj[q], acc); });
@@ -185,6 +214,8 @@ __global__ __launch_bounds__(64) void source_lnkc_kernel(MechView m,
         acc[k * 64 + lane] = 0.0;
     }
     const double log2T = log2(Tu), invT = 1.0 / Tu;
+    // unrolled so that several reactions' ln K_c loads are in flight at once
+#pragma unroll 4
     for (int j = 0; j < m.nr; ++j) {
         const RxnRec *r = &m.rx[j];
         const RxnAux *x = &m.aux[j];
@@ -246,6 +277,9 @@ int kc_tables(const ak_mechanism *m, const KcRxn **kr, const int32_t **order)
                     ++r.cnt;
                 }
         }
+        int maxcnt = 0;
+        for (const KcRxn &r : t) maxcnt = std::max(maxcnt, (int)r.cnt);
+        m->kc_wide = maxcnt > 4;
         std::vector<int32_t> ord(m->rxn_order.begin(), m->rxn_order.end());
         const size_t bytes = sizeof(KcRxn) * nr + sizeof(int32_t) * nr;
         unsigned char *d = nullptr;
@@ -279,16 +313,40 @@ int check_cells(const char *fn, int64_t n)
     return AK_OK;
 }
 
+// Reaction (or output) chunks per tile: enough that the grid holds about
+// `target` waves, at least `minr` rows per chunk, and at most `cap` chunks.
+int chunks_for(int64_t tiles, int nr, int64_t target, int minr, int64_t cap)
+{
+    int64_t c = (target + tiles - 1) / tiles;
+    c = std::min<int64_t>(c, std::max(1, nr / minr));
+    c = std::min<int64_t>(c, std::max<int64_t>(1, cap));
+    return (int)std::max<int64_t>(1, c);
+}
+
+constexpr int64_t kTargetWaves = 8192;   // 8 per SIMD
+
+template <typename T>
+struct Tag {
+    using type = T;
+};
+
 template <typename E>
 hipError_t launch_kcnet(const ak_kcnet *net, const E *w, const void *T, int64_t n, void *lnK,
                         int64_t ldK, hipStream_t st)
 {
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 g((unsigned)blocks), b(256);
+    // a chunk repeats the hidden layers: keep that below the readout's work
+    const int64_t hidden = (int64_t)net->nhp * (1 + 8 * net->nl) +
+                           (int64_t)(net->nl - 1) * net->nhp * net->nhp;
+    const int64_t readout = (int64_t)net->nhp * net->nr;
+    const int ch = chunks_for((n + 63) / 64, net->nr, kTargetWaves, 16,
+                              readout / (hidden * AK_KCNET_CHUNK_DIV));
+    const int rpc = (net->nr + ch - 1) / ch;
+    const dim3 g((unsigned)blocks, (unsigned)((net->nr + rpc - 1) / rpc)), b(256);
 #define AK_KCNET(NH)                                                                         \
-    hipLaunchKernelGGL((kcnet_kernel<E, NH>), g, b, 0, st, w, net->nl, net->nr, net->x_mean,  \
-                       net->x_std, (const E *)T, n, (E *)lnK, ldK)
+    hipLaunchKernelGGL((kcnet_kernel<E, NH>), g, b, 0, st, w, net->nl, net->nr, rpc,          \
+                       net->x_mean, net->x_std, (const E *)T, n, (E *)lnK, ldK)
     switch (net->nhp) {
         case 8: AK_KCNET(8); break;
         case 16: AK_KCNET(16); break;
@@ -382,24 +440,28 @@ int ak_eval_lnkc(const ak_mechanism *m, ak_precision prec, const void *T, int64_
     if (blocks > 0x7fffffff) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
     const size_t lds = lnkc_lds(m->ns);
     hipStream_t st = (hipStream_t)stream;
+    // each chunk repeats the Gibbs layer (14 ns FMAs per cell): at most as
+    // many chunks as make that the stoichiometric layer's work (~4 per row)
+    const int ch = chunks_for(blocks, m->nr, kTargetWaves, 16,
+                              std::max(1, (4 * m->nr) / (14 * m->ns)) * 2);
+    const int rpc = (m->nr + ch - 1) / ch;
+    const dim3 grid((unsigned)blocks, (unsigned)((m->nr + rpc - 1) / rpc));
     hipError_t e;
-    if (prec == AK_FP64) {
-        auto k = lnkc_kernel<double>;
-        e = allow_dynamic_lds((const void *)k);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64), lds, st, m->view, kr,
-                               (const double *)T, n, (double *)lnK, ldK);
-            e = hipGetLastError();
-        }
-    } else {
-        auto k = lnkc_kernel<float>;
-        e = allow_dynamic_lds((const void *)k);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64), lds, st, m->view, kr,
-                               (const float *)T, n, (float *)lnK, ldK);
-            e = hipGetLastError();
-        }
-    }
+    auto go = [&](auto kern, auto tp) {
+        using IO = typename decltype(tp)::type;
+        hipError_t r = allow_dynamic_lds((const void *)kern);
+        if (r != hipSuccess) return r;
+        hipLaunchKernelGGL(kern, grid, dim3(64), lds, st, m->view, kr, rpc, (const IO *)T, n,
+                           (IO *)lnK, ldK);
+        return hipGetLastError();
+    };
+    const bool wide = m->kc_wide;
+    if (prec == AK_FP64)
+        e = wide ? go(lnkc_kernel<double, 8>, Tag<double>{})
+                 : go(lnkc_kernel<double, 4>, Tag<double>{});
+    else
+        e = wide ? go(lnkc_kernel<float, 8>, Tag<float>{})
+                 : go(lnkc_kernel<float, 4>, Tag<float>{});
     if (e != hipSuccess) return hip_error(e, "ak_eval_lnkc: launch");
     return AK_OK;
 }
