@@ -91,6 +91,9 @@ def _lib_handle():
             getattr(lib, f"ora_jacobian_scaled_{sfx}").argtypes = [
                 C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                 C.c_void_p, C.c_void_p, C.c_int64, C.c_int]
+            getattr(lib, f"ora_integrate_implicit_{sfx}").argtypes = [
+                C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                C.c_double, C.c_int]
             getattr(lib, f"ora_lnkc_{sfx}").argtypes = [C.c_void_p, C.c_int64, C.c_void_p,
                                                         C.c_void_p, C.c_int64]
             getattr(lib, f"ora_source_lnkc_{sfx}").argtypes = [
@@ -209,6 +212,27 @@ def source(mech, T, P, Y, precision: str = "f64", scales: bool = False, n_thread
     if rc:
         raise RuntimeError("oracle source failed")
     return (om, S, N) if scales else om
+
+
+def integrate_implicit(mech, T, P, Y, dt: float, n_steps: int, precision: str = "f64"):
+    """0-D constant-pressure reactor, n_steps linearly implicit Euler steps of
+    dt: (I - dt Jf) dx = dt f(x) with f = (W omega / rho, omega_T) and Jf from
+    the analytic Jacobian, rho held at the step's start (Sec. 4's stiff
+    integration).  Returns new (T [n], Y [NS, n]); P [n] is held fixed."""
+    m = _as_mech(mech)
+    _dtype(precision)
+    T = np.array(T, dtype=np.float64, copy=True)
+    P = _f64(P)
+    Y = np.array(Y, dtype=np.float64, copy=True, order="C")
+    n = T.shape[0]
+    assert P.shape == (n,) and Y.shape == (m.ns, n)
+    rc = getattr(_lib_handle(), f"ora_integrate_implicit_{precision}")(
+        m.ptr, n, T.ctypes.data, P.ctypes.data, Y.ctypes.data, n, float(dt), int(n_steps))
+    if rc == -2:
+        raise NotImplementedError("oracle Jacobian of third-body and falloff reactions")
+    if rc:
+        raise RuntimeError(f"oracle integrate_implicit failed ({rc})")
+    return T, Y
 
 
 def lnkc(mech, T, precision: str = "f64"):

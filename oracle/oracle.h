@@ -72,7 +72,9 @@ typedef struct {
     int ora_lnkc_##S(const ora_mech *m, int64_t n, const double *T, R *lnK, int64_t ldK);       \
     int ora_source_lnkc_##S(const ora_mech *m, int64_t n, const double *T, const double *P,    \
                             const double *Y, int64_t ldY, const double *lnK, int64_t ldK,      \
-                            R *omega, R *S, R *N, int64_t ldO, int n_threads);
+                            R *omega, R *S, R *N, int64_t ldO, int n_threads);          \
+    int ora_integrate_implicit_##S(const ora_mech *m, int64_t n, double *T, const double *P,   \
+                                   double *Y, int64_t ldY, double dt, int n_steps);
 
 ORA_DECL(double, f64)
 ORA_DECL(long double, ld)

@@ -531,3 +531,96 @@ int SFX(ora_integrate_euler)(const ora_mech *m, int64_t n, double *T, const doub
     }
     return err;
 }
+
+/* Solve A x = b in place for one dense system of order nv (A row-major,
+ * overwritten), Gaussian elimination with partial pivoting (the largest
+ * remaining |A[i][k]| in column k becomes the pivot); b becomes x.
+ * Returns -1 for a zero pivot. */
+static int SFX(gauss_solve)(int nv, REAL *A, REAL *b)
+{
+    for (int k = 0; k < nv; ++k) {
+        int p = k;
+        for (int i = k + 1; i < nv; ++i)
+            if (FABS(A[i * nv + k]) > FABS(A[p * nv + k])) p = i;
+        if (A[p * nv + k] == 0) return -1;
+        if (p != k) {
+            for (int c = 0; c < nv; ++c) {
+                REAL t = A[k * nv + c];
+                A[k * nv + c] = A[p * nv + c];
+                A[p * nv + c] = t;
+            }
+            REAL t = b[k];
+            b[k] = b[p];
+            b[p] = t;
+        }
+        for (int i = k + 1; i < nv; ++i) {
+            REAL l = A[i * nv + k] / A[k * nv + k];
+            if (l == 0) continue;
+            for (int c = k; c < nv; ++c) A[i * nv + c] -= l * A[k * nv + c];
+            b[i] -= l * b[k];
+        }
+    }
+    for (int k = nv - 1; k >= 0; --k) {
+        REAL v = b[k];
+        for (int c = k + 1; c < nv; ++c) v -= A[k * nv + c] * b[c];
+        b[k] = v / A[k * nv + k];
+    }
+    return 0;
+}
+
+/* 0-D constant-pressure reactor, linearly implicit Euler steps (the stiff
+ * integration the paper names as the next step, Sec. 4): with x = (Y, T),
+ *     f(x) = (W_k omega_k / rho, omega_T),
+ *     (I - dt Jf) dx = dt f(x),   x <- x + dx,
+ * where Jf has the rows (W_k / rho) d omega_k / dx and d omega_T / dx from
+ * the analytic Jacobian (ora_jacobian), rho held at its value at x (a
+ * W-method: the step is first-order accurate with any such matrix, and with
+ * Jf exact it is one Newton iteration of backward Euler).  P is fixed; the
+ * state is carried in double between steps.  Cells run one after another.
+ * Returns -2 for mechanisms the Jacobian does not cover, -3 for a singular
+ * system. */
+int SFX(ora_integrate_implicit)(const ora_mech *m, int64_t n, double *T, const double *P,
+                                double *Y, int64_t ldY, double dt, int n_steps)
+{
+    const int ns = m->ns, nv = ns + 1;
+    REAL *J = (REAL *)malloc(sizeof(REAL) * (nv * nv * 2 + 4 * nv));
+    double *Yc = (double *)malloc(sizeof(double) * ns);
+    if (!J || !Yc) { free(J); free(Yc); return -1; }
+    REAL *A = J + nv * nv, *b = A + nv * nv, *om = b + nv, *C = om + nv;
+    int rc = 0;
+    for (int64_t i = 0; i < n && !rc; ++i) {
+        double Ti = T[i], Pi = P[i];
+        for (int k = 0; k < ns; ++k) Yc[k] = Y[k * ldY + i];
+        for (int step = 0; step < n_steps && !rc; ++step) {
+            REAL omT;
+            if ((rc = SFX(ora_jacobian)(m, 1, &Ti, &Pi, Yc, 1, J, nv * nv, 1))) break;
+            if ((rc = SFX(ora_source)(m, 1, &Ti, &Pi, Yc, 1, om, 0, 0, 1, 1))) break;
+            if ((rc = SFX(ora_temp_source)(m, 1, &Ti, &Pi, Yc, 1, &omT, 1))) break;
+            /* rho = sum_k C_k W_k at the current state */
+            REAL rho = 0, sum = 0;
+            for (int k = 0; k < ns; ++k) {
+                REAL y = Yc[k] > 0 ? (REAL)Yc[k] : 0;
+                sum += y / (REAL)m->W[k];
+            }
+            for (int k = 0; k < ns; ++k) {
+                REAL y = Yc[k] > 0 ? (REAL)Yc[k] : 0;
+                C[k] = (REAL)Pi / ((REAL)ORA_RU * (REAL)Ti * sum) * y / (REAL)m->W[k];
+                rho += C[k] * (REAL)m->W[k];
+            }
+            for (int r = 0; r < nv; ++r) {
+                REAL s = r < ns ? (REAL)m->W[r] / rho : 1;
+                for (int c = 0; c < nv; ++c)
+                    A[r * nv + c] = (r == c ? 1 : 0) - (REAL)dt * s * J[r * nv + c];
+                b[r] = (REAL)dt * (r < ns ? s * om[r] : omT);
+            }
+            if (SFX(gauss_solve)(nv, A, b)) { rc = -3; break; }
+            for (int k = 0; k < ns; ++k) Yc[k] = (double)((REAL)Yc[k] + b[k]);
+            Ti = (double)((REAL)Ti + b[ns]);
+        }
+        T[i] = Ti;
+        for (int k = 0; k < ns; ++k) Y[k * ldY + i] = Yc[k];
+    }
+    free(J);
+    free(Yc);
+    return rc;
+}
