@@ -386,6 +386,14 @@ def deriv_bench(torch, annkin, steps=10):
             finally:
                 del os.environ["AK_JIT_JACOBIAN"]
         res["jacobian_roofline_ms"] = jbytes / roofline.PEAK_HBM * 1e3
+        # one linearly implicit Euler step of the 0-D reactor (Jacobian,
+        # source term, then one workgroup per cell solving its 54 x 54
+        # system), on copies of the states; dt far past explicit stability
+        T2, Y2 = Tt.clone(), Yt.clone()
+        res["implicit_step_ms"] = timed(
+            lambda: annkin.integrate_implicit(mech, T2, Pt, Y2, 1e-12, 1))
+        res["implicit_step_cells_per_s"] = n / (res["implicit_step_ms"] * 1e-3)
+        del T2, Y2
         out[name] = res
         del Tt, Pt, Yt, J, g
     mech.close()

@@ -329,6 +329,27 @@ int ak_integrate_euler(const ak_mechanism *mech, ak_precision prec, void *T, con
                        void *stream);
 
 /*
+ * The same reactor advanced by n_steps linearly implicit Euler steps (the
+ * stiff integration Sec. 4 calls for), each using the state Jacobian: with
+ * x = (Y, T) and f(x) = (W_k omega_k / rho, omega_T),
+ *     (I - dt Jf) dx = dt f(x),   x <- x + dx,
+ * where Jf has the rows (W_k / rho) d omega_k / dx and d omega_T / dx
+ * (ak_eval_jacobian) and rho is held at the step's start.  A step stays
+ * bounded far beyond the explicit stability limit and conserves total mass
+ * fraction and elements.  Per step: the Jacobian and omega into scratch
+ * (n_cells ((NS+1)^2 + NS) elements, allocated and freed stream-ordered),
+ * then one workgroup per cell solves its (NS+1) x (NS+1) system in LDS
+ * (Gaussian elimination with partial pivoting, fixed reduction order).  A
+ * cell whose system is singular or whose state is bad gets NaN and is
+ * counted (ak_error_count).  Errors: as ak_integrate_euler, AK_EUNSUPPORTED
+ * for mechanisms ak_eval_jacobian does not take (third-body or falloff
+ * reactions) or systems larger than the LDS, AK_ENOMEM.
+ */
+int ak_integrate_implicit(const ak_mechanism *mech, ak_precision prec, void *T, const void *P,
+                          void *Y, int64_t ldY, int64_t n_cells, double dt, int n_steps,
+                          void *stream);
+
+/*
  * ak_integrate_euler without any allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid it).  Same arguments, results and errors; the

@@ -96,6 +96,9 @@ def lib():
         h.ak_integrate_euler.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_int64, C.c_int64, C.c_double, C.c_int,
                                          C.c_void_p]
+        h.ak_integrate_implicit.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_int64, C.c_int64, C.c_double,
+                                            C.c_int, C.c_void_p]
         h.ak_free_mechanism.argtypes = [C.c_void_p]
         h.ak_mechanism_n_species.argtypes = [C.c_void_p]
         h.ak_mechanism_n_reactions.argtypes = [C.c_void_p]
@@ -564,6 +567,17 @@ def eval_source_net(mech: Mechanism, net: KcNet, T, P, Y, out=None, stream=None)
                                     P.data_ptr(), Y.data_ptr(), ldY, n, out.data_ptr(), ldO,
                                     _stream_ptr(stream)))
     return out
+
+
+def integrate_implicit(mech: Mechanism, T, P, Y, dt: float, n_steps: int, stream=None):
+    """Advance (T [n], Y [NS, n]) in place by n_steps linearly implicit
+    Euler steps of dt seconds ((I - dt Jf) dx = dt f, Jf from the state
+    Jacobian; Sec. 4's stiff integration) at fixed P [n].  Asynchronous."""
+    n = _check_state(mech, T, P, Y)
+    _check(lib().ak_integrate_implicit(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
+                                       Y.data_ptr(), Y.stride(0), n, float(dt), int(n_steps),
+                                       _stream_ptr(stream)))
+    return T, Y
 
 
 def _source_function():

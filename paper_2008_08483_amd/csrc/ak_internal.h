@@ -67,6 +67,10 @@ hipError_t source_batch_launch(bool f64, const BatchDesc *d_desc, int nreq, int6
 hipError_t euler_update_launch(const MechView &m, bool f64, void *T, const void *P, void *Y,
                                int64_t ldY, int64_t n, const void *om, int64_t ldO, double dt,
                                hipStream_t st);
+size_t implicit_lds_bytes(int ns);
+hipError_t implicit_update_launch(const MechView &m, bool f64, void *T, const void *P, void *Y,
+                                  int64_t ldY, int64_t n, const void *om, int64_t ldO,
+                                  const void *J, int64_t ldJ, double dt, hipStream_t st);
 // Argument checks of the integrators (fn names the entry point in messages)
 // and their body: n_steps of (source term into `omega` [NS][n], update).
 int integrate_check(const char *fn, const ak_mechanism *m, int prec, const void *T,

@@ -855,6 +855,48 @@ int ak_integrate_euler(const ak_mechanism *m, ak_precision prec, void *T, const 
     return AK_OK;
 }
 
+int ak_integrate_implicit(const ak_mechanism *m, ak_precision prec, void *T, const void *P,
+                          void *Y, int64_t ldY, int64_t n, double dt, int n_steps, void *stream)
+{
+    const char *fn = "ak_integrate_implicit";
+    int rc = integrate_check(fn, m, prec, T, P, Y, ldY, n, dt, n_steps);
+    if (rc) return rc;
+    if (m->pdep)
+        return set_error(AK_EUNSUPPORTED, "%s: third-body and falloff reactions are not "
+                                          "differentiated", fn);
+    if (implicit_lds_bytes(m->ns) > (size_t)m->lds_max)
+        return set_error(AK_EUNSUPPORTED, "%s: %d species exceed the LDS", fn, m->ns);
+    if (n == 0 || n_steps == 0) return AK_OK;
+    if (n > 0x7fffffff) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, m->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t es = prec == AK_FP64 ? 8 : 4;
+    const int64_t nv = (int64_t)m->ns + 1;
+    const size_t jbytes = (size_t)n * nv * nv * es, obytes = (size_t)m->ns * n * es;
+    void *scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, jbytes + obytes + 256, st);
+    if (e != hipSuccess)
+        return set_error(AK_ENOMEM, "%s: scratch of %zu bytes: %s", fn, jbytes + obytes,
+                         hipGetErrorString(e));
+    void *J = scratch;
+    void *om = (unsigned char *)scratch + ((jbytes + 255) & ~(size_t)255);
+    const JitKernels &jk = m->jit[prec];
+    for (int s = 0; s < n_steps && !rc; ++s) {
+        if ((rc = ak_eval_jacobian(m, prec, T, P, Y, ldY, n, J, nv * nv, stream))) break;
+        e = jk.src ? jit_launch(jk, T, P, Y, ldY, n, om, n, m->view.err, st)
+                   : source_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, om, n, st);
+        if (e == hipSuccess)
+            e = implicit_update_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, om, n, J,
+                                       nv * nv, dt, st);
+        if (e != hipSuccess) rc = hip_error(e, "ak_integrate_implicit: step");
+    }
+    e = hipFreeAsync(scratch, st);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_error(e, "ak_integrate_implicit: freeing the scratch");
+    return AK_OK;
+}
+
 int ak_error_count(const ak_mechanism *m, void *stream, int64_t *n_bad)
 {
     if (!m || !n_bad) return set_error(AK_EINVAL, "ak_error_count: null argument");

@@ -92,3 +92,106 @@ def test_euler_argument_errors(torch, ak):
     torch.cuda.synchronize()
     assert torch.equal(T, T0)
     m.close()
+
+
+# ---------------------------------------------------------------------------
+# linearly implicit Euler (Sec. 4's stiff integration): (I - dt Jf) dx = dt f
+# with the state Jacobian.  Tolerances: FP64 within 1e-11 of the mass
+# fraction sum and 1e-12 relative in T (the oracle's double and extended
+# results differ by below 1e-13 on these cases); FP32 one step as above,
+# widened to 1e-4 of the change for the float Jacobian.
+
+@pytest.mark.parametrize("ns,nr,n,dt,steps", [(9, 21, 300, 1e-12, 1), (9, 21, 300, 1e-12, 10),
+                                              (53, 325, 130, 1e-12, 1),
+                                              (53, 325, 130, 1e-10, 10)])
+def test_implicit_fp64_against_oracle(torch, ak, ns, nr, n, dt, steps):
+    src = synth.make_mechanism(ns, nr, **MILD)
+    m = ak.Mechanism(src)
+    T, P, Y = synth.make_states(src, n, 23, (1000.0, 2500.0), (1.0, 20.0), 0.5)
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    ak.integrate_implicit(m, Tt, Pt, Yt, dt, steps)
+    torch.cuda.synchronize()
+    T1, Y1 = oracle.integrate_implicit(src, T, P, Y, dt, steps, precision="ld")
+    assert np.abs(T1 - T).max() > 1.0                          # the state moved
+    np.testing.assert_allclose(Tt.cpu().numpy(), T1, rtol=1e-12, atol=0)
+    assert np.abs(Yt.cpu().numpy() - Y1).max() <= 1e-11 * Y.sum(axis=0).max()
+    assert m.error_count() == 0
+    m.close()
+
+
+def test_implicit_fp32_one_step(torch, ak):
+    src = synth.make_mechanism(53, 325, **MILD)
+    m = ak.Mechanism(src)
+    T, P, Y = (a.astype(np.float32) for a in
+               synth.make_states(src, 257, 24, (1000.0, 2500.0), (1.0, 20.0), 0.5))
+    dt = 1e-11
+    Tt, Pt, Yt = _dev(torch, torch.float32, T, P, Y)
+    ak.integrate_implicit(m, Tt, Pt, Yt, dt, 1)
+    torch.cuda.synchronize()
+    T64, P64, Y64 = (a.astype(np.float64) for a in (T, P, Y))
+    T1, Y1 = oracle.integrate_implicit(src, T64, P64, Y64, dt, 1)
+    dT, dY = T1 - T64, Y1 - Y64
+    gT = Tt.cpu().numpy().astype(np.float64) - T64
+    gY = Yt.cpu().numpy().astype(np.float64) - Y64
+    ulpT = np.spacing(np.abs(T1).astype(np.float32)).astype(np.float64)
+    ulpY = np.spacing(np.abs(Y1).astype(np.float32)).astype(np.float64)
+    assert np.abs(dT).max() > 1.0
+    assert np.all(np.abs(gT - dT) <= 1e-4 * np.abs(dT).max() + 2 * ulpT)
+    assert np.all(np.abs(gY - dY) <= 1e-4 * np.abs(dY).max() + 2 * ulpY)
+    m.close()
+
+
+@pytest.mark.parametrize("kdt", [1e-3, 1.0, 250.0])
+def test_implicit_first_order_reaction_is_backward_euler(torch, ak, kdt):
+    # A -> B with equal molar masses and thermodynamics, k = A: one step is
+    # Y_A / (1 + k dt) and T stays put (the oracle's pin, on the GPU path)
+    import math
+
+    from tests.test_oracle_pins import _Mech, _nasa
+    k = 2.5e4
+    src = _Mech([20.0, 20.0], [[1, 0]], [[0, 1]], [math.log(k)], [0.0], [0.0],
+                _nasa([3.5, 3.5], [-1200.0, -1200.0]), rev=[0])
+    m = ak.Mechanism(src)
+    Tt, Pt, Yt = _dev(torch, torch.float64, np.full(70, 1400.0), np.full(70, 2e5),
+                      np.vstack([np.full(70, 0.7), np.full(70, 0.3)]))
+    ak.integrate_implicit(m, Tt, Pt, Yt, kdt / k, 1)
+    torch.cuda.synchronize()
+    assert torch.all(Tt == 1400.0)
+    ya = Yt[0].cpu().numpy()
+    # the solve's rounding: a few ulps of the system's scale (1 + k dt) |Y|
+    np.testing.assert_allclose(ya, 0.7 / (1 + kdt), rtol=0,
+                               atol=4 * 2.0 ** -53 * (1 + kdt) * 0.7)
+    np.testing.assert_allclose(Yt.sum(dim=0).cpu().numpy(), 1.0, rtol=1e-14)
+    m.close()
+
+
+def test_implicit_conservation_bad_cells_and_refusals(torch, ak):
+    src = synth.make_mechanism(53, 325, **MILD)
+    m = ak.Mechanism(src)
+    T, P, Y = synth.make_states(src, 200, 25, (1000.0, 2500.0), (1.0, 20.0), 0.5)
+    T[7] = np.nan
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    m.error_count()
+    ak.integrate_implicit(m, Tt, Pt, Yt, 1e-11, 20)   # 400 x the explicit limit
+    torch.cuda.synchronize()
+    Tn, Yn = Tt.cpu().numpy(), Yt.cpu().numpy()
+    assert np.isnan(Tn[7]) and np.all(np.isnan(Yn[:, 7]))
+    ok = np.arange(200) != 7
+    assert np.all(np.isfinite(Tn[ok])) and np.all(np.isfinite(Yn[:, ok]))
+    # conserved up to rounding amplified by the systems' conditioning (the
+    # oracle in double drifts by 2e-12 on the same states)
+    assert np.abs(Yn[:, ok].sum(axis=0) - Y[:, ok].sum(axis=0)).max() < 1e-11
+    el0 = src.atoms.T.astype(float) @ (Y[:, ok] / src.W[:, None])
+    el1 = src.atoms.T.astype(float) @ (Yn[:, ok] / src.W[:, None])
+    assert np.abs(el1 - el0).max() <= 1e-11 * np.abs(el0).max()
+    assert m.error_count() >= 1
+    pd = ak.Mechanism(synth.with_pressure_dependence(synth.make_mechanism(9, 21), frac=0.5))
+    T2, P2, Y2 = _dev(torch, torch.float64, *synth.make_states(synth.make_mechanism(9, 21), 8, 1))
+    with pytest.raises(ak.AnnkinError) as e:
+        ak.integrate_implicit(pd, T2, P2, Y2, 1e-12, 1)
+    assert e.value.code == -7
+    with pytest.raises(ak.AnnkinError) as e:
+        ak.integrate_implicit(m, Tt, Pt, Yt, -1.0, 1)
+    assert e.value.code == -1
+    m.close()
+    pd.close()
