@@ -382,11 +382,14 @@ int ak_error_count(const ak_mechanism *mech, void *stream, int64_t *n_bad_cells)
 /*
  * ln K_c of every reaction from the Gibbs layer and the net stoichiometric
  * layer (Eqs. 9-11): ln K_c,j = -sum_k nu_kj (G_k - ln(p_ref/(R T))), with
- * the NASA-7 range chosen per species and cell.  The arithmetic is double
- * in both precisions (AK_FP32 rounds the result).  A cell with T <= 0 or
- * non-finite T gets NaN and is counted (ak_error_count).  Errors: AK_EINVAL,
- * AK_EUNSUPPORTED (more species than the LDS holds: 8 * 64 bytes each),
- * AK_EDEVICE.
+ * the NASA-7 range chosen per species and cell.  The two linear layers are
+ * composed per reaction and temperature interval (the intervals between the
+ * distinct T_mid of its species; at most 3 such T_mid per reaction, else
+ * the layers run separately, the Gibbs outputs in LDS).  The arithmetic is
+ * double in both precisions (AK_FP32 rounds the result).  A cell with
+ * T <= 0 or non-finite T gets NaN and is counted (ak_error_count).
+ * Errors: AK_EINVAL, AK_EUNSUPPORTED (the separate form with more species
+ * than the LDS holds: 8 * 64 bytes each), AK_EDEVICE.
  */
 int ak_eval_lnkc(const ak_mechanism *mech, ak_precision prec, const void *T, int64_t n_cells,
                  void *lnK, int64_t ldK, void *stream);

@@ -37,6 +37,8 @@ struct ak_mechanism {
     // index), uploaded at the first call that needs them
     mutable unsigned char *kc_dev = nullptr;
     mutable bool kc_wide = false;   // a reaction has more than 4 distinct species
+    mutable int kc_pieces = 0;      // intervals of the composed ln K_c layers (0: not built)
+    mutable size_t kc_fold_off = 0; // their records' offset in kc_dev
 };
 
 namespace ak {

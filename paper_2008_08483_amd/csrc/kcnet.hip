@@ -110,6 +110,49 @@ __global__ __launch_bounds__(64) void lnkc_kernel(MechView m, const KcRxn *__res
     if (live && bad && blockIdx.y == 0) atomicAdd(m.err, 1ull);
 }
 
+// The same ln K_c with the two linear layers composed per reaction: over a
+// temperature interval on which every species of reaction j keeps its NASA
+// range, ln K_c,j = F(T) . w_j with F = (ln T, T, T^2, T^3, T^4, 1/T, 1) and
+// w_j = -ln 2 sum_k nu_kj c_k (c_k the species' Gibbs-layer weights of that
+// range).  A reaction has one interval per distinct T_mid of its species
+// plus one (PM at most): its record holds the PM - 1 interval bounds, then
+// PM weight vectors.  Lane = cell, no LDS; every weight is a scalar operand.
+template <typename IO, int PM>
+__global__ __launch_bounds__(256) void lnkc_fold_kernel(const double *__restrict__ fw, int nr,
+                                                        int rpc, const IO *__restrict__ T,
+                                                        int64_t n, IO *__restrict__ lnK,
+                                                        int64_t ldK,
+                                                        unsigned long long *err)
+{
+    constexpr int FS = (PM - 1) + 7 * PM;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double t = (double)T[i];
+    const bool bad = !(t > 0.0) || !__builtin_isfinite(t);
+    const double Tc = bad ? 1000.0 : t;
+    const double F[7] = {log(Tc), Tc, Tc * Tc, Tc * Tc * Tc, (Tc * Tc) * (Tc * Tc), 1.0 / Tc, 1.0};
+    const IO nan = (IO)__builtin_nan("");
+    const int j0 = blockIdx.y * rpc, j1 = min(nr, j0 + rpc);
+#pragma unroll 2
+    for (int j = j0; j < j1; ++j) {
+        const double *w = fw + (int64_t)j * FS;
+        const double *v = w + (PM - 1);
+        double acc = v[0] * F[0];
+#pragma unroll
+        for (int f = 1; f < 7; ++f) acc = __builtin_fma(v[f], F[f], acc);
+#pragma unroll
+        for (int q = 1; q < PM; ++q) {
+            const double *u = v + 7 * q;
+            double a2 = u[0] * F[0];
+#pragma unroll
+            for (int f = 1; f < 7; ++f) a2 = __builtin_fma(u[f], F[f], a2);
+            acc = Tc >= w[q - 1] ? a2 : acc;
+        }
+        lnK[(int64_t)j * ldK + i] = bad ? nan : (IO)acc;
+    }
+    if (bad && blockIdx.y == 0) atomicAdd(err, 1ull);
+}
+
 // f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile
 // time so that register arrays indexed by i never go to scratch memory
 template <int I, int N, typename F>
@@ -246,6 +289,7 @@ __global__ __launch_bounds__(64) void source_lnkc_kernel(MechView m,
 // host side
 
 std::mutex g_kc_mu;   // guards the lazy tables of every mechanism
+constexpr int kMaxPieces = 4;   // temperature intervals per reaction of the composed layers
 
 size_t source_lnkc_lds(int ns) { return (size_t)ns * 64 * 2 * sizeof(double); }
 size_t lnkc_lds(int ns) { return (size_t)ns * 64 * sizeof(double); }
@@ -280,19 +324,57 @@ int kc_tables(const ak_mechanism *m, const KcRxn **kr, const int32_t **order)
         int maxcnt = 0;
         for (const KcRxn &r : t) maxcnt = std::max(maxcnt, (int)r.cnt);
         m->kc_wide = maxcnt > 4;
+        // the composed layers: per reaction the distinct T_mid of its
+        // species bound the intervals; the largest count sets the layout
+        std::vector<std::vector<double>> thr(nr);
+        int pm = 1;
+        for (int j = 0; j < nr; ++j) {
+            for (int q = 0; q < t[j].cnt; ++q) thr[j].push_back(m->host_species[t[j].sp[q]].T_mid);
+            std::sort(thr[j].begin(), thr[j].end());
+            thr[j].erase(std::unique(thr[j].begin(), thr[j].end()), thr[j].end());
+            pm = std::max(pm, (int)thr[j].size() + 1);
+        }
+        std::vector<double> fold;
+        if (pm <= kMaxPieces) {
+            const int fs = (pm - 1) + 7 * pm;
+            fold.assign((size_t)fs * nr, 0.0);
+            for (int j = 0; j < nr; ++j) {
+                double *w = &fold[(size_t)j * fs];
+                const int np = (int)thr[j].size() + 1;
+                for (int q = 0; q < pm - 1; ++q)
+                    w[q] = q < np - 1 ? thr[j][q] : __builtin_inf();
+                for (int q = 0; q < pm; ++q) {
+                    double *v = w + (pm - 1) + 7 * q;
+                    const int qq = std::min(q, np - 1);   // unused intervals repeat the last
+                    for (int a = 0; a < t[j].cnt; ++a) {
+                        const SpeciesRec &sr = m->host_species[t[j].sp[a]];
+                        const bool hi = qq > 0 && sr.T_mid <= thr[j][qq - 1];
+                        for (int f = 0; f < 7; ++f)
+                            v[f] += (double)t[j].nu[a] * (hi ? sr.hi[f] : sr.lo[f]);
+                    }
+                    for (int f = 0; f < 7; ++f) v[f] *= -kLn2;
+                }
+            }
+        }
+        m->kc_pieces = fold.empty() ? 0 : pm;
         std::vector<int32_t> ord(m->rxn_order.begin(), m->rxn_order.end());
-        const size_t bytes = sizeof(KcRxn) * nr + sizeof(int32_t) * nr;
+        const size_t o_ord = sizeof(KcRxn) * nr;
+        const size_t o_fold = (o_ord + sizeof(int32_t) * nr + 255) & ~(size_t)255;
+        const size_t bytes = o_fold + sizeof(double) * fold.size();
         unsigned char *d = nullptr;
         hipError_t e = hipMalloc(&d, bytes);
         if (e == hipSuccess) e = hipMemcpy(d, t.data(), sizeof(KcRxn) * nr, hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy(d + sizeof(KcRxn) * nr, ord.data(), sizeof(int32_t) * nr,
+            e = hipMemcpy(d + o_ord, ord.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice);
+        if (e == hipSuccess && !fold.empty())
+            e = hipMemcpy(d + o_fold, fold.data(), sizeof(double) * fold.size(),
                           hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             if (d) (void)hipFree(d);
             return hip_error(e, "ln K_c tables");
         }
         m->kc_dev = d;
+        m->kc_fold_off = o_fold;
     }
     *kr = (const KcRxn *)m->kc_dev;
     *order = (const int32_t *)(m->kc_dev + sizeof(KcRxn) * m->nr);
@@ -429,8 +511,6 @@ int ak_eval_lnkc(const ak_mechanism *m, ak_precision prec, const void *T, int64_
     if (ldK < n)
         return set_error(AK_EINVAL, "%s: ldK=%lld < n_cells=%lld", fn, (long long)ldK,
                          (long long)n);
-    if (lnkc_lds(m->ns) > (size_t)m->lds_max)
-        return set_error(AK_EUNSUPPORTED, "%s: %d species exceed the LDS", fn, m->ns);
     DeviceGuard g(m->device);
     if (!g.ok) return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, m->device);
     const KcRxn *kr;
@@ -438,8 +518,32 @@ int ak_eval_lnkc(const ak_mechanism *m, ak_precision prec, const void *T, int64_
     if ((rc = kc_tables(m, &kr, &order))) return rc;
     const int64_t blocks = (n + 63) / 64;
     if (blocks > 0x7fffffff) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
-    const size_t lds = lnkc_lds(m->ns);
     hipStream_t st = (hipStream_t)stream;
+    if (m->kc_pieces > 0) {
+        // the composed layers: no LDS, no repeated work per chunk
+        const int64_t b256 = (n + 255) / 256;
+        const int ch = chunks_for((n + 63) / 64, m->nr, kTargetWaves, 8, m->nr);
+        const int rpc = (m->nr + ch - 1) / ch;
+        const dim3 grid((unsigned)b256, (unsigned)((m->nr + rpc - 1) / rpc));
+        const double *fw = (const double *)(m->kc_dev + m->kc_fold_off);
+#define AK_FOLD(IO, PM)                                                                      \
+    hipLaunchKernelGGL((lnkc_fold_kernel<IO, PM>), grid, dim3(256), 0, st, fw, m->nr, rpc,     \
+                       (const IO *)T, n, (IO *)lnK, ldK, m->view.err)
+        const bool f64 = prec == AK_FP64;
+        switch (m->kc_pieces) {
+            case 1: if (f64) AK_FOLD(double, 1); else AK_FOLD(float, 1); break;
+            case 2: if (f64) AK_FOLD(double, 2); else AK_FOLD(float, 2); break;
+            case 3: if (f64) AK_FOLD(double, 3); else AK_FOLD(float, 3); break;
+            default: if (f64) AK_FOLD(double, 4); else AK_FOLD(float, 4); break;
+        }
+#undef AK_FOLD
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_error(e, "ak_eval_lnkc: launch");
+        return AK_OK;
+    }
+    if (lnkc_lds(m->ns) > (size_t)m->lds_max)
+        return set_error(AK_EUNSUPPORTED, "%s: %d species exceed the LDS", fn, m->ns);
+    const size_t lds = lnkc_lds(m->ns);
     // each chunk repeats the Gibbs layer (14 ns FMAs per cell): at most as
     // many chunks as make that the stoichiometric layer's work (~4 per row)
     const int ch = chunks_for(blocks, m->nr, kTargetWaves, 16,

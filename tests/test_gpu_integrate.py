@@ -195,3 +195,20 @@ def test_implicit_conservation_bad_cells_and_refusals(torch, ak):
     assert e.value.code == -1
     m.close()
     pd.close()
+
+
+def test_implicit_more_than_64_unknowns(torch, ak):
+    # 70 species: 71 unknowns, past the register form; the system is solved
+    # column-major in LDS (and the Jacobian comes from the table kernel)
+    src = synth.make_mechanism(70, 180, **MILD)
+    m = ak.Mechanism(src)
+    T, P, Y = synth.make_states(src, 40, 26, (1000.0, 2500.0), (1.0, 20.0), 0.5)
+    Tt, Pt, Yt = _dev(torch, torch.float64, T, P, Y)
+    ak.integrate_implicit(m, Tt, Pt, Yt, 1e-12, 2)
+    torch.cuda.synchronize()
+    T1, Y1 = oracle.integrate_implicit(src, T, P, Y, 1e-12, 2, precision="ld")
+    assert np.abs(T1 - T).max() > 1.0
+    np.testing.assert_allclose(Tt.cpu().numpy(), T1, rtol=1e-12, atol=0)
+    assert np.abs(Yt.cpu().numpy() - Y1).max() <= 1e-11 * Y.sum(axis=0).max()
+    assert m.error_count() == 0
+    m.close()

@@ -211,3 +211,30 @@ def test_source_net_refusals(torch, ak):
     with pytest.raises(ak.AnnkinError) as e:
         ak.eval_source_lnkc(mp_, Tg, Pg, Yg, ak.eval_lnkc(mp_, Tg))
     assert e.value.code == -7
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("pattern", ["two", "distinct"])
+def test_lnkc_exact_mixed_tmid(torch, ak, prec, pattern):
+    # per-species T_mid: two values (up to 3 intervals per reaction, the
+    # composed layers) or all distinct (up to 5 intervals: the layers run
+    # separately); temperatures include every T_mid exactly
+    src = synth.make_mechanism(20, 60)
+    rng = np.random.default_rng(11)
+    if pattern == "two":
+        src.T_mid = np.where(rng.random(20) < 0.5, 1000.0, 1300.0)
+    else:
+        src.T_mid = rng.uniform(700.0, 1500.0, 20).round(3)
+    m = ak.Mechanism(src)
+    n = 700
+    T = rng.uniform(300.0, 3000.0, n)
+    T[:20] = src.T_mid
+    T[20:40] = np.nextafter(src.T_mid, 0.0)
+    dt = _dt(torch, prec)
+    Tg = torch.tensor(T, dtype=dt, device="cuda")
+    Tx = Tg.double().cpu().numpy()
+    got = ak.eval_lnkc(m, Tg).cpu().numpy().astype(np.float64)
+    ref = oracle.lnkc(src, Tx, precision="ld").astype(np.float64)
+    tol = 1e-11 * (1.0 + np.abs(ref)) + (U[prec] * 2 * np.abs(ref) if prec == "f32" else 0)
+    assert np.all(np.abs(got - ref) <= tol)
+    m.close()
