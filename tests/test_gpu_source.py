@@ -353,3 +353,39 @@ def test_abi_argument_errors(torch, ak):
     assert L.ak_eval_source(None, 0, p(x), p(x), p(Y), 16, 16, p(o), 16, None) == -1
     assert b"ak_eval_source" in L.ak_last_error()
     assert L.ak_eval_source(m.handle, 0, None, None, None, 0, 0, None, 0, None) == 0
+
+
+def _real_a6(src, seed):
+    # NASA-7 a6 of real-mechanism magnitude: element-additive (-0.6e4 to -1e4 K
+    # per atom, as formation enthalpies of molecules of 2-4 atoms run to a
+    # few 1e4 K) plus +-3000 K per species, so that |G_k| reaches ~150-200 at
+    # 300 K while each reaction's enthalpy change stays moderate; products of
+    # four species factors then span ~2^+-900, near the edge of the double
+    # range
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-1.0e4, -0.6e4, src.atoms.shape[1])
+    a6 = src.atoms.astype(float) @ mu + rng.uniform(-3000.0, 3000.0, src.n_species)
+    src.nasa_low = src.nasa_low.copy()
+    src.nasa_high = src.nasa_high.copy()
+    src.nasa_low[:, 5] = a6
+    src.nasa_high[:, 5] = a6 + rng.uniform(-50.0, 50.0, src.n_species)
+    return src
+
+
+@pytest.mark.parametrize("ns,nr", [(9, 21), (53, 325)])
+@pytest.mark.parametrize("kernels", ["auto", "table"])
+def test_real_magnitude_a6_at_low_temperature(torch, ak, ns, nr, kernels):
+    src = _real_a6(synth.make_mechanism(ns, nr), 40 + ns)
+    m = ak.Mechanism(src, kernels=kernels)
+    rng = np.random.default_rng(41)
+    n = 1000
+    T = rng.uniform(300.0, 800.0, n)
+    P = synth.ATM * rng.uniform(1.0, 20.0, n)
+    Y = rng.dirichlet(np.full(ns, 0.3), n).T.copy()
+    om = _run(torch, ak, m, T, P, Y, torch.float64)
+    _check64(src, T, P, Y, om)
+    T32, P32, Y32 = (a.astype(np.float32) for a in (T, P, Y))
+    om32 = _run(torch, ak, m, T32, P32, Y32, torch.float32)
+    _check32(src, T32, P32, Y32, om32)
+    assert m.error_count() == 0
+    m.close()
