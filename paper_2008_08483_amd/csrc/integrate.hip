@@ -222,6 +222,19 @@ __global__ __launch_bounds__(64) void implicit_update_kernel(MechView m, IO *__r
 
 namespace {
 
+template <typename T>
+struct Tag {
+    using type = T;
+};
+
+__device__ __forceinline__ double readlane_d_impl(double v, int lane)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 template <int I, int N, typename F>
 __device__ __forceinline__ void unrolled(F &&f)
 {
@@ -231,13 +244,38 @@ __device__ __forceinline__ void unrolled(F &&f)
     }
 }
 
-__device__ __forceinline__ double readlane_d(double v, int lane)
+// x moved across lanes by one DPP pattern (both halves); lanes with no
+// source lane take 0
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x)
 {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
-    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
-    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+    int w[2];
+    __builtin_memcpy(w, &x, 8);
+    w[0] = __builtin_amdgcn_update_dpp(0, w[0], CTRL, 0xf, 0xf, false);
+    w[1] = __builtin_amdgcn_update_dpp(0, w[1], CTRL, 0xf, 0xf, false);
+    double r;
+    __builtin_memcpy(&r, w, 8);
+    return r;
 }
+
+// Maximum over the 64 lanes of values >= -1 (a lane without a candidate
+// holds -1), the same in every lane: a max-scan within rows of 16 lanes
+// (row_shr 1, 2, 4, 8), then across rows (row_bcast 15, 31), read from lane
+// 63.  The shifted-in zeros only matter when every candidate is negative,
+// i.e. when there is none, and the caller treats a maximum of 0 as singular
+// either way.  DPP stays in the vector registers (no LDS crossbar).
+__device__ __forceinline__ double wave_max_pivot(double x)
+{
+    x = fmax(x, dpp_move<0x111>(x));
+    x = fmax(x, dpp_move<0x112>(x));
+    x = fmax(x, dpp_move<0x114>(x));
+    x = fmax(x, dpp_move<0x118>(x));
+    x = fmax(x, dpp_move<0x142>(x));
+    x = fmax(x, dpp_move<0x143>(x));
+    return readlane_d_impl(x, 63);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) { return readlane_d_impl(v, lane); }
 
 }  // namespace
 
@@ -246,13 +284,14 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
 // identity (padding rows never become pivots before the real ones are
 // used up, and leave the solution unchanged).  Every column index is a
 // compile-time constant.  Step k: the wave maximum of |A[r][k]| over rows
-// not yet used as pivots, the lowest such lane becomes the pivot (ballot);
+// not yet used as pivots (a DPP max-scan), the lowest such lane becomes the
+// pivot (ballot);
 // its row is read into scalar registers (readlane) and every other unused
 // row subtracts its multiple of it.  No row moves: the pivot order is kept
 // in the per-lane step index, and back substitution runs over the steps in
 // reverse.  No LDS, no barriers.
-template <typename IO>
-__global__ __launch_bounds__(64) void implicit_update_reg_kernel(MechView m, IO *__restrict__ T,
+template <typename IO, int N>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void implicit_update_reg_kernel(MechView m, IO *__restrict__ T,
                                                                  const IO *__restrict__ P,
                                                                  IO *__restrict__ Y, int64_t ldY,
                                                                  const IO *__restrict__ om,
@@ -260,7 +299,6 @@ __global__ __launch_bounds__(64) void implicit_update_reg_kernel(MechView m, IO 
                                                                  const IO *__restrict__ J,
                                                                  int64_t ldJ, double dt)
 {
-    constexpr int N = 64;
     const int64_t i = blockIdx.x;
     const int r = threadIdx.x;
     const int ns = m.ns, nv = ns + 1;
@@ -306,8 +344,7 @@ __global__ __launch_bounds__(64) void implicit_update_reg_kernel(MechView m, IO 
     int pivot_of[N];
     unrolled<0, N>([&](auto k) {
         const double v = step == N ? fabs(a[k]) : -1.0;
-        double mx = v;
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+        const double mx = wave_max_pivot(v);
         const unsigned long long hit = __ballot(v == mx);
         const int p = __builtin_ctzll(hit);
         pivot_of[k] = p;
@@ -347,14 +384,23 @@ hipError_t implicit_update_launch(const MechView &m, bool f64, void *T, const vo
     if (n <= 0) return hipSuccess;
     if (n > 0x7fffffff) return hipErrorInvalidValue;
     if (m.ns + 1 <= 64) {
-        if (f64)
-            hipLaunchKernelGGL(implicit_update_reg_kernel<double>, dim3((unsigned)n), dim3(64), 0,
-                               st, m, (double *)T, (const double *)P, (double *)Y, ldY,
-                               (const double *)om, ldO, (const double *)J, ldJ, dt);
-        else
-            hipLaunchKernelGGL(implicit_update_reg_kernel<float>, dim3((unsigned)n), dim3(64), 0,
-                               st, m, (float *)T, (const float *)P, (float *)Y, ldY,
-                               (const float *)om, ldO, (const float *)J, ldJ, dt);
+        // systems padded to 16, 32 or 64 unknowns
+        auto go = [&](auto kern, auto tag) {
+            using E = typename decltype(tag)::type;
+            hipLaunchKernelGGL(kern, dim3((unsigned)n), dim3(64), 0, st, m, (E *)T,
+                               (const E *)P, (E *)Y, ldY, (const E *)om, ldO, (const E *)J, ldJ,
+                               dt);
+        };
+        const int nv = m.ns + 1;
+        if (f64) {
+            if (nv <= 16) go(implicit_update_reg_kernel<double, 16>, Tag<double>{});
+            else if (nv <= 32) go(implicit_update_reg_kernel<double, 32>, Tag<double>{});
+            else go(implicit_update_reg_kernel<double, 64>, Tag<double>{});
+        } else {
+            if (nv <= 16) go(implicit_update_reg_kernel<float, 16>, Tag<float>{});
+            else if (nv <= 32) go(implicit_update_reg_kernel<float, 32>, Tag<float>{});
+            else go(implicit_update_reg_kernel<float, 64>, Tag<float>{});
+        }
         return hipGetLastError();
     }
     const size_t lds = implicit_lds_bytes(m.ns);
