@@ -140,3 +140,31 @@ def test_compiled_jacobian_generation_without_gpu():
     with pytest.raises(annkin.AnnkinError) as e:
         annkin.jit_jacobian_source(pd, "fp64")
     assert e.value.code == -7
+
+
+def test_kcnet_descriptor_refusals_without_gpu():
+    # ak_load_kcnet checks the descriptor before it touches a device
+    import ctypes as C
+
+    from paper_2008_08483_amd import annkin, kcnet
+    h = annkin.lib()
+    net = kcnet.random_weights(2, 8, 5, seed=1)
+    w = np.concatenate([a.reshape(-1) for a in net.weights])
+    b = np.concatenate(net.biases)
+    ym, ys = np.ascontiguousarray(net.y_mean), np.ascontiguousarray(net.y_std)
+
+    def load(nl=2, nh=8, nr=5, ww=w, xstd=net.x_std):
+        d = annkin.KcNetDesc(nl, nh, nr, 0, ww.ctypes.data, b.ctypes.data, net.x_mean, xstd,
+                             ym.ctypes.data, ys.ctypes.data)
+        out = C.c_void_p()
+        return h.ak_load_kcnet(C.byref(d), 0, C.byref(out))
+
+    assert load(nh=65) == -1
+    assert load(nl=0) == -1
+    assert load(nl=17) == -1
+    assert load(nr=0) == -1
+    assert load(xstd=0.0) == -1
+    bad = w.copy()
+    bad[3] = np.nan
+    assert load(ww=bad) == -1
+    assert "non-finite weight" in h.ak_last_error().decode()

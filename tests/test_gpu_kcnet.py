@@ -238,3 +238,25 @@ def test_lnkc_exact_mixed_tmid(torch, ak, prec, pattern):
     tol = 1e-11 * (1.0 + np.abs(ref)) + (U[prec] * 2 * np.abs(ref) if prec == "f32" else 0)
     assert np.all(np.abs(got - ref) <= tol)
     m.close()
+
+
+def test_empty_batches_and_argument_errors(torch, ak):
+    src, m = _mech(ak, 9, 21)
+    net = ak.KcNet(kcnet.random_weights(1, 8, 21, seed=5))
+    e64 = torch.empty(0, dtype=torch.float64, device="cuda")
+    assert ak.eval_lnkc(m, e64).shape == (21, 0)
+    assert ak.eval_lnkc_net(net, e64).shape == (21, 0)
+    Y0 = torch.empty((9, 0), dtype=torch.float64, device="cuda")
+    assert ak.eval_source_net(m, net, e64, e64, Y0).shape == (9, 0)
+    T = torch.full((5,), 1200.0, dtype=torch.float64, device="cuda")
+    lib = ak.lib()
+    out = torch.empty((21, 5), dtype=torch.float64, device="cuda")
+    # ldK below n, null pointers, bad precision: refused before any launch
+    assert lib.ak_eval_lnkc(m.handle, 0, T.data_ptr(), 5, out.data_ptr(), 4, None) == -1
+    assert lib.ak_eval_lnkc(m.handle, 0, None, 5, out.data_ptr(), 5, None) == -1
+    assert lib.ak_eval_lnkc(m.handle, 7, T.data_ptr(), 5, out.data_ptr(), 5, None) == -1
+    assert lib.ak_eval_lnkc_net(net.handle, 0, T.data_ptr(), 5, out.data_ptr(), 4, None) == -1
+    assert lib.ak_eval_lnkc_net(None, 0, T.data_ptr(), 5, out.data_ptr(), 5, None) == -1
+    assert lib.ak_eval_source_lnkc(m.handle, 0, T.data_ptr(), T.data_ptr(), None, 5, 5,
+                                   out.data_ptr(), 5, out.data_ptr(), 5, None) == -1
+    assert (out.isnan() | out.isfinite()).all()
