@@ -465,6 +465,7 @@ def kc_bench(torch, annkin, steps=20, train=True):
     Tv = torch.tensor(rng.uniform(300.0, 3000.0, 200_000), dtype=torch.float64, device="cuda")
     Kv = annkin.eval_lnkc(mech, Tv)
     t_src = timed(lambda: annkin.eval_source(mech, Tt, Pt, Yt))
+    nets = {}
     for tag, (l, h) in (("LF_1x8", (1, 8)), ("HF_3x32", (3, 32))):
         t0 = time.perf_counter()
         w = kcnet.train(Ttr, Ktr, l, h, epochs=20, batch=4096, lr=1e-2 if h <= 8 else 3e-3,
@@ -483,11 +484,35 @@ def kc_bench(torch, annkin, steps=20, train=True):
                     "omega_rel_err_p99": float(torch.quantile(sel, 0.99)),
                     "source_net_ms": t_net, "source_given_lnK_ms": t_lnk,
                     "exact_compiled_source_ms": t_src}
-        net.close()
+        nets[tag] = net
     out["accuracy_definition"] = ("FP64; omega with the network's ln K_c against the exact "
                                   "compiled source term on the 65,536 c4 states, |d|/|w| over "
                                   "entries with |w| >= 1e-6 max|w|; ln K_c errors on 2e5 "
                                   "temperatures in the training range")
+    # a-posteriori (Sec. 3.1): 0-D reactors advanced with the exact ln K_c
+    # and with each network; the mild variant of the same mechanism (same
+    # species, thermodynamics and stoichiometry, so the networks apply)
+    # allows explicit steps of 5e-16 s
+    msrc = synth.make_mechanism(53, 325, ln_A_range=(8.0, 16.0), Ea_range=(20000.0, 60000.0))
+    mild = annkin.Mechanism(msrc)
+    m0 = 4096
+    T0, P0, Y0 = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in
+                  synth.make_states(msrc, m0, 4242, (1000.0, 2500.0), (1.0, 20.0), 0.5))
+    Te, Ye = T0.clone(), Y0.clone()
+    annkin.integrate_euler(mild, Te, P0, Ye, 5e-16, 200)
+    post = {"cells": m0, "dt_s": 5e-16, "steps": 200,
+            "states": "T ~ U[1000, 2500] K, P ~ U[1, 20] atm, Y ~ Dirichlet(0.5)",
+            "exact_max_abs_dT_K": float((Te - T0).abs().max()),
+            "exact_nonfinite_cells": int((~torch.isfinite(Te)).sum())}
+    for tag, net in nets.items():
+        Ta, Ya = T0.clone(), Y0.clone()
+        annkin.integrate_euler_net(mild, net, Ta, P0, Ya, 5e-16, 200)
+        post[tag] = {"max_abs_dT_vs_exact_K": float((Ta - Te).abs().max()),
+                     "median_abs_dT_vs_exact_K": float((Ta - Te).abs().median()),
+                     "max_abs_dY_vs_exact": float((Ya - Ye).abs().max())}
+        net.close()
+    out["a_posteriori_0d"] = post
+    mild.close()
     mech.close()
     return out
 

@@ -467,6 +467,17 @@ int ak_eval_source_net(const ak_mechanism *mech, const ak_kcnet *net, ak_precisi
                        const void *T, const void *P, const void *Y, int64_t ldY,
                        int64_t n_cells, void *omega, int64_t ldO, void *stream);
 
+/*
+ * The 0-D reactor of ak_integrate_euler with the network's ln K_c in place
+ * of Eq. 8 at every step (the a-posteriori use of Sec. 3.1): per step
+ * ak_eval_lnkc_net, ak_eval_source_lnkc, then the same state update.
+ * Scratch of (N_R + NS) x n_cells elements, stream-ordered.  Errors: as
+ * ak_eval_source_net and ak_integrate_euler.
+ */
+int ak_integrate_euler_net(const ak_mechanism *mech, const ak_kcnet *net, ak_precision prec,
+                           void *T, const void *P, void *Y, int64_t ldY, int64_t n_cells,
+                           double dt, int n_steps, void *stream);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of many callers' source-term requests.
  *

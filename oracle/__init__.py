@@ -235,6 +235,34 @@ def integrate_implicit(mech, T, P, Y, dt: float, n_steps: int, precision: str = 
     return T, Y
 
 
+def integrate_euler_lnkc(mech, lnk_of, T, P, Y, dt: float, n_steps: int):
+    """The forward-Euler 0-D reactor of ``integrate_euler`` with ln K_c from
+    ``lnk_of(T) -> [NR, n]`` in place of Eq. 8 at every step (a trained
+    ln K_c as a drop-in, Sec. 3.1's a-posteriori use), in float64, composed
+    from ``source_lnkc`` and ``thermo``:
+        Y_k += dt W_k omega_k / rho,  T += dt omega_T,
+        omega_T = -sum_k H_k omega_k / sum_k C_k cp_k,  rho = sum_k C_k W_k.
+    Returns new (T [n], Y [NS, n])."""
+    m = _as_mech(mech)
+    W = np.asarray(mech.W, np.float64)
+    T = np.array(T, dtype=np.float64, copy=True)
+    P = _f64(P)
+    Y = np.array(Y, dtype=np.float64, copy=True)
+    n = T.shape[0]
+    ru = 8314.46261815324
+    for _ in range(n_steps):
+        om = source_lnkc(mech, T, P, Y, lnk_of(T))
+        for i in range(n):
+            h, _, cp = thermo(m, T[i])
+            yc = np.maximum(Y[:, i], 0.0)
+            C = P[i] / (ru * T[i]) * (yc / W) / (yc / W).sum()
+            rho = float((C * W).sum())
+            omT = -float((ru * T[i] * h * om[:, i]).sum()) / float((C * ru * cp).sum())
+            Y[:, i] += dt * W * om[:, i] / rho
+            T[i] += dt * omT
+    return T, Y
+
+
 def lnkc(mech, T, precision: str = "f64"):
     """ln K_c (Eq. 8) [NR, n] of every reaction (file order) at temperatures T [n]."""
     m = _as_mech(mech)

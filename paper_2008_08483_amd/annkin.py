@@ -137,6 +137,9 @@ def lib():
         h.ak_eval_source_net.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                          C.c_void_p, C.c_int64, C.c_void_p]
+        h.ak_integrate_euler_net.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                             C.c_double, C.c_int, C.c_void_p]
         _lib = h
     return _lib
 
@@ -577,6 +580,17 @@ def integrate_implicit(mech: Mechanism, T, P, Y, dt: float, n_steps: int, stream
     _check(lib().ak_integrate_implicit(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
                                        Y.data_ptr(), Y.stride(0), n, float(dt), int(n_steps),
                                        _stream_ptr(stream)))
+    return T, Y
+
+
+def integrate_euler_net(mech: Mechanism, net: KcNet, T, P, Y, dt: float, n_steps: int,
+                        stream=None):
+    """integrate_euler with the network's ln K_c in place of Eq. 8 at every
+    step (Sec. 3.1's a-posteriori test).  In place, asynchronous."""
+    n = _check_state(mech, T, P, Y)
+    _check(lib().ak_integrate_euler_net(mech.handle, net.handle, _prec(T.dtype), T.data_ptr(),
+                                        P.data_ptr(), Y.data_ptr(), Y.stride(0), n, float(dt),
+                                        int(n_steps), _stream_ptr(stream)))
     return T, Y
 
 

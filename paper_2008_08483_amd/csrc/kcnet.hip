@@ -737,4 +737,50 @@ int ak_eval_source_net(const ak_mechanism *m, const ak_kcnet *net, ak_precision 
     return AK_OK;
 }
 
+int ak_integrate_euler_net(const ak_mechanism *m, const ak_kcnet *net, ak_precision prec,
+                           void *T, const void *P, void *Y, int64_t ldY, int64_t n, double dt,
+                           int n_steps, void *stream)
+{
+    const char *fn = "ak_integrate_euler_net";
+    int rc = check_source(fn, m, prec, T, P, Y, ldY, n, Y, ldY);
+    if (rc) return rc;
+    if (!net) return set_error(AK_EINVAL, "%s: null network", fn);
+    if (net->nr != m->nr)
+        return set_error(AK_EINVAL, "%s: network has %d outputs, mechanism %d reactions", fn,
+                         net->nr, m->nr);
+    if (net->device != m->device)
+        return set_error(AK_EINVAL, "%s: network on device %d, mechanism on %d", fn,
+                         net->device, m->device);
+    if (!(dt > 0.0) || !std::isfinite(dt))
+        return set_error(AK_EINVAL, "%s: dt must be positive and finite", fn);
+    if (n_steps < 0) return set_error(AK_EINVAL, "%s: n_steps < 0", fn);
+    if (n == 0 || n_steps == 0) return AK_OK;
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, m->device);
+    const KcRxn *kr;
+    const int32_t *order;
+    if ((rc = kc_tables(m, &kr, &order))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t es = prec == AK_FP64 ? 8 : 4;
+    const size_t kbytes = ((size_t)m->nr * (size_t)n * es + 255) & ~(size_t)255;
+    const size_t obytes = (size_t)m->ns * (size_t)n * es;
+    void *scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, kbytes + obytes, st);
+    if (e != hipSuccess)
+        return set_error(AK_ENOMEM, "%s: scratch of %zu bytes: %s", fn, kbytes + obytes,
+                         hipGetErrorString(e));
+    void *lnK = scratch, *om = (unsigned char *)scratch + kbytes;
+    for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
+        e = kcnet_launch(net, prec, T, n, lnK, n, st);
+        if (e == hipSuccess)
+            e = source_lnkc_launch(m, order, prec, T, P, Y, ldY, n, lnK, n, om, n, st);
+        if (e == hipSuccess)
+            e = euler_update_launch(m->view, prec == AK_FP64, T, P, Y, ldY, n, om, n, dt, st);
+    }
+    const hipError_t ef = hipFreeAsync(scratch, st);
+    if (e != hipSuccess) return hip_error(e, "ak_integrate_euler_net: step");
+    if (ef != hipSuccess) return hip_error(ef, "ak_integrate_euler_net: freeing the scratch");
+    return AK_OK;
+}
+
 }  // extern "C"

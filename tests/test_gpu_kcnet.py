@@ -260,3 +260,32 @@ def test_empty_batches_and_argument_errors(torch, ak):
     assert lib.ak_eval_source_lnkc(m.handle, 0, T.data_ptr(), T.data_ptr(), None, 5, 5,
                                    out.data_ptr(), 5, out.data_ptr(), 5, None) == -1
     assert (out.isnan() | out.isfinite()).all()
+
+
+@pytest.mark.parametrize("ns,nr,dt", [(9, 21, 1e-14), (53, 325, 5e-16)])
+def test_integrate_euler_with_network(torch, ak, ns, nr, dt):
+    # the 0-D reactor driven by a trained network's ln K_c (Sec. 3.1's
+    # a-posteriori use) against the oracle's composition with the same
+    # network; FP64, 30 steps
+    mild = dict(ln_A_range=(8.0, 16.0), Ea_range=(20000.0, 60000.0))
+    src = synth.make_mechanism(ns, nr, **mild)
+    m = ak.Mechanism(src)
+    Ttr = np.random.default_rng(13).uniform(900.0, 2700.0, 8000)
+    w = kcnet.train(Ttr, oracle.lnkc(src, Ttr), 1, 16, epochs=15, batch=512, lr=1e-2, seed=3)
+    net = ak.KcNet(w)
+    T, P, Y = synth.make_states(src, 70, 31, (1000.0, 2500.0), (1.0, 20.0), 0.5)
+    Tt, Pt, Yt = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (T, P, Y))
+    ak.integrate_euler_net(m, net, Tt, Pt, Yt, dt, 30)
+    torch.cuda.synchronize()
+    T1, Y1 = oracle.integrate_euler_lnkc(src, lambda t: oracle.kcnet(w, t), T, P, Y, dt, 30)
+    assert np.abs(T1 - T).max() > 0.1
+    np.testing.assert_allclose(Tt.cpu().numpy(), T1, rtol=1e-11, atol=0)
+    assert np.abs(Yt.cpu().numpy() - Y1).max() <= 1e-11 * Y.sum(axis=0).max()
+    # and the exact integrator, for scale: the network's error in ln K_c moves
+    # the trajectory by far more than rounding
+    Te, Ye = (torch.tensor(a, dtype=torch.float64, device="cuda") for a in (T, Y))
+    ak.integrate_euler(m, Te, Pt, Ye, dt, 30)
+    torch.cuda.synchronize()
+    print("ann vs exact after 30 steps: max |dT| %.3e K, max |dY| %.3e" % (
+        np.abs(Te.cpu().numpy() - T1).max(), np.abs(Ye.cpu().numpy() - Y1).max()))
+    m.close()

@@ -172,3 +172,15 @@ def test_kcnet_identity_hidden_layers():
     three = oracle.kcnet(_Net([w0, np.eye(8), np.eye(8), wo], [b0, np.zeros(8), np.zeros(8), bo],
                               7.0, 0.6, ym, ys), T)
     np.testing.assert_allclose(three, one, rtol=1e-14, atol=1e-13)
+
+
+def test_euler_with_given_lnkc_is_euler_when_exact():
+    # the composition with the exact ln K_c reproduces the (pinned) Euler
+    # integrator of the oracle, step for step
+    mech = synth.make_mechanism(9, 21, ln_A_range=(8.0, 16.0), Ea_range=(20000.0, 60000.0))
+    T, P, Y = synth.make_states(mech, 6, 12, (1000.0, 2500.0), 1.0, 0.5)
+    a = oracle.integrate_euler_lnkc(mech, lambda t: oracle.lnkc(mech, t), T, P, Y, 1e-14, 20)
+    b = oracle.integrate_euler(mech, T, P, Y, 1e-14, 20)
+    assert np.abs(a[0] - T).max() > 1e-3
+    np.testing.assert_allclose(a[0], b[0], rtol=1e-13)
+    assert np.abs(a[1] - b[1]).max() <= 1e-13
