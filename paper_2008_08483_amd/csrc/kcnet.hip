@@ -25,6 +25,7 @@
 #include "annkin.h"
 #include "ak_device.h"
 #include "ak_internal.h"
+#include "ak_math.h"
 
 struct ak_kcnet {
     int device = 0;
@@ -218,71 +219,98 @@ __global__ __launch_bounds__(256) void kcnet_kernel(const E *__restrict__ w, int
     }
 }
 
-// The source term with a given ln K_c, one 64-cell tile per workgroup (one
-// wave), lane = cell.  LDS holds the lane's log2 C_k and its omega_k
-// accumulators (its own columns: no atomics, a fixed order of additions).
-// Reactions run in the library's sorted order; ln K_c is read at the
-// descriptor index of each.
-template <typename IO>
-__global__ __launch_bounds__(64) void source_lnkc_kernel(MechView m,
-                                                         const int32_t *__restrict__ order,
-                                                         const IO *__restrict__ T,
-                                                         const IO *__restrict__ P,
-                                                         const IO *__restrict__ Y, int64_t ldY,
-                                                         int64_t n, const IO *__restrict__ lnK,
-                                                         int64_t ldK, IO *__restrict__ om,
-                                                         int64_t ldO)
+// The source term with a given ln K_c, one 64-cell tile per workgroup of SW
+// waves, lane = cell.  LDS holds the tile's log2 C_k (written by the waves
+// in turn, species k = wave + SW i) and, per wave, omega_k accumulators for
+// the contiguous share of the reactions the wave sweeps (its own region: no
+// atomics).  The shares are added in wave order at the end, so every omega_k
+// is a sum in a fixed order.  Reactions run in the library's sorted order;
+// ln K_c is read at the descriptor index of each.
+template <typename IO, int SW>
+__global__ __launch_bounds__(64 * SW) void source_lnkc_kernel(MechView m,
+                                                              const int32_t *__restrict__ order,
+                                                              const IO *__restrict__ T,
+                                                              const IO *__restrict__ P,
+                                                              const IO *__restrict__ Y,
+                                                              int64_t ldY, int64_t n,
+                                                              const IO *__restrict__ lnK,
+                                                              int64_t ldK, IO *__restrict__ om,
+                                                              int64_t ldO)
 {
     extern __shared__ double lds[];
-    const int lane = threadIdx.x;
-    double *l2C = lds, *acc = lds + (size_t)m.ns * 64;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ns = m.ns;
+    double *l2C = lds;
+    double *acc = lds + (size_t)ns * 64 * (1 + wave);
+    double *part = lds + (size_t)ns * 64 * (1 + SW);   // [SW][64]
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     const bool live = i < n;
     const int64_t c = live ? i : n - 1;
     const double Tc = (double)T[c], Pc = (double)P[c];
-    bool bad = !(Tc > 0.0) || !(Pc > 0.0) || !__builtin_isfinite(Tc) || !__builtin_isfinite(Pc);
-    double sigma = 0.0;
-    for (int k = 0; k < m.ns; ++k) {
+    const bool tp_bad = !(Tc > 0.0) || !(Pc > 0.0) || !__builtin_isfinite(Tc) ||
+                        !__builtin_isfinite(Pc);
+    // mixture sum: a partial per wave, then the waves' partials in order (a
+    // non-finite mass fraction makes it NaN)
+    double ps = 0.0;
+    for (int k = wave; k < ns; k += SW) {
         const double y = (double)Y[(int64_t)k * ldY + c];
-        if (!__builtin_isfinite(y)) bad = true;
-        sigma += (y > 0.0 ? y : 0.0) * m.sp[k].inv_W;
+        ps += __builtin_isfinite(y) ? (y > 0.0 ? y : 0.0) * m.sp[k].inv_W : __builtin_nan("");
     }
-    if (!(sigma > 0.0) || !__builtin_isfinite(sigma)) bad = true;
+    part[wave * 64 + lane] = ps;
+    __syncthreads();
+    double sigma = 0.0;
+    for (int w = 0; w < SW; ++w) sigma += part[w * 64 + lane];
+    const bool bad = tp_bad || !(sigma > 0.0) || !__builtin_isfinite(sigma);
     const double Tu = bad ? 1000.0 : Tc;
     const double rh = bad ? 0.0 : Pc / (kRu * Tu * sigma);
-    for (int k = 0; k < m.ns; ++k) {
+    for (int k = wave; k < ns; k += SW) {
         const double y = (double)Y[(int64_t)k * ldY + c];
         const double C = rh * (y > 0.0 ? y : 0.0) * m.sp[k].inv_W;
-        l2C[k * 64 + lane] = C > 0.0 ? log2(C) : -__builtin_inf();
-        acc[k * 64 + lane] = 0.0;
+        // an absent species: a floor far below any rate's range, so that
+        // 2^t underflows to an exact 0 through the finite exponent path
+        l2C[k * 64 + lane] = C > 0.0 ? log2(C) : -4096.0;
     }
+    for (int k = 0; k < ns; ++k) acc[k * 64 + lane] = 0.0;
+    __syncthreads();
     const double log2T = log2(Tu), invT = 1.0 / Tu;
+    const int j0 = (int)((int64_t)m.nr * wave / SW), j1 = (int)((int64_t)m.nr * (wave + 1) / SW);
     // unrolled so that several reactions' ln K_c loads are in flight at once
 #pragma unroll 4
-    for (int j = 0; j < m.nr; ++j) {
+    for (int j = j0; j < j1; ++j) {
         const RxnRec *r = &m.rx[j];
         const RxnAux *x = &m.aux[j];
         const int nf = x->nf, np = x->nr;
         const double t0 = r->log2A + r->beta * log2T + r->negEoR2 * invT;
         double tf = t0;
         for (int q = 0; q < nf; ++q) tf += l2C[x->sp[q] * 64 + lane];
-        double qn = exp2(tf);
+        double qn = scale_exp2(1.0, tf);
         if (x->rev) {
             double tr = t0 - (double)lnK[(int64_t)order[j] * ldK + c] * kLog2e;
             for (int q = 0; q < np; ++q) tr += l2C[x->sp[nf + q] * 64 + lane];
-            qn -= exp2(tr);
+            qn -= scale_exp2(1.0, tr);
         }
         for (int q = 0; q < nf; ++q) acc[x->sp[q] * 64 + lane] -= qn;
         for (int q = 0; q < np; ++q) acc[x->sp[nf + q] * 64 + lane] += qn;
     }
+    __syncthreads();
+    // the waves' shares in wave order; this wave stores species k = wave + SW i
     bool nonfinite = false;
     const IO nan = (IO)__builtin_nan("");
-    for (int k = 0; k < m.ns; ++k) {
-        const double v = acc[k * 64 + lane];
+    for (int k = wave; k < ns; k += SW) {
+        double v = 0.0;
+        for (int w = 0; w < SW; ++w) v += lds[(size_t)ns * 64 * (1 + w) + k * 64 + lane];
         if (!__builtin_isfinite(v)) nonfinite = true;
         if (live) om[(int64_t)k * ldO + i] = bad ? nan : (IO)v;
     }
-    if (live && (bad || nonfinite)) atomicAdd(m.err, 1ull);
+    // one count per bad cell: the waves' flags meet in LDS
+    part[wave * 64 + lane] = nonfinite ? 1.0 : 0.0;
+    __syncthreads();
+    if (wave == 0 && live) {
+        bool any = bad;
+        for (int w = 0; w < SW; ++w) any = any || part[w * 64 + lane] != 0.0;
+        if (any) atomicAdd(m.err, 1ull);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -291,7 +319,19 @@ __global__ __launch_bounds__(64) void source_lnkc_kernel(MechView m,
 std::mutex g_kc_mu;   // guards the lazy tables of every mechanism
 constexpr int kMaxPieces = 4;   // temperature intervals per reaction of the composed layers
 
-size_t source_lnkc_lds(int ns) { return (size_t)ns * 64 * 2 * sizeof(double); }
+// LDS of the given-ln K_c source term with `sw` sweep waves per tile
+size_t source_lnkc_lds(int ns, int sw)
+{
+    return ((size_t)ns * 64 * (1 + sw) + (size_t)64 * sw) * sizeof(double);
+}
+
+// The most sweep waves (4, 2 or 1) whose LDS fits the device
+int source_lnkc_waves(int ns, int lds_max)
+{
+    for (int sw = 4; sw > 1; sw /= 2)
+        if (source_lnkc_lds(ns, sw) <= (size_t)lds_max) return sw;
+    return 1;
+}
 size_t lnkc_lds(int ns) { return (size_t)ns * 64 * sizeof(double); }
 
 // The descriptor-order reaction table and the sorted-to-descriptor index,
@@ -454,22 +494,25 @@ hipError_t source_lnkc_launch(const ak_mechanism *m, const int32_t *order, int p
 {
     const int64_t blocks = (n + 63) / 64;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    const size_t lds = source_lnkc_lds(m->ns);
-    hipError_t e;
+    const int sw = source_lnkc_waves(m->ns, m->lds_max);
+    const size_t lds = source_lnkc_lds(m->ns, sw);
+    auto go = [&](auto kern, auto tag) {
+        using IO = typename decltype(tag)::type;
+        hipError_t e = allow_dynamic_lds((const void *)kern);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * sw), lds, st, m->view, order,
+                           (const IO *)T, (const IO *)P, (const IO *)Y, ldY, n,
+                           (const IO *)lnK, ldK, (IO *)om, ldO);
+        return hipGetLastError();
+    };
     if (prec == AK_FP64) {
-        auto fn = source_lnkc_kernel<double>;
-        if ((e = allow_dynamic_lds((const void *)fn)) != hipSuccess) return e;
-        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, st, m->view, order,
-                           (const double *)T, (const double *)P, (const double *)Y, ldY, n,
-                           (const double *)lnK, ldK, (double *)om, ldO);
-    } else {
-        auto fn = source_lnkc_kernel<float>;
-        if ((e = allow_dynamic_lds((const void *)fn)) != hipSuccess) return e;
-        hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64), lds, st, m->view, order,
-                           (const float *)T, (const float *)P, (const float *)Y, ldY, n,
-                           (const float *)lnK, ldK, (float *)om, ldO);
+        if (sw == 4) return go(source_lnkc_kernel<double, 4>, Tag<double>{});
+        if (sw == 2) return go(source_lnkc_kernel<double, 2>, Tag<double>{});
+        return go(source_lnkc_kernel<double, 1>, Tag<double>{});
     }
-    return hipGetLastError();
+    if (sw == 4) return go(source_lnkc_kernel<float, 4>, Tag<float>{});
+    if (sw == 2) return go(source_lnkc_kernel<float, 2>, Tag<float>{});
+    return go(source_lnkc_kernel<float, 1>, Tag<float>{});
 }
 
 int check_source(const char *fn, const ak_mechanism *m, int prec, const void *T, const void *P,
@@ -486,7 +529,7 @@ int check_source(const char *fn, const ak_mechanism *m, int prec, const void *T,
     if (m->pdep)
         return set_error(AK_EUNSUPPORTED, "%s: third-body and falloff reactions are not "
                                           "supported with a given ln K_c", fn);
-    if (source_lnkc_lds(m->ns) > (size_t)m->lds_max)
+    if (source_lnkc_lds(m->ns, 1) > (size_t)m->lds_max)
         return set_error(AK_EUNSUPPORTED, "%s: %d species exceed the LDS", fn, m->ns);
     return AK_OK;
 }
