@@ -219,6 +219,38 @@ __global__ __launch_bounds__(256) void kcnet_kernel(const E *__restrict__ w, int
     }
 }
 
+// One run of reactions of the same shape (NF reactant and NR product
+// molecules, one reversibility) within [j, end): rates with the given ln K_c
+// into this wave's accumulators.  The shape is a compile-time constant, so
+// every loop unrolls and the next reactions' record loads can be issued
+// while the current ones compute.
+template <typename IO, int NF, int NR>
+__device__ __forceinline__ void lnk_run(const MechView &m, const int32_t *__restrict__ order,
+                                        int j, int end, double rev, const double *l2C,
+                                        double *acc, int lane, const IO *__restrict__ lnK,
+                                        int64_t ldK, int64_t c, double log2T, double invT)
+{
+#pragma unroll 2
+    for (; j < end; ++j) {
+        const RxnRec r = m.rx[j];
+        const double t0 = r.log2A + r.beta * log2T + r.negEoR2 * invT;
+        double tf = t0;
+#pragma unroll
+        for (int q = 0; q < NF; ++q) tf += l2C[r.sp[q] * 64 + lane];
+        double qn = scale_exp2(1.0, tf);
+        if (rev != 0.0) {
+            double tr = t0 - (double)lnK[(int64_t)order[j] * ldK + c] * kLog2e;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) tr += l2C[r.sp[NF + q] * 64 + lane];
+            qn -= scale_exp2(1.0, tr);
+        }
+#pragma unroll
+        for (int q = 0; q < NF; ++q) acc[r.sp[q] * 64 + lane] -= qn;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[r.sp[NF + q] * 64 + lane] += qn;
+    }
+}
+
 // The source term with a given ln K_c, one 64-cell tile per workgroup of SW
 // waves, lane = cell.  LDS holds the tile's log2 C_k (written by the waves
 // in turn, species k = wave + SW i) and, per wave, omega_k accumulators for
@@ -275,23 +307,25 @@ __global__ __launch_bounds__(64 * SW) void source_lnkc_kernel(MechView m,
     __syncthreads();
     const double log2T = log2(Tu), invT = 1.0 / Tu;
     const int j0 = (int)((int64_t)m.nr * wave / SW), j1 = (int)((int64_t)m.nr * (wave + 1) / SW);
-    // unrolled so that several reactions' ln K_c loads are in flight at once
-#pragma unroll 4
-    for (int j = j0; j < j1; ++j) {
-        const RxnRec *r = &m.rx[j];
-        const RxnAux *x = &m.aux[j];
-        const int nf = x->nf, np = x->nr;
-        const double t0 = r->log2A + r->beta * log2T + r->negEoR2 * invT;
-        double tf = t0;
-        for (int q = 0; q < nf; ++q) tf += l2C[x->sp[q] * 64 + lane];
-        double qn = scale_exp2(1.0, tf);
-        if (x->rev) {
-            double tr = t0 - (double)lnK[(int64_t)order[j] * ldK + c] * kLog2e;
-            for (int q = 0; q < np; ++q) tr += l2C[x->sp[nf + q] * 64 + lane];
-            qn -= scale_exp2(1.0, tr);
+    // this wave's range, run by run (runs hold reactions of one shape)
+    for (int rn = 0; rn < m.nruns; ++rn) {
+        const ShapeRun run = m.runs[rn];
+        const int a = run.start > j0 ? run.start : j0;
+        const int b = run.start + run.count < j1 ? run.start + run.count : j1;
+        if (a >= b) continue;
+        const int shape = (run.nf - 1) * 4 + (run.nr - 1);
+#define AK_LNK(F, R)                                                                         \
+    case (F - 1) * 4 + (R - 1):                                                              \
+        lnk_run<IO, F, R>(m, order, a, b, run.rev, l2C, acc, lane, lnK, ldK, c, log2T, invT); \
+        break;
+        switch (shape) {
+            AK_LNK(1, 1) AK_LNK(1, 2) AK_LNK(1, 3) AK_LNK(1, 4)
+            AK_LNK(2, 1) AK_LNK(2, 2) AK_LNK(2, 3) AK_LNK(2, 4)
+            AK_LNK(3, 1) AK_LNK(3, 2) AK_LNK(3, 3) AK_LNK(3, 4)
+            AK_LNK(4, 1) AK_LNK(4, 2) AK_LNK(4, 3) AK_LNK(4, 4)
+            default: break;
         }
-        for (int q = 0; q < nf; ++q) acc[x->sp[q] * 64 + lane] -= qn;
-        for (int q = 0; q < np; ++q) acc[x->sp[nf + q] * 64 + lane] += qn;
+#undef AK_LNK
     }
     __syncthreads();
     // the waves' shares in wave order; this wave stores species k = wave + SW i
