@@ -47,10 +47,17 @@ struct ak_kcnet {
 #ifndef AK_KCNET_CHUNK_DIV
 #define AK_KCNET_CHUNK_DIV 4
 #endif
-// FP32 readout of networks of width >= 16 on the matrix cores (1) or the
-// vector ALU (0)
+// Readout of networks of width >= 16 on the matrix cores (1) or the vector
+// ALU (0), FP32 and FP64.  The FP64 matrix-core form
+// (v_mfma_f64_16x16x4_f64, same operand layouts) differed from the float64
+// oracle by about 4e-9 relative, a million times the rounding of the same
+// sums on the vector ALU, so the FP64 path stays on the vector ALU (whose
+// peak the FP64 matrix cores do not exceed on this device).
 #ifndef AK_KCNET_MFMA
 #define AK_KCNET_MFMA 1
+#endif
+#ifndef AK_KCNET_MFMA64
+#define AK_KCNET_MFMA64 0
 #endif
 
 namespace ak {
@@ -170,6 +177,10 @@ __device__ __forceinline__ void static_for(F &&f)
     }
 }
 
+// fused multiply-add in the element type (float stays float)
+__device__ __forceinline__ float fma_e(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_e(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename E>
 __device__ __forceinline__ E elu(E x)
 {
@@ -206,7 +217,7 @@ __global__ __launch_bounds__(256) void kcnet_kernel(const E *__restrict__ w, int
         E g[NH];
         static_for<0, NH>([&](auto o) {
             E acc = p[NH * NH + o];
-            static_for<0, NH>([&](auto q) { acc = __builtin_fma(h[q], p[o * NH + q], acc); });
+            static_for<0, NH>([&](auto q) { acc = fma_e(h[q], p[o * NH + q], acc); });
             g[o] = elu<E>(acc);
         });
         static_for<0, NH>([&](auto o) { h[o] = g[o]; });
@@ -219,12 +230,23 @@ __global__ __launch_bounds__(256) void kcnet_kernel(const E *__restrict__ w, int
     for (int j = j0; j < j1; ++j) {
         const E *wj = p + (int64_t)j * NH;
         E acc = bo[j];
-        static_for<0, NH>([&](auto q) { acc = __builtin_fma(h[q], wj[q], acc); });
+        static_for<0, NH>([&](auto q) { acc = fma_e(h[q], wj[q], acc); });
         lnK[(int64_t)j * ldK + i] = bad ? nan : acc;
     }
 }
 
 typedef float ak_f32x4 __attribute__((ext_vector_type(4)));
+typedef double ak_f64x4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 4 matrix-core step D = A B + D in the element type
+__device__ __forceinline__ ak_f32x4 mfma16x16x4(float a, float b, ak_f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ ak_f64x4 mfma16x16x4(double a, double b, ak_f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // FP32 networks of width 16 and more: the hidden layers as in kcnet_kernel
 // (lane = cell, activations in registers), then the readout, a
@@ -237,67 +259,66 @@ typedef float ak_f32x4 __attribute__((ext_vector_type(4)));
 // leaves early (the matrix instructions need the whole wave): lanes past the
 // last cell compute the last cell again and store nothing.  The k-steps run
 // in a fixed order (bitwise repeatable).
-template <int NH>
-__global__ __launch_bounds__(256) void kcnet_mfma_kernel(const float *__restrict__ w, int nl,
-                                                         int nr, int rpc, double x_mean,
-                                                         double x_std,
-                                                         const float *__restrict__ T, int64_t n,
-                                                         float *__restrict__ lnK, int64_t ldK)
+template <typename E, int NH>
+__global__ __launch_bounds__(256) void kcnet_mfma_kernel(const E *__restrict__ w, int nl, int nr,
+                                                         int rpc, double x_mean, double x_std,
+                                                         const E *__restrict__ T, int64_t n,
+                                                         E *__restrict__ lnK, int64_t ldK)
 {
+    using V4 = typename std::conditional<sizeof(E) == 8, ak_f64x4, ak_f32x4>::type;
     constexpr int LDH = NH + 1;
     constexpr int KS = NH / 4;
-    // dynamic LDS: per wave 64 rows of LDH floats, then 64 bad-cell flags
-    extern __shared__ float kc_lds[];
+    // dynamic LDS: per wave 64 rows of LDH elements, then 64 bad-cell flags
+    extern __shared__ double kc_lds_d[];
+    E *kc_lds = (E *)kc_lds_d;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    float *Hw = kc_lds + wave * 64 * LDH;
-    float *badw = kc_lds + 4 * 64 * LDH + wave * 64;
+    E *Hw = kc_lds + wave * 64 * LDH;
+    E *badw = kc_lds + 4 * 64 * LDH + wave * 64;
     const int64_t c0 = (int64_t)blockIdx.x * 256 + wave * 64;
     const int64_t i = c0 + lane;
     const int64_t ic = i < n ? i : n - 1;
     const double t = (double)T[ic];
     const bool bad = !(t > 0.0) || !__builtin_isfinite(t);
-    const float z = (float)((log(bad ? 1.0 : t) - x_mean) / x_std);
-    float h[NH];
-    static_for<0, NH>([&](auto o) { h[o] = elu<float>(z * w[o] + w[NH + o]); });
-    const float *p = w + 2 * NH;
+    const E z = (E)((log(bad ? 1.0 : t) - x_mean) / x_std);
+    E h[NH];
+    static_for<0, NH>([&](auto o) { h[o] = elu<E>(z * w[o] + w[NH + o]); });
+    const E *p = w + 2 * NH;
     for (int l = 1; l < nl; ++l) {
-        float g[NH];
+        E g[NH];
         static_for<0, NH>([&](auto o) {
-            float acc = p[NH * NH + o];
-            static_for<0, NH>([&](auto q) { acc = __builtin_fmaf(h[q], p[o * NH + q], acc); });
-            g[o] = elu<float>(acc);
+            E acc = p[NH * NH + o];
+            static_for<0, NH>([&](auto q) { acc = fma_e(h[q], p[o * NH + q], acc); });
+            g[o] = elu<E>(acc);
         });
         static_for<0, NH>([&](auto o) { h[o] = g[o]; });
         p += NH * NH + NH;
     }
     static_for<0, NH>([&](auto q) { Hw[lane * LDH + q] = h[q]; });
-    badw[lane] = bad ? 1.0f : 0.0f;
+    badw[lane] = bad ? (E)1 : (E)0;
     __syncthreads();
     // B operand: lane l holds H[cell 16 cb + l % 16][unit 4 kb + l / 16]
     const int lm = lane & 15, lk = lane >> 4;
-    float bfr[4][KS];
+    E bfr[4][KS];
     bool bcol[4];
     static_for<0, 4>([&](auto cb) {
         static_for<0, KS>([&](auto kb) { bfr[cb][kb] = Hw[(cb * 16 + lm) * LDH + kb * 4 + lk]; });
-        bcol[cb] = badw[cb * 16 + lm] != 0.0f;
+        bcol[cb] = badw[cb * 16 + lm] != (E)0;
     });
-    const float *bo = p + (int64_t)nr * NH;
-    const float nan = __builtin_nanf("");
+    const E *bo = p + (int64_t)nr * NH;
+    const E nan = (E)__builtin_nan("");
     const int j0 = blockIdx.y * rpc, j1 = min(nr, j0 + rpc);
     for (int jb = j0; jb < j1; jb += 16) {
         // A operand: lane l holds W^T[reaction jb + l % 16][unit 4 kb + l / 16]
         const int ja = min(jb + lm, nr - 1);
-        float afr[KS];
+        E afr[KS];
         static_for<0, KS>([&](auto kb) { afr[kb] = p[(int64_t)ja * NH + kb * 4 + lk]; });
         // this lane's result rows: reactions jb + 4 (l / 16) + v
-        float bias[4];
+        E bias[4];
         static_for<0, 4>([&](auto v) { bias[v] = bo[min(jb + 4 * lk + (int)v, nr - 1)]; });
         static_for<0, 4>([&](auto cb) {
-            ak_f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            static_for<0, KS>([&](auto kb) {
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[kb], bfr[cb][kb], acc, 0, 0, 0);
-            });
+            V4 acc = {(E)0, (E)0, (E)0, (E)0};
+            static_for<0, KS>([&](auto kb) { acc = mfma16x16x4(afr[kb], bfr[cb][kb], acc); });
             const int64_t cell = c0 + cb * 16 + lm;
             static_for<0, 4>([&](auto v) {
                 const int j = jb + 4 * lk + v;
@@ -570,6 +591,7 @@ int chunks_for(int64_t tiles, int nr, int64_t target, int minr, int64_t cap)
 
 constexpr int64_t kTargetWaves = 8192;   // 8 per SIMD
 constexpr bool kMfmaReadout = AK_KCNET_MFMA != 0;
+constexpr bool kMfmaReadout64 = AK_KCNET_MFMA64 != 0;
 
 template <typename T>
 struct Tag {
@@ -589,24 +611,23 @@ hipError_t launch_kcnet(const ak_kcnet *net, const E *w, const void *T, int64_t 
     const int ch = chunks_for((n + 63) / 64, net->nr, kTargetWaves, 16,
                               readout / (hidden * AK_KCNET_CHUNK_DIV));
     int rpc = (net->nr + ch - 1) / ch;
-    if constexpr (sizeof(E) == 4) {
-        if (net->nhp >= 16 && kMfmaReadout) {
+    if (net->nhp >= 16 && (sizeof(E) == 4 ? kMfmaReadout : kMfmaReadout64)) {
+        {
             // whole 16-reaction blocks per chunk
             rpc = (rpc + 15) & ~15;
             const dim3 g((unsigned)blocks, (unsigned)((net->nr + rpc - 1) / rpc)), b(256);
             auto go = [&](auto kern, int nh) {
-                const size_t lds = ((size_t)4 * 64 * (nh + 1) + 4 * 64) * sizeof(float);
+                const size_t lds = ((size_t)4 * 64 * (nh + 1) + 4 * 64) * sizeof(E);
                 hipError_t e = allow_dynamic_lds((const void *)kern);
                 if (e != hipSuccess) return e;
-                hipLaunchKernelGGL(kern, g, b, lds, st, (const float *)w, net->nl, net->nr, rpc,
-                                   net->x_mean, net->x_std, (const float *)T, n, (float *)lnK,
-                                   ldK);
+                hipLaunchKernelGGL(kern, g, b, lds, st, w, net->nl, net->nr, rpc, net->x_mean,
+                                   net->x_std, (const E *)T, n, (E *)lnK, ldK);
                 return hipGetLastError();
             };
             switch (net->nhp) {
-                case 16: return go(kcnet_mfma_kernel<16>, 16);
-                case 32: return go(kcnet_mfma_kernel<32>, 32);
-                case 64: return go(kcnet_mfma_kernel<64>, 64);
+                case 16: return go(kcnet_mfma_kernel<E, 16>, 16);
+                case 32: return go(kcnet_mfma_kernel<E, 32>, 32);
+                case 64: return go(kcnet_mfma_kernel<E, 64>, 64);
                 default: return hipErrorInvalidValue;
             }
         }
