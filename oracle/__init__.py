@@ -11,7 +11,8 @@ changes (Eq. 8), reverse constants k_r = k_f / K_c (Eq. 7), rates of progress
 as products of concentrations (Eq. 3), and net production rates (Eq. 2).
 ``source(..., precision="ld")`` evaluates in x86 extended precision.
 ``lnkc`` gives ln K_c alone, ``source_lnkc`` the source term with a given
-ln K_c in place of Eq. 8, and ``kcnet`` the approximate ln K_c network of
+ln K_c in place of Eq. 8, ``production`` the stoichiometric contraction
+omega = nu r of given rates of progress, and ``kcnet`` the approximate ln K_c network of
 Sec. 2.3 (Architecture 2) written out in numpy float64.
 
 Pins (``tests/test_oracle_pins.py``): two hand-worked reactions in closed
@@ -331,6 +332,18 @@ def kcnet(net, T, bound: bool = False):
         return lnk
     mag = ((Xa @ np.abs(W[-1]) + np.abs(B[-1])) * np.abs(ys) + np.abs(ym)).T.copy()
     return lnk, mag
+
+
+def production(mech, r):
+    """Net production rates omega = nu r [NS, n] (Eq. 2) from given rates of
+    progress r [NR, n] (r_j = q_f,j - q_r,j, file order), in float64, with
+    nu = nu'' - nu' (products minus reactants).  The reduced-precision
+    contraction (the single/half-precision future work of Sec. 4) is checked
+    against this exact product."""
+    nu = (np.asarray(mech.nu_r, np.float64) - np.asarray(mech.nu_f, np.float64)).T
+    r = np.asarray(r, np.float64)
+    assert r.ndim == 2 and r.shape[0] == nu.shape[1]
+    return nu @ r
 
 
 def temp_source(mech, T, P, Y, precision: str = "f64", n_threads: int = 0):
