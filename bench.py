@@ -400,6 +400,52 @@ def deriv_bench(torch, annkin, steps=10):
     return out
 
 
+def prod_bench(torch, annkin, steps=20):
+    """The stoichiometric contraction omega = nu r from given FP32 rates of
+    progress on the matrix cores in split bfloat16 (ak_eval_production),
+    53/325 x 2^20 and 150/600 x 2^19 cells.  It is HBM-bound: the
+    algorithmic traffic is (N_R + N_S) x 4 bytes per cell.  Beside it, the
+    same product as a dense FP32 library GEMM (torch.matmul) for context,
+    and the error of the sampled result against nu r in float64 relative to
+    sum |nu| |r| (the FP32 dot-product error, about 2^-24 per term)."""
+    rows = {}
+    for ns, nr, n in ((53, 325, 1 << 20), (150, 600, 1 << 19)):
+        src = synth.make_mechanism(ns, nr)
+        mech = annkin.Mechanism(src)
+        g = torch.Generator(device="cuda").manual_seed(1)
+        r = torch.randn((nr, n), generator=g, device="cuda", dtype=torch.float32)
+        out = torch.empty((ns, n), dtype=torch.float32, device="cuda")
+        nu = torch.tensor((src.nu_r.astype(np.float32) - src.nu_f.astype(np.float32)).T,
+                          device="cuda").contiguous()
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / steps
+
+        ms = timed(lambda: annkin.eval_production(mech, r, out=out))
+        ms_mm = timed(lambda: torch.matmul(nu, r))
+        byt = (nr + ns) * 4 * n
+        idx = torch.arange(0, n, 257, device="cuda")
+        rs = r[:, idx].double()
+        want = nu.double() @ rs
+        err = ((out[:, idx].double() - want).abs() / (nu.double().abs() @ rs.abs())
+               .clamp_min(1e-300)).max().item()
+        rows[f"{ns}x{nr}"] = {
+            "n_cells": n, "ms": ms, "cells_per_s": n / (ms * 1e-3),
+            "hbm_GBps": byt / (ms * 1e-3) / 1e9, "hbm_frac": byt / (ms * 1e-3) / roofline.PEAK_HBM,
+            "torch_fp32_matmul_ms": ms_mm, "max_err_rel_to_sum_abs": err}
+        del r, out
+        mech.close()
+    return rows
+
+
 def kc_bench(torch, annkin, steps=20, train=True):
     """The trained ln K_c network of Sec. 2.3 (Architecture 2) against the
     exact Gibbs and stoichiometric layers, at the paper's N_C = 10^5 (its
@@ -535,6 +581,9 @@ def main():
     ap.add_argument("--only-deriv", action="store_true",
                     help="time only the differentiation configuration (for profiler runs)")
     ap.add_argument("--no-kc", action="store_true")
+    ap.add_argument("--no-prod", action="store_true")
+    ap.add_argument("--only-prod", action="store_true",
+                    help="only the split-bfloat16 stoichiometric contraction")
     ap.add_argument("--only-kc", action="store_true",
                     help="time only the ln K_c network study (no training)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -551,6 +600,10 @@ def main():
     if args.only_deriv:
         from paper_2008_08483_amd import annkin
         print(json.dumps({"differentiation": deriv_bench(torch, annkin)}), flush=True)
+        return
+    if args.only_prod:
+        from paper_2008_08483_amd import annkin
+        print(json.dumps({"stoich_contraction_bf16x3": prod_bench(torch, annkin)}), flush=True)
         return
     if args.only_kc:
         from paper_2008_08483_amd import annkin
@@ -636,7 +689,7 @@ def main():
 
     if args.only_main:
         args.no_fp64 = args.no_cpu_baseline = args.no_serving = args.no_deriv = True
-        args.no_c2 = args.no_saturation = args.no_pdep = args.no_kc = True
+        args.no_c2 = args.no_saturation = args.no_pdep = args.no_kc = args.no_prod = True
     result["kernel_compiled"] = bool(mech.compiled(torch.float32))
     if not args.only_main:
         result["accuracy"] = accuracy(torch, annkin, mech, src, T, P, Y)
@@ -683,6 +736,8 @@ def main():
 
     if not args.no_kc:
         result["approx_lnkc"] = kc_bench(torch, annkin)
+    if not args.no_prod:
+        result["stoich_contraction_bf16x3"] = prod_bench(torch, annkin)
 
     if not args.no_serving:
         result["serving"] = serving_bench(torch, annkin)

@@ -478,6 +478,25 @@ int ak_integrate_euler_net(const ak_mechanism *mech, const ak_kcnet *net, ak_pre
                            void *T, const void *P, void *Y, int64_t ldY, int64_t n_cells,
                            double dt, int n_steps, void *stream);
 
+/*
+ * Net production rates from given rates of progress, omega = nu r (Eq. 2,
+ * nu = nu'' - nu'), with the contraction on the matrix cores in split
+ * bfloat16: the reduced-precision environment Sec. 4 names as future work.
+ * nu is exact in bfloat16; each rate is cut exactly into three bfloat16
+ * parts, so every product is exact and only the FP32 accumulation rounds
+ * (the error of an FP32 dot product over 3 N_R terms; rates below about
+ * 1e-33 in magnitude lose their lowest part).
+ *   rates  device, FP32, [N_R][ldR]: r_j = q_f,j - q_r,j of reaction j
+ *          (descriptor order) in cell i at rates[j*ldR + i]; finite (a
+ *          non-finite rate makes its species' outputs non-finite)
+ *   omega  device, FP32, [NS][ldO], written for i < n_cells only
+ * The caller owns both buffers.  The first call uploads nu in the operand
+ * order (a few hundred KB, kept with the mechanism).  Errors: AK_EINVAL
+ * (null pointers, ldR or ldO < n_cells), AK_E2BIG, AK_EDEVICE, AK_ENOMEM.
+ */
+int ak_eval_production(const ak_mechanism *mech, const float *rates, int64_t ldR,
+                       int64_t n_cells, float *omega, int64_t ldO, void *stream);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of many callers' source-term requests.
  *

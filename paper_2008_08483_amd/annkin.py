@@ -134,6 +134,8 @@ def lib():
         h.ak_eval_source_lnkc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                           C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
                                           C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+        h.ak_eval_production.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                         C.c_void_p, C.c_int64, C.c_void_p]
         h.ak_eval_source_net.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                          C.c_void_p, C.c_int64, C.c_void_p]
@@ -551,6 +553,28 @@ def eval_source_lnkc(mech: Mechanism, T, P, Y, lnK, out=None, stream=None):
     _check(lib().ak_eval_source_lnkc(mech.handle, _prec(T.dtype), T.data_ptr(), P.data_ptr(),
                                      Y.data_ptr(), ldY, n, lnK.data_ptr(), ldK, out.data_ptr(),
                                      ldO, _stream_ptr(stream)))
+    return out
+
+
+def eval_production(mech: Mechanism, rates, out=None, stream=None):
+    """omega = nu r [NS, n] (FP32) from rates of progress r [NR, n] (FP32,
+    cells contiguous), contracted on the matrix cores in split bfloat16.
+    Asynchronous."""
+    torch = _torch()
+    if (not isinstance(rates, torch.Tensor) or not rates.is_cuda
+            or rates.dtype != torch.float32 or rates.dim() != 2
+            or rates.shape[0] != mech.n_reactions or rates.stride(1) != 1):
+        raise ValueError("rates must be a GPU float32 [NR, n] tensor, cells contiguous")
+    n = rates.shape[1]
+    if out is None:
+        out = torch.empty((mech.n_species, n), dtype=torch.float32, device=rates.device)
+    elif (out.shape != (mech.n_species, n) or out.dtype != torch.float32
+          or out.stride(1) != 1 or not out.is_cuda):
+        raise ValueError("out must be a GPU float32 [NS, n] tensor")
+    ldR = rates.stride(0) if mech.n_reactions > 1 else n
+    ldO = out.stride(0) if mech.n_species > 1 else n
+    _check(lib().ak_eval_production(mech.handle, rates.data_ptr(), ldR, n, out.data_ptr(),
+                                    ldO, _stream_ptr(stream)))
     return out
 
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libannkin.so")
 
 SOURCES = ["api.cpp", "jit.cpp", "jit_jac.cpp", "server.cpp", "source_kernels.hip",
-           "deriv_kernels.hip", "integrate.hip", "kcnet.hip"]
+           "deriv_kernels.hip", "integrate.hip", "kcnet.hip", "production.hip"]
 
 # Packed FP32 instructions stay disabled: every float op is a plain VALU op.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",

@@ -39,6 +39,9 @@ struct ak_mechanism {
     mutable bool kc_wide = false;   // a reaction has more than 4 distinct species
     mutable int kc_pieces = 0;      // intervals of the composed ln K_c layers (0: not built)
     mutable size_t kc_fold_off = 0; // their records' offset in kc_dev
+    // nu in the matrix-core operand order of the split-bfloat16
+    // contraction, uploaded at its first call
+    mutable unsigned char *prod_dev = nullptr;
 };
 
 namespace ak {

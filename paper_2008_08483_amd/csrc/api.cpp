@@ -555,6 +555,7 @@ int ak_free_mechanism(ak_mechanism *m)
     }
     if (m->jac_dev) (void)hipFree(m->jac_dev);
     if (m->kc_dev) (void)hipFree(m->kc_dev);
+    if (m->prod_dev) (void)hipFree(m->prod_dev);
     (void)hipFree(m->dev);
     delete m;
     return AK_OK;

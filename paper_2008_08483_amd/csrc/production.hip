@@ -1,0 +1,218 @@
+// The stoichiometric contraction omega = nu r on the matrix cores in split
+// bfloat16 (the reduced-precision environments named as future work in
+// Sec. 4; the contraction itself is Eq. 2 with the rates of progress given).
+//
+// nu = nu'' - nu' holds small integers, exact in bfloat16.  Each FP32 rate
+// is cut into three bfloat16 parts h + m + l == r exactly (8 + 8 + 8
+// significant bits, truncation leaves no remainder for normal numbers), so
+// every product nu_kj * part is exact and the only rounding is the FP32
+// accumulation inside v_mfma_f32_16x16x32_bf16.  The result carries the
+// error of an FP32 dot product over 3 N_R terms.
+//
+// Layout: one wave owns 16 cells, one workgroup 64 (four waves), and a group
+// of up to 8 blocks of 16 species (grid y).  Per chunk of 32 reactions a
+// lane loads the 8 rates of its (reaction octet, cell) pair straight from
+// HBM (each load instruction covers 4 rows x 64 contiguous bytes), splits
+// them, and issues three MFMAs per species block against the constant
+// nu operand, which the host lays out in lane order once per mechanism.
+// The work is HBM-bound: (N_R + N_S) x 4 bytes per cell against
+// 2 N_S N_R x 3 dense MFMA flops.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "annkin.h"
+#include "ak_device.h"
+#include "ak_internal.h"
+
+namespace ak {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGroup = 8;        // species blocks of 16 per workgroup
+constexpr int kChunk = 32;       // reactions per MFMA step
+std::mutex g_prod_mu;
+
+// x == h + m + l with each part's FP32 pattern in the high 16 bits (returned
+// as the bfloat16 bit pattern)
+__device__ __forceinline__ void split3(float x, unsigned &h, unsigned &m, unsigned &l)
+{
+    const unsigned hb = __float_as_uint(x) & 0xffff0000u;
+    const float r1 = x - __uint_as_float(hb);
+    const unsigned mb = __float_as_uint(r1) & 0xffff0000u;
+    const float r2 = r1 - __uint_as_float(mb);
+    h = hb >> 16;
+    m = mb >> 16;
+    l = __float_as_uint(r2) >> 16;
+}
+
+__device__ __forceinline__ bf16x8 pack8(const unsigned (&v)[8])
+{
+    u32x4 p;
+    p[0] = v[0] | (v[1] << 16);
+    p[1] = v[2] | (v[3] << 16);
+    p[2] = v[4] | (v[5] << 16);
+    p[3] = v[6] | (v[7] << 16);
+    return __builtin_bit_cast(bf16x8, p);
+}
+
+// A: [kchunks][mbp][64 lanes] x 8 bfloat16 of nu, lane l holding species
+// 16 b + l % 16 and reactions 32 c + 8 (l / 16) + 0..7 (the MFMA's A
+// operand layout; the B operand uses the same reaction index per lane and
+// slot, so the k order inside a chunk is immaterial).
+template <int MB>
+__global__ __launch_bounds__(256) void production_kernel(const u32x4 *__restrict__ A,
+                                                         int kchunks, int mbp,
+                                                         const float *__restrict__ r,
+                                                         int64_t ldr, int nr, int64_t n,
+                                                         float *__restrict__ w, int64_t ldw,
+                                                         int ns)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int64_t cell = (int64_t)blockIdx.x * 64 + wave * 16 + col;
+    const int64_t cc = cell < n ? cell : n - 1;
+    const int g0 = blockIdx.y * MB;
+    f32x4 acc[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < kchunks; ++c) {
+        unsigned h[8], m[8], l[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = c * kChunk + kq * 8 + i;
+            float x = r[(int64_t)(k < nr ? k : nr - 1) * ldr + cc];
+            if (k >= nr) x = 0.f;
+            split3(x, h[i], m[i], l[i]);
+        }
+        const bf16x8 bh = pack8(h), bm = pack8(m), bl = pack8(l);
+        const u32x4 *Ac = A + ((int64_t)c * mbp + g0) * 64 + lane;
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+            const bf16x8 a = __builtin_bit_cast(bf16x8, Ac[b * 64]);
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[b], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bm, acc[b], 0, 0, 0);
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc[b], 0, 0, 0);
+        }
+    }
+    if (cell >= n) return;
+    // output element (4 (l / 16) + v, l % 16) of each 16 x 16 block
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int s = (g0 + b) * 16 + kq * 4 + v;
+            if (s < ns) w[(int64_t)s * ldw + cell] = acc[b][v];
+        }
+}
+
+struct ProdShape {
+    int kchunks, mbp, mb, groups;
+};
+
+ProdShape prod_shape(int ns, int nr)
+{
+    ProdShape p;
+    const int mbt = (ns + 15) / 16;
+    p.mb = std::min(mbt, kGroup);
+    p.groups = (mbt + p.mb - 1) / p.mb;
+    p.mbp = p.groups * p.mb;
+    p.kchunks = (nr + kChunk - 1) / kChunk;
+    return p;
+}
+
+// nu in the A operand's lane order, built from the reaction records at the
+// first call and kept with the mechanism
+int prod_table(const ak_mechanism *m, const ProdShape &p, const u32x4 **out)
+{
+    std::lock_guard<std::mutex> lk(g_prod_mu);
+    if (!m->prod_dev) {
+        std::vector<int> nu((size_t)m->ns * m->nr, 0);   // [species][descriptor reaction]
+        for (int s = 0; s < m->nr; ++s) {
+            const RxnAux &x = m->host_aux[s];
+            const int j = m->rxn_order[s];
+            for (int q = 0; q < x.nf + x.nr; ++q)
+                nu[(size_t)x.sp[q] * m->nr + j] += q < x.nf ? -1 : 1;
+        }
+        const size_t words = (size_t)p.kchunks * p.mbp * 64 * 4;
+        std::vector<uint32_t> t(words, 0);
+        for (int c = 0; c < p.kchunks; ++c)
+            for (int b = 0; b < p.mbp; ++b)
+                for (int l = 0; l < 64; ++l)
+                    for (int i = 0; i < 8; ++i) {
+                        const int s = b * 16 + (l & 15), k = c * kChunk + 8 * (l >> 4) + i;
+                        if (s >= m->ns || k >= m->nr) continue;
+                        const float v = (float)nu[(size_t)s * m->nr + k];
+                        uint32_t bits;
+                        std::memcpy(&bits, &v, 4);
+                        // |nu| <= 8: its float pattern has a zero low half
+                        const uint32_t bf = bits >> 16;
+                        t[(((size_t)c * p.mbp + b) * 64 + l) * 4 + i / 2] |= bf << (16 * (i & 1));
+                    }
+        void *d = nullptr;
+        hipError_t e = hipMalloc(&d, words * 4);
+        if (e != hipSuccess) return hip_error(e, "ak_eval_production: table allocation");
+        e = hipMemcpy(d, t.data(), words * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_error(e, "ak_eval_production: table upload");
+        }
+        m->prod_dev = (unsigned char *)d;
+    }
+    *out = (const u32x4 *)m->prod_dev;
+    return AK_OK;
+}
+
+}  // namespace
+}  // namespace ak
+
+using namespace ak;
+
+extern "C" {
+
+int ak_eval_production(const ak_mechanism *m, const float *rates, int64_t ldR, int64_t n,
+                       float *omega, int64_t ldO, void *stream)
+{
+    const char *fn = "ak_eval_production";
+    if (!m) return set_error(AK_EINVAL, "%s: null mechanism", fn);
+    if (n < 0) return set_error(AK_EINVAL, "%s: n_cells < 0", fn);
+    if (n > (int64_t)1 << 40) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
+    if (n == 0) return AK_OK;
+    if (!rates || !omega) return set_error(AK_EINVAL, "%s: null pointer", fn);
+    if (ldR < n || ldO < n)
+        return set_error(AK_EINVAL, "%s: ldR=%lld, ldO=%lld < n_cells=%lld", fn,
+                         (long long)ldR, (long long)ldO, (long long)n);
+    const ProdShape p = prod_shape(m->ns, m->nr);
+    const int64_t blocks = (n + 63) / 64;
+    if (blocks > 0x7fffffff) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
+    DeviceGuard g(m->device);
+    if (!g.ok) return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, m->device);
+    const u32x4 *A;
+    int rc = prod_table(m, p, &A);
+    if (rc) return rc;
+    const dim3 grid((unsigned)blocks, (unsigned)p.groups);
+    hipStream_t st = (hipStream_t)stream;
+#define AK_PROD(MB)                                                                         \
+    case MB:                                                                                \
+        hipLaunchKernelGGL((production_kernel<MB>), grid, dim3(256), 0, st, A, p.kchunks,   \
+                           p.mbp, rates, ldR, m->nr, n, omega, ldO, m->ns);                 \
+        break
+    switch (p.mb) {
+        AK_PROD(1); AK_PROD(2); AK_PROD(3); AK_PROD(4);
+        AK_PROD(5); AK_PROD(6); AK_PROD(7); AK_PROD(8);
+        default: return set_error(AK_EINVAL, "%s: species blocks %d", fn, p.mb);
+    }
+#undef AK_PROD
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, "ak_eval_production: launch");
+    return AK_OK;
+}
+
+}  // extern "C"

@@ -50,6 +50,7 @@ def test_argument_errors_without_gpu(lib):
     assert b"257 species" in lib.ak_last_error()
     assert lib.ak_eval_source(None, 0, None, None, None, 0, 0, None, 0, None) == -1
     assert lib.ak_free_mechanism(None) == 0
+    assert lib.ak_eval_production(None, None, 0, 0, None, 0, None) == -1
     assert lib.ak_mechanism_n_species(None) == -1
     assert lib.ak_version().startswith(b"annkin")
 
