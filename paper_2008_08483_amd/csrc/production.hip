@@ -9,12 +9,14 @@
 // accumulation inside v_mfma_f32_16x16x32_bf16.  The result carries the
 // error of an FP32 dot product over 3 N_R terms.
 //
-// Layout: one wave owns 16 cells, one workgroup 64 (four waves), and a group
-// of up to 8 blocks of 16 species (grid y).  Per chunk of 32 reactions a
+// Layout: one wave owns 16 NCB cells, one workgroup 64 NCB (four waves), and a group
+// of up to 16 blocks of 16 species (grid y; one group up to 256 species, so
+// the rates are read once).  Per chunk of 32 reactions a
 // lane loads the 8 rates of its (reaction octet, cell) pair straight from
 // HBM (each load instruction covers 4 rows x 64 contiguous bytes), splits
 // them, and issues three MFMAs per species block against the constant
-// nu operand, which the host lays out in lane order once per mechanism.
+// nu operand, which the host lays out in lane order once per mechanism; the
+// next chunk's loads are in flight meanwhile.
 // The work is HBM-bound: (N_R + N_S) x 4 bytes per cell against
 // 2 N_S N_R x 3 dense MFMA flops.
 #include <hip/hip_runtime.h>
@@ -36,7 +38,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGroup = 8;        // species blocks of 16 per workgroup
+#ifndef AK_PROD_GROUP
+#define AK_PROD_GROUP 16
+#endif
+constexpr int kGroup = AK_PROD_GROUP;   // species blocks of 16 per workgroup
 constexpr int kChunk = 32;       // reactions per MFMA step
 std::mutex g_prod_mu;
 
@@ -66,8 +71,10 @@ __device__ __forceinline__ bf16x8 pack8(const unsigned (&v)[8])
 // A: [kchunks][mbp][64 lanes] x 8 bfloat16 of nu, lane l holding species
 // 16 b + l % 16 and reactions 32 c + 8 (l / 16) + 0..7 (the MFMA's A
 // operand layout; the B operand uses the same reaction index per lane and
-// slot, so the k order inside a chunk is immaterial).
-template <int MB>
+// slot, so the k order inside a chunk is immaterial).  Each wave owns NCB
+// blocks of 16 cells, so a workgroup reads 256 NCB contiguous bytes of each
+// rate row and every nu operand load feeds 3 NCB MFMAs.
+template <int MB, int NCB>
 __global__ __launch_bounds__(256) void production_kernel(const u32x4 *__restrict__ A,
                                                          int kchunks, int mbp,
                                                          const float *__restrict__ r,
@@ -77,40 +84,89 @@ __global__ __launch_bounds__(256) void production_kernel(const u32x4 *__restrict
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const int64_t cell = (int64_t)blockIdx.x * 64 + wave * 16 + col;
-    const int64_t cc = cell < n ? cell : n - 1;
-    const int g0 = blockIdx.y * MB;
-    f32x4 acc[MB];
+    const int64_t cell0 = (int64_t)blockIdx.x * (64 * NCB) + wave * (16 * NCB) + col;
+    int64_t cc[NCB];
 #pragma unroll
-    for (int b = 0; b < MB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NCB; ++j) cc[j] = cell0 + 16 * j < n ? cell0 + 16 * j : n - 1;
+    const int g0 = blockIdx.y * MB;
+    f32x4 acc[MB][NCB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) acc[b][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the next chunk's rates are loaded while this chunk's MFMAs run (rows
+    // past the last reaction read the last row and are zeroed)
+    float x[NCB][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = kq * 8 + i;
+        const float *row = r + (int64_t)(k < nr ? k : nr - 1) * ldr;
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) x[j][i] = k < nr ? row[cc[j]] : 0.f;
+    }
     for (int c = 0; c < kchunks; ++c) {
-        unsigned h[8], m[8], l[8];
+        float xn[NCB][8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const int k = c * kChunk + kq * 8 + i;
-            float x = r[(int64_t)(k < nr ? k : nr - 1) * ldr + cc];
-            if (k >= nr) x = 0.f;
-            split3(x, h[i], m[i], l[i]);
+            const int k = (c + 1) * kChunk + kq * 8 + i;
+            const float *row = r + (int64_t)(k < nr ? k : nr - 1) * ldr;
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) {
+                xn[j][i] = row[cc[j]];
+                if (k >= nr) xn[j][i] = 0.f;
+            }
         }
-        const bf16x8 bh = pack8(h), bm = pack8(m), bl = pack8(l);
+        bf16x8 bh[NCB], bm[NCB], bl[NCB];
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) {
+            unsigned h[8], m[8], l[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) split3(x[j][i], h[i], m[i], l[i]);
+            bh[j] = pack8(h);
+            bm[j] = pack8(m);
+            bl[j] = pack8(l);
+        }
         const u32x4 *Ac = A + ((int64_t)c * mbp + g0) * 64 + lane;
 #pragma unroll
         for (int b = 0; b < MB; ++b) {
             const bf16x8 a = __builtin_bit_cast(bf16x8, Ac[b * 64]);
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[b], 0, 0, 0);
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bm, acc[b], 0, 0, 0);
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh, acc[b], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) {
+                acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[j], acc[b][j], 0, 0, 0);
+                acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bm[j], acc[b][j], 0, 0, 0);
+                acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh[j], acc[b][j], 0, 0, 0);
+            }
         }
+#pragma unroll
+        for (int j = 0; j < NCB; ++j)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[j][i] = xn[j][i];
     }
-    if (cell >= n) return;
     // output element (4 (l / 16) + v, l % 16) of each 16 x 16 block
 #pragma unroll
-    for (int b = 0; b < MB; ++b)
+    for (int j = 0; j < NCB; ++j) {
+        const int64_t cell = cell0 + 16 * j;
+        if (cell >= n) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int s = (g0 + b) * 16 + kq * 4 + v;
-            if (s < ns) w[(int64_t)s * ldw + cell] = acc[b][v];
-        }
+        for (int b = 0; b < MB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int s = (g0 + b) * 16 + kq * 4 + v;
+                if (s < ns) w[(int64_t)s * ldw + cell] = acc[b][j][v];
+            }
+    }
+}
+
+// cell blocks per wave for MB species blocks.  Two blocks halve the
+// re-reads of the nu operand (from L2, MB KB per wave and chunk); four push
+// the wave past 160 registers and halve the waves per SIMD (53/325 x 2^20:
+// 0.51 ms with one, 0.39 ms with two, 1.03 ms with four)
+#ifndef AK_PROD_NCB
+#define AK_PROD_NCB 0
+#endif
+constexpr int ncb_for(int mb)
+{
+    return AK_PROD_NCB > 0 ? AK_PROD_NCB : mb <= 4 ? 2 : 1;
 }
 
 struct ProdShape {
@@ -190,7 +246,8 @@ int ak_eval_production(const ak_mechanism *m, const float *rates, int64_t ldR, i
         return set_error(AK_EINVAL, "%s: ldR=%lld, ldO=%lld < n_cells=%lld", fn,
                          (long long)ldR, (long long)ldO, (long long)n);
     const ProdShape p = prod_shape(m->ns, m->nr);
-    const int64_t blocks = (n + 63) / 64;
+    const int64_t cells_per_block = 64 * ncb_for(p.mb);
+    const int64_t blocks = (n + cells_per_block - 1) / cells_per_block;
     if (blocks > 0x7fffffff) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
     DeviceGuard g(m->device);
     if (!g.ok) return set_error(AK_EDEVICE, "%s: cannot select device %d", fn, m->device);
@@ -201,12 +258,16 @@ int ak_eval_production(const ak_mechanism *m, const float *rates, int64_t ldR, i
     hipStream_t st = (hipStream_t)stream;
 #define AK_PROD(MB)                                                                         \
     case MB:                                                                                \
-        hipLaunchKernelGGL((production_kernel<MB>), grid, dim3(256), 0, st, A, p.kchunks,   \
-                           p.mbp, rates, ldR, m->nr, n, omega, ldO, m->ns);                 \
+        hipLaunchKernelGGL((production_kernel<MB, ncb_for(MB)>), grid, dim3(256), 0, st, A, \
+                           p.kchunks, p.mbp, rates, ldR, m->nr, n, omega, ldO, m->ns);      \
         break
     switch (p.mb) {
         AK_PROD(1); AK_PROD(2); AK_PROD(3); AK_PROD(4);
         AK_PROD(5); AK_PROD(6); AK_PROD(7); AK_PROD(8);
+#if AK_PROD_GROUP > 8
+        AK_PROD(9); AK_PROD(10); AK_PROD(11); AK_PROD(12);
+        AK_PROD(13); AK_PROD(14); AK_PROD(15); AK_PROD(16);
+#endif
         default: return set_error(AK_EINVAL, "%s: species blocks %d", fn, p.mb);
     }
 #undef AK_PROD
