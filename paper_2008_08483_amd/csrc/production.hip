@@ -157,6 +157,102 @@ __global__ __launch_bounds__(256) void production_kernel(const u32x4 *__restrict
     }
 }
 
+// The same contraction with nu staged in LDS: per stage of sc chunks the
+// workgroup copies its nu blocks (sc x MB KB) once and its four waves read
+// them from LDS, instead of each wave reading its MB KB per chunk from L2.
+// Used for more than four species blocks, where those re-reads bound the
+// register form (150/600 x 2^19: 1.06 -> 0.78 ms); at four blocks or fewer
+// the register form is faster.
+template <int MB, int NCB>
+__global__ __launch_bounds__(256) void production_lds_kernel(const u32x4 *__restrict__ A,
+                                                             int kchunks, int mbp, int sc,
+                                                             const float *__restrict__ r,
+                                                             int64_t ldr, int nr, int64_t n,
+                                                             float *__restrict__ w,
+                                                             int64_t ldw, int ns)
+{
+    extern __shared__ u32x4 As[];   // sc chunks x MB blocks x 64 lanes
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int64_t cell0 = (int64_t)blockIdx.x * (64 * NCB) + wave * (16 * NCB) + col;
+    int64_t cc[NCB];
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) cc[j] = cell0 + 16 * j < n ? cell0 + 16 * j : n - 1;
+    const int g0 = blockIdx.y * MB;
+    f32x4 acc[MB][NCB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b)
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) acc[b][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float x[NCB][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = kq * 8 + i;
+        const float *row = r + (int64_t)(k < nr ? k : nr - 1) * ldr;
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) x[j][i] = k < nr ? row[cc[j]] : 0.f;
+    }
+    for (int c0 = 0; c0 < kchunks; c0 += sc) {
+        // this group's nu blocks for chunks c0 .. c0 + cn - 1 (the loop is
+        // uniform over the workgroup: every wave reaches both barriers)
+        const int cn = kchunks - c0 < sc ? kchunks - c0 : sc;
+        __syncthreads();
+        for (int t = threadIdx.x; t < cn * MB * 64; t += 256)
+            As[t] = A[((int64_t)(c0 + t / (MB * 64)) * mbp + g0) * 64 + t % (MB * 64)];
+        __syncthreads();
+        for (int c = c0; c < c0 + cn; ++c) {
+            float xn[NCB][8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = (c + 1) * kChunk + kq * 8 + i;
+                const float *row = r + (int64_t)(k < nr ? k : nr - 1) * ldr;
+#pragma unroll
+                for (int j = 0; j < NCB; ++j) {
+                    xn[j][i] = row[cc[j]];
+                    if (k >= nr) xn[j][i] = 0.f;
+                }
+            }
+            bf16x8 bh[NCB], bm[NCB], bl[NCB];
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) {
+                unsigned h[8], m[8], l[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) split3(x[j][i], h[i], m[i], l[i]);
+                bh[j] = pack8(h);
+                bm[j] = pack8(m);
+                bl[j] = pack8(l);
+            }
+            const u32x4 *Ac = As + (c - c0) * MB * 64 + lane;
+#pragma unroll
+            for (int b = 0; b < MB; ++b) {
+                const bf16x8 a = __builtin_bit_cast(bf16x8, Ac[b * 64]);
+#pragma unroll
+                for (int j = 0; j < NCB; ++j) {
+                    acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[j], acc[b][j], 0, 0, 0);
+                    acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bm[j], acc[b][j], 0, 0, 0);
+                    acc[b][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh[j], acc[b][j], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NCB; ++j)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) x[j][i] = xn[j][i];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) {
+        const int64_t cell = cell0 + 16 * j;
+        if (cell >= n) continue;
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int s = (g0 + b) * 16 + kq * 4 + v;
+                if (s < ns) w[(int64_t)s * ldw + cell] = acc[b][j][v];
+            }
+    }
+}
+
 // cell blocks per wave for MB species blocks.  Two blocks halve the
 // re-reads of the nu operand (from L2, MB KB per wave and chunk); four push
 // the wave past 160 registers and halve the waves per SIMD (53/325 x 2^20:
@@ -164,6 +260,8 @@ __global__ __launch_bounds__(256) void production_kernel(const u32x4 *__restrict
 #ifndef AK_PROD_NCB
 #define AK_PROD_NCB 0
 #endif
+constexpr int kProdLdsBytes = 32 * 1024;   // nu staged per workgroup
+
 constexpr int ncb_for(int mb)
 {
     return AK_PROD_NCB > 0 ? AK_PROD_NCB : mb <= 4 ? 2 : 1;
@@ -255,11 +353,19 @@ int ak_eval_production(const ak_mechanism *m, const float *rates, int64_t ldR, i
     int rc = prod_table(m, p, &A);
     if (rc) return rc;
     const dim3 grid((unsigned)blocks, (unsigned)p.groups);
+    // chunks of nu per LDS stage (one 1 KB block per species block and chunk)
+    const int sc = std::max(1, kProdLdsBytes / (p.mb * 1024));
+    const size_t lds = (size_t)sc * p.mb * 1024;
     hipStream_t st = (hipStream_t)stream;
 #define AK_PROD(MB)                                                                         \
     case MB:                                                                                \
-        hipLaunchKernelGGL((production_kernel<MB, ncb_for(MB)>), grid, dim3(256), 0, st, A, \
-                           p.kchunks, p.mbp, rates, ldR, m->nr, n, omega, ldO, m->ns);      \
+        if (MB <= 4)                                                                        \
+            hipLaunchKernelGGL((production_kernel<MB, ncb_for(MB)>), grid, dim3(256), 0, st,\
+                               A, p.kchunks, p.mbp, rates, ldR, m->nr, n, omega, ldO, m->ns);\
+        else                                                                                \
+            hipLaunchKernelGGL((production_lds_kernel<MB, ncb_for(MB)>), grid, dim3(256),   \
+                               lds, st, A, p.kchunks, p.mbp, sc, rates, ldR, m->nr, n,      \
+                               omega, ldO, m->ns);                                          \
         break
     switch (p.mb) {
         AK_PROD(1); AK_PROD(2); AK_PROD(3); AK_PROD(4);
