@@ -163,8 +163,8 @@ __global__ __launch_bounds__(256) void production_kernel(const u32x4 *__restrict
 // Used for more than four species blocks, where those re-reads bound the
 // register form (150/600 x 2^19: 1.06 -> 0.78 ms); at four blocks or fewer
 // the register form is faster.
-template <int MB, int NCB>
-__global__ __launch_bounds__(256) void production_lds_kernel(const u32x4 *__restrict__ A,
+template <int MB, int NCB, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void production_lds_kernel(const u32x4 *__restrict__ A,
                                                              int kchunks, int mbp, int sc,
                                                              const float *__restrict__ r,
                                                              int64_t ldr, int nr, int64_t n,
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void production_lds_kernel(const u32x4 *__rest
     extern __shared__ u32x4 As[];   // sc chunks x MB blocks x 64 lanes
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const int64_t cell0 = (int64_t)blockIdx.x * (64 * NCB) + wave * (16 * NCB) + col;
+    const int64_t cell0 = (int64_t)blockIdx.x * (16 * NCB * WAVES) + wave * (16 * NCB) + col;
     int64_t cc[NCB];
 #pragma unroll
     for (int j = 0; j < NCB; ++j) cc[j] = cell0 + 16 * j < n ? cell0 + 16 * j : n - 1;
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void production_lds_kernel(const u32x4 *__rest
         // uniform over the workgroup: every wave reaches both barriers)
         const int cn = kchunks - c0 < sc ? kchunks - c0 : sc;
         __syncthreads();
-        for (int t = threadIdx.x; t < cn * MB * 64; t += 256)
+        for (int t = threadIdx.x; t < cn * MB * 64; t += 64 * WAVES)
             As[t] = A[((int64_t)(c0 + t / (MB * 64)) * mbp + g0) * 64 + t % (MB * 64)];
         __syncthreads();
         for (int c = c0; c < c0 + cn; ++c) {
@@ -261,6 +261,10 @@ __global__ __launch_bounds__(256) void production_lds_kernel(const u32x4 *__rest
 #define AK_PROD_NCB 0
 #endif
 constexpr int kProdLdsBytes = 32 * 1024;   // nu staged per workgroup
+#ifndef AK_PROD_LDS_WAVES
+#define AK_PROD_LDS_WAVES 4
+#endif
+constexpr int kLdsWaves = AK_PROD_LDS_WAVES;   // waves sharing each staged block
 
 constexpr int ncb_for(int mb)
 {
@@ -344,7 +348,7 @@ int ak_eval_production(const ak_mechanism *m, const float *rates, int64_t ldR, i
         return set_error(AK_EINVAL, "%s: ldR=%lld, ldO=%lld < n_cells=%lld", fn,
                          (long long)ldR, (long long)ldO, (long long)n);
     const ProdShape p = prod_shape(m->ns, m->nr);
-    const int64_t cells_per_block = 64 * ncb_for(p.mb);
+    const int64_t cells_per_block = 16 * ncb_for(p.mb) * (p.mb <= 4 ? 4 : kLdsWaves);
     const int64_t blocks = (n + cells_per_block - 1) / cells_per_block;
     if (blocks > 0x7fffffff) return set_error(AK_E2BIG, "%s: n_cells too large", fn);
     DeviceGuard g(m->device);
@@ -363,7 +367,8 @@ int ak_eval_production(const ak_mechanism *m, const float *rates, int64_t ldR, i
             hipLaunchKernelGGL((production_kernel<MB, ncb_for(MB)>), grid, dim3(256), 0, st,\
                                A, p.kchunks, p.mbp, rates, ldR, m->nr, n, omega, ldO, m->ns);\
         else                                                                                \
-            hipLaunchKernelGGL((production_lds_kernel<MB, ncb_for(MB)>), grid, dim3(256),   \
+            hipLaunchKernelGGL((production_lds_kernel<MB, ncb_for(MB), kLdsWaves>), grid,   \
+                               dim3(64 * kLdsWaves),                                        \
                                lds, st, A, p.kchunks, p.mbp, sc, rates, ldR, m->nr, n,      \
                                omega, ldO, m->ns);                                          \
         break
